@@ -1,0 +1,231 @@
+"""CPU oracle of the wetting pseudopotential lattice Boltzmann step (TEST INFRASTRUCTURE).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may import
+this package. It shares no code with the HIP library in ``paper_1410_2569_amd``.
+
+* ``lbm_oracle.c``: the time step S1-S8 in plain C, FP64, ``-ffp-contract=off``.
+* this module: ctypes binding, the Maxwell construction (scipy), observables (density extremes,
+  spurious-current maximum, Kasa circle fit of the contact angle) and the wetting objective.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+from .maxwell import (cs_pressure, maxwell_cs, cs_temperature_for_ratio, piecewise_spinodals,
+                      piecewise_pressure)  # noqa: F401
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "lbm_oracle.c")
+LIB = os.path.join(HERE, "_build", "liblbm_oracle.so")
+
+EOS = {"cs": 0, "piecewise": 1}
+WALL = {"rho": 0, "psi": 1, "modpsi": 2}
+
+
+class Params(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("walls", C.c_int32), ("ghost", C.c_int32),
+                ("eos", C.c_int32), ("wall_force", C.c_int32),
+                ("a", C.c_double), ("b", C.c_double), ("R", C.c_double), ("T", C.c_double),
+                ("rho1", C.c_double), ("rho2", C.c_double), ("th_v", C.c_double),
+                ("th_m", C.c_double), ("th_l", C.c_double),
+                ("G", C.c_double), ("sigma", C.c_double),
+                ("s_rho", C.c_double), ("s_e", C.c_double), ("s_zeta", C.c_double),
+                ("s_j", C.c_double), ("s_q", C.c_double),
+                ("tau_l", C.c_double), ("tau_v", C.c_double),
+                ("rho_l", C.c_double), ("rho_v", C.c_double)]
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (OpenMP row loops, no FP contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        os.makedirs(os.path.dirname(LIB), exist_ok=True)
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-fopenmp", "-shared", "-fPIC", SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        P = C.POINTER(Params)
+        dp = C.POINTER(C.c_double)
+        _lib.orc_run.argtypes = [P, dp, dp, C.c_int64]
+        _lib.orc_init_rest.argtypes = [P, dp, dp]
+        _lib.orc_fields.argtypes = [P, dp, dp, dp, dp, dp, dp, dp]
+        _lib.orc_p_eos.argtypes = [P, C.c_double]
+        _lib.orc_p_eos.restype = C.c_double
+        _lib.orc_psi.argtypes = [P, C.c_double]
+        _lib.orc_psi.restype = C.c_double
+        _lib.orc_collide_node.argtypes = [P, dp, C.c_double, dp, dp, dp]
+        _lib.orc_tables.argtypes = [dp, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                    C.POINTER(C.c_int), dp]
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def coexistence(p: dict) -> tuple[float, float]:
+    """(rho_v, rho_l) of the Maxwell construction for the EOS in p."""
+    if p.get("eos", "cs") == "cs":
+        rv, rl, _ = maxwell_cs(p["a"], p["b"], p["R"], p["T"])
+        return rv, rl
+    return p["rho_v"], p["rho_l"]
+
+
+def make_params(p: dict) -> Params:
+    """ctypes parameter block from a parameter dict (see synth.base_params)."""
+    q = Params()
+    q.nx, q.ny = int(p["nx"]), int(p["ny"])
+    q.walls, q.ghost = int(p.get("walls", 1)), int(p.get("ghost", 1))
+    q.eos = EOS[p.get("eos", "cs")]
+    q.wall_force = WALL[p.get("wall_force", "psi")]
+    for k in ("a", "b", "R", "T"):
+        setattr(q, k, float(p.get(k, 0.0)))
+    if q.eos == EOS["piecewise"]:
+        q.th_v, q.th_m, q.th_l = p["th_v"], p["th_m"], p["th_l"]
+        if "rho1" in p:
+            q.rho1, q.rho2 = p["rho1"], p["rho2"]
+        else:
+            q.rho1, q.rho2 = piecewise_spinodals(p["rho_v"], p["rho_l"], p["th_v"], p["th_m"],
+                                                 p["th_l"])
+    q.G, q.sigma = float(p.get("G", -1.0)), float(p["sigma"])
+    for k in ("s_rho", "s_e", "s_zeta", "s_j", "s_q", "tau_l", "tau_v"):
+        setattr(q, k, float(p[k]))
+    if "rho_l" in p and "rho_v" in p:
+        q.rho_l, q.rho_v = float(p["rho_l"]), float(p["rho_v"])
+    else:
+        q.rho_v, q.rho_l = coexistence(p)
+    return q
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _rc(rc: int):
+    if rc != 0:
+        raise OracleError({-1: "invalid parameters", -2: "psi radicand negative",
+                           -3: "out of memory"}.get(rc, f"error {rc}"))
+
+
+def init_rest(q: Params, rho0: np.ndarray) -> np.ndarray:
+    """f^0_a = t_a rho0 (rest equilibrium), shape (9, ny, nx)."""
+    rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
+    f = np.zeros((9, q.ny, q.nx))
+    _rc(lib().orc_init_rest(C.byref(q), _ptr(rho0), _ptr(f)))
+    return f
+
+
+def run(q: Params, gw: np.ndarray | None, f: np.ndarray, nsteps: int) -> np.ndarray:
+    """Advance f (9, ny, nx) by nsteps steps, in place; returns f."""
+    g = np.zeros((2, q.nx)) if gw is None else np.ascontiguousarray(gw, dtype=np.float64)
+    _rc(lib().orc_run(C.byref(q), _ptr(g), _ptr(f), int(nsteps)))
+    return f
+
+
+def fields(q: Params, gw: np.ndarray | None, f: np.ndarray) -> dict:
+    """rho, psi (ny, nx); Fm, Fads, v (2, ny, nx) of state f."""
+    g = np.zeros((2, q.nx)) if gw is None else np.ascontiguousarray(gw, dtype=np.float64)
+    rho = np.zeros((q.ny, q.nx)); psi = np.zeros_like(rho)
+    Fm = np.zeros((2, q.ny, q.nx)); Fads = np.zeros_like(Fm); v = np.zeros_like(Fm)
+    _rc(lib().orc_fields(C.byref(q), _ptr(g), _ptr(f), _ptr(rho), _ptr(psi), _ptr(Fm),
+                         _ptr(Fads), _ptr(v)))
+    return dict(rho=rho, psi=psi, Fm=Fm, Fads=Fads, v=v)
+
+
+def fluid_mask(q: Params) -> np.ndarray:
+    m = np.ones((q.ny, q.nx), dtype=bool)
+    if q.walls:
+        m[0, :] = m[-1, :] = False
+    return m
+
+
+def interface_points(q: Params, rho: np.ndarray, rho_mid: float, y_min: float,
+                     x_lo: float = -np.inf, x_hi: float = np.inf) -> np.ndarray:
+    """Crossings of rho = rho_mid on horizontal and vertical fluid-fluid lattice edges.
+
+    An edge (a, b) crosses when exactly one of rho_a >= rho_mid, rho_b >= rho_mid holds; the
+    point is linearly interpolated. Edges across the periodic x seam are not used. Points with
+    y < y_min or x outside [x_lo, x_hi) are dropped."""
+    fl = fluid_mask(q)
+    pts = []
+    ny, nx = rho.shape
+    for y in range(ny):
+        for x in range(nx):
+            if not fl[y, x]:
+                continue
+            for dx, dy in ((1, 0), (0, 1)):
+                xb, yb = x + dx, y + dy
+                if xb >= nx or yb >= ny or not fl[yb, xb]:
+                    continue
+                ra, rb = rho[y, x], rho[yb, xb]
+                if (ra >= rho_mid) != (rb >= rho_mid):
+                    t = (rho_mid - ra) / (rb - ra)
+                    px, py = x + t * dx, y + t * dy
+                    if py >= y_min and x_lo <= px < x_hi:
+                        pts.append((px, py))
+    return np.array(pts, dtype=np.float64).reshape(-1, 2)
+
+
+def kasa_fit(pts: np.ndarray) -> tuple[float, float, float]:
+    """Kasa circle fit: least squares of x^2 + y^2 + D x + E y + F = 0 -> (xc, yc, r)."""
+    A = np.column_stack([pts[:, 0], pts[:, 1], np.ones(len(pts))])
+    rhs = -(pts[:, 0] ** 2 + pts[:, 1] ** 2)
+    (D, E, F), *_ = np.linalg.lstsq(A, rhs, rcond=None)
+    xc, yc = -D / 2.0, -E / 2.0
+    return xc, yc, float(np.sqrt(xc * xc + yc * yc - F))
+
+
+def contact_angle(q: Params, rho: np.ndarray, x_lo=-np.inf, x_hi=np.inf):
+    """Static contact angle of a droplet on the bottom wall (wall plane y_b = 0.5):
+    theta = acos((y_b - yc) / r) from the Kasa fit of the interface points with y >= y_b + 3.
+    Returns (theta_deg, xc, yc, r, n_points); theta is NaN when fewer than 6 points remain or
+    the fitted circle does not cut the wall plane."""
+    rho_mid = 0.5 * (q.rho_l + q.rho_v)
+    yb = 0.5
+    pts = interface_points(q, rho, rho_mid, yb + 3.0, x_lo, x_hi)
+    if len(pts) < 6:
+        return float("nan"), float("nan"), float("nan"), float("nan"), len(pts)
+    xc, yc, r = kasa_fit(pts)
+    c = (yb - yc) / r
+    th = float(np.degrees(np.arccos(c))) if abs(c) <= 1.0 else float("nan")
+    return th, xc, yc, r, len(pts)
+
+
+def observables(q: Params, gw, f) -> dict:
+    """Density extremes, spurious-current maxima, mass and contact angle of state f."""
+    fd = fields(q, gw, f)
+    fl = fluid_mask(q)
+    rho = fd["rho"]
+    u = np.sqrt(fd["v"][0] ** 2 + fd["v"][1] ** 2)
+    rho_mid = 0.5 * (q.rho_l + q.rho_v)
+    liq = fl & (rho >= rho_mid)
+    th, xc, yc, r, n = contact_angle(q, rho)
+    return dict(rho_min=float(rho[fl].min()), rho_max=float(rho[fl].max()),
+                umax=float(u[fl].max()), umax_liquid=float(u[liq].max()) if liq.any() else 0.0,
+                mass=float(rho[fl].sum()), theta=th, xc=xc, yc=yc, r=r, n_fit=n)
+
+
+def loss(q: Params, rho: np.ndarray, w_centroid: float = 1.0, w_wet: float = 1.0) -> float:
+    """Smooth wetting objective: phase fraction phi = (rho - rho_v)/(rho_l - rho_v);
+    centroid height y_c = sum phi (y - y_b) / sum phi over fluid nodes; wetted length
+    l_w = sum_x phi(x, 1). L = w_centroid y_c + w_wet l_w."""
+    fl = fluid_mask(q)
+    phi = (rho - q.rho_v) / (q.rho_l - q.rho_v)
+    y = np.arange(q.ny, dtype=np.float64)[:, None] - 0.5
+    yc = float((phi * y)[fl].sum() / phi[fl].sum())
+    lw = float(phi[1, :].sum())
+    return w_centroid * yc + w_wet * lw

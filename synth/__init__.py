@@ -1,0 +1,276 @@
+"""Seeded synthetic inputs for the wetting lattice Boltzmann workloads.
+
+This module is shared by the CPU oracle tests and by the HIP path. It holds no arithmetic of the
+lattice Boltzmann method itself: it only draws random numbers and lays out initial density fields,
+wall wettability patterns and workload parameter lists.
+
+Random numbers come from SplitMix64 (Vigna, public domain), a counter-based generator:
+
+    z += 0x9E3779B97F4A7C15
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EB
+    return z ^ (z >> 31)                      (all arithmetic modulo 2**64)
+
+A uniform double in [0, 1) is (splitmix64(...) >> 11) * 2**-53.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(z):
+    """SplitMix64 output for each uint64 in ``z`` (array or scalar)."""
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = z + _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def to_unit(u64):
+    """Map uint64 values to doubles in [0, 1) using their top 53 bits."""
+    return (np.asarray(u64, dtype=np.uint64) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+
+
+def node_uniform(seed: int, counters):
+    """Per-node uniforms: u = unit(splitmix64(splitmix64(seed) + counter))."""
+    base = splitmix64(np.uint64(seed & 0xFFFFFFFFFFFFFFFF))
+    with np.errstate(over="ignore"):
+        z = base + np.asarray(counters, dtype=np.uint64)
+    return to_unit(splitmix64(z))
+
+
+class Draws:
+    """Sequential seeded draws: the k-th value is unit(splitmix64(seed + k)), k = 0, 1, 2, ..."""
+
+    def __init__(self, seed: int):
+        self.seed = seed & 0xFFFFFFFFFFFFFFFF
+        self.k = 0
+
+    def u01(self) -> float:
+        with np.errstate(over="ignore"):
+            z = np.uint64(self.seed) + np.uint64(self.k)
+        self.k += 1
+        return float(to_unit(splitmix64(z)))
+
+    def uniform(self, lo: float, hi: float) -> float:
+        return lo + (hi - lo) * self.u01()
+
+    def choice(self, items):
+        i = min(int(self.u01() * len(items)), len(items) - 1)
+        return items[i]
+
+    def permutation(self, n: int):
+        """Fisher-Yates shuffle of range(n) driven by the draws."""
+        idx = list(range(n))
+        for i in range(n - 1, 0, -1):
+            j = min(int(self.u01() * (i + 1)), i)
+            idx[i], idx[j] = idx[j], idx[i]
+        return idx
+
+
+# ----------------------------------------------------------------------------------------------
+# Initial density fields
+# ----------------------------------------------------------------------------------------------
+
+def droplet_rho(nx: int, ny: int, rho_l: float, rho_v: float, centres, radii,
+                width: float = 2.0, jitter: float = 1e-3, seed: int = 1,
+                walls: bool = True) -> np.ndarray:
+    """Density field of one or more circular liquid droplets in vapour, shape (ny, nx).
+
+    Each droplet k has the profile
+        rho_k = (rho_l + rho_v)/2 - (rho_l - rho_v)/2 * tanh(2 (d_k - R_k) / width)
+    with d_k the distance of the node (x, y) from centre k; the field is the maximum over droplets.
+    The field is then multiplied by (1 + jitter*(2u - 1)) with u = node_uniform(seed, y*nx + x).
+    With walls, rows 0 and ny-1 are solid and hold 0.
+    """
+    y, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64),
+                       indexing="ij")
+    rho = np.full((ny, nx), -np.inf)
+    for (x0, y0), r in zip(centres, radii):
+        d = np.sqrt((x - x0) ** 2 + (y - y0) ** 2)
+        rk = 0.5 * (rho_l + rho_v) - 0.5 * (rho_l - rho_v) * np.tanh(2.0 * (d - r) / width)
+        rho = np.maximum(rho, rk)
+    if jitter:
+        cnt = (np.arange(ny, dtype=np.uint64)[:, None] * np.uint64(nx)
+               + np.arange(nx, dtype=np.uint64)[None, :])
+        u = node_uniform(seed, cnt)
+        rho = rho * (1.0 + jitter * (2.0 * u - 1.0))
+    if walls:
+        rho[0, :] = 0.0
+        rho[-1, :] = 0.0
+    return np.ascontiguousarray(rho)
+
+
+def slab_rho(nx: int, ny: int, rho_l: float, rho_v: float, lo: float, hi: float,
+             width: float = 2.0) -> np.ndarray:
+    """Flat liquid slab lo < y < hi (periodic in both directions), tanh edges, shape (ny, nx)."""
+    y = np.arange(ny, dtype=np.float64)
+    prof = rho_v + 0.5 * (rho_l - rho_v) * (np.tanh(2.0 * (y - lo) / width)
+                                            - np.tanh(2.0 * (y - hi) / width))
+    return np.ascontiguousarray(np.repeat(prof[:, None], nx, axis=1))
+
+
+# ----------------------------------------------------------------------------------------------
+# Wall wettability patterns, shape (2, nx): row 0 = bottom wall (y = 0), row 1 = top wall
+# ----------------------------------------------------------------------------------------------
+
+def gw_uniform(nx: int, bottom: float, top: float | None = None) -> np.ndarray:
+    g = np.empty((2, nx))
+    g[0, :] = bottom
+    g[1, :] = bottom if top is None else top
+    return g
+
+
+def gw_smooth(nx: int, mean: float, amp: float, seed: int, modes: int = 4) -> np.ndarray:
+    """Bottom wall: mean + amp * g(x), g a periodic sum of `modes` sinusoids with seeded
+    amplitudes and phases, normalised so max|g| = 1. Top wall: 0."""
+    d = Draws(seed)
+    x = np.arange(nx, dtype=np.float64)
+    g = np.zeros(nx)
+    for k in range(1, modes + 1):
+        a = d.uniform(0.5, 1.0)
+        ph = d.uniform(0.0, 2.0 * np.pi)
+        g += a * np.sin(2.0 * np.pi * k * x / nx + ph)
+    g /= np.max(np.abs(g))
+    out = np.zeros((2, nx))
+    out[0] = mean + amp * g
+    return out
+
+
+def gw_stripes(nx: int, width: int, v0: float, v1: float) -> np.ndarray:
+    """Bottom wall: stripes of `width` nodes alternating v0, v1. Top wall: 0."""
+    x = np.arange(nx)
+    out = np.zeros((2, nx))
+    out[0] = np.where((x // width) % 2 == 0, v0, v1)
+    return out
+
+
+# ----------------------------------------------------------------------------------------------
+# Workload parameter sets
+# ----------------------------------------------------------------------------------------------
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_MODEL_JSON = os.path.join(os.path.dirname(_HERE), "configs", "cs_ratio500.json")
+
+# Relaxation rates of the MRT operator (s_rho, s_e, s_zeta, s_j, s_q) of the paper's Sec. III.
+RATES = dict(s_rho=1.0, s_e=0.8, s_zeta=0.8, s_j=1.0, s_q=1.1)
+# Adhesion-force variants, in the order Eq. (10), Eq. (11), Eq. (14).
+FORMS = ("rho", "psi", "modpsi")
+# Wall-strength ranges for the sweeps, in Carnahan-Starling units (transferred from the
+# intervals of the paper's spurious-current study, Sec. III.C).
+GW_RANGE = {"rho": (-0.14, 0.28), "psi": (-0.06, 0.09), "modpsi": (-0.2, 0.4)}
+
+
+def model_constants() -> dict:
+    """EOS and forcing constants of the density-ratio-500 Carnahan-Starling fluid.
+
+    a, b, R and the target ratio are fixed; T and sigma were computed by the oracle scripts
+    (Maxwell construction and flat-interface calibration) and stored in configs/cs_ratio500.json.
+    """
+    with open(_MODEL_JSON) as fh:
+        return json.load(fh)
+
+
+def base_params(**over) -> dict:
+    c = model_constants()
+    p = dict(nx=120, ny=60, walls=1, ghost=1, eos="cs", a=c["a"], b=c["b"], R=c["R"],
+             T=c["T"], G=-1.0, sigma=c["sigma"], tau_l=1.1, tau_v=1.1, wall_force="psi")
+    p.update(RATES)
+    p.update(over)
+    return p
+
+
+def c1_small() -> dict:
+    """120x60, psi-based wall force G_w = -0.2 on both walls, droplet R = 20 on the bottom wall,
+    10,000 steps."""
+    p = base_params(nx=120, ny=60, wall_force="psi")
+    return dict(params=p, gw=gw_uniform(120, -0.2), centres=[(60.0, 0.5)], radii=[20.0],
+                seed=1, steps=10_000)
+
+
+def c2_sweep(seed: int = 2) -> list[dict]:
+    """1024x512, droplet R = 150, three wall-force forms x 8 G_w values on a uniform grid,
+    run order shuffled by the seed; 50,000 steps per run."""
+    runs = []
+    for form in FORMS:
+        lo, hi = GW_RANGE[form]
+        for g in np.linspace(lo, hi, 8):
+            runs.append((form, float(g)))
+    order = Draws(seed).permutation(len(runs))
+    out = []
+    for i in order:
+        form, g = runs[i]
+        out.append(dict(params=base_params(nx=1024, ny=512, wall_force=form),
+                        gw=gw_uniform(1024, g), centres=[(512.0, 0.5)], radii=[150.0],
+                        seed=seed + 1000 + i, steps=50_000, form=form, G_w=g))
+    return out
+
+
+def c3_ensemble(seed: int = 3, count: int = 96) -> list[dict]:
+    """Uneven ensemble: nx from {128,192,256,384,512}, ny = nx/2, droplet radius U(0.15,0.3)*nx;
+    instance i uses form i mod 3, G_w = linspace(range, 32)[i div 3] and vapour/liquid kinematic
+    viscosity ratio {1, 5, 15}[(i div 3) mod 3] with liquid viscosity 1/30; 20,000 steps."""
+    d = Draws(seed)
+    out = []
+    nu_l = 1.0 / 30.0
+    for i in range(count):
+        nx = d.choice([128, 192, 256, 384, 512])
+        ny = nx // 2
+        r = d.uniform(0.15, 0.3) * nx
+        form = FORMS[i % 3]
+        lo, hi = GW_RANGE[form]
+        g = float(np.linspace(lo, hi, 32)[(i // 3) % 32])
+        ratio = (1.0, 5.0, 15.0)[(i // 3) % 3]
+        tau_l = 3.0 * nu_l + 0.5
+        tau_v = 3.0 * nu_l * ratio + 0.5
+        p = base_params(nx=nx, ny=ny, wall_force=form, tau_l=tau_l, tau_v=tau_v)
+        out.append(dict(params=p, gw=gw_uniform(nx, g), centres=[(nx / 2.0, 0.5)], radii=[r],
+                        seed=seed * 1000 + i, steps=20_000, form=form, G_w=g, visc_ratio=ratio))
+    return out
+
+
+def c4_adjoint(seed: int = 4) -> dict:
+    """256x128, droplet R = 40, modified form, bottom G_w = -0.1 + 0.05 g(x), top 0;
+    4,000 steps, checkpoint every 200."""
+    p = base_params(nx=256, ny=128, wall_force="modpsi")
+    return dict(params=p, gw=gw_smooth(256, -0.1, 0.05, seed), centres=[(128.0, 0.5)],
+                radii=[40.0], seed=seed, steps=4_000, K=200)
+
+
+def c5_droplets(seed: int, nx: int = 2048, count: int = 6, rmin: float = 40.0,
+                rmax: float = 120.0, gap: float = 10.0):
+    """Non-overlapping droplets on the bottom wall: radii U(rmin, rmax), centres placed left to
+    right with seeded spacing and at least `gap` nodes between neighbouring droplets."""
+    d = Draws(seed)
+    radii = [d.uniform(rmin, rmax) for _ in range(count)]
+    need = sum(2 * r for r in radii) + gap * count
+    slack = max(nx - need, 0.0)
+    w = [d.u01() + 1e-3 for _ in range(count)]
+    s = sum(w)
+    centres, x = [], 0.0
+    for r, wk in zip(radii, w):
+        x += gap / 2 + slack * wk / s
+        centres.append((x + r, 0.5))
+        x += 2 * r + gap / 2
+    return centres, radii
+
+
+def c5_batch(seed: int = 5, count: int = 8) -> list[dict]:
+    """8 instances of 2048x1024, 6 droplets each on a striped wall (width 64, G_w -0.1 / +0.2),
+    modified form; 30,000 forward steps, adjoint over the last 2,000."""
+    out = []
+    for i in range(count):
+        c, r = c5_droplets(seed * 100 + i)
+        p = base_params(nx=2048, ny=1024, wall_force="modpsi")
+        out.append(dict(params=p, gw=gw_stripes(2048, 64, -0.1, 0.2), centres=c, radii=r,
+                        seed=seed * 1000 + i, steps=30_000))
+    return out
