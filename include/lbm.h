@@ -1,0 +1,160 @@
+/*
+ * lbm.h -- C ABI of liblbm: one GPU time step of the D2Q9 multi-relaxation-time pseudopotential
+ * (Shan-Chen) lattice Boltzmann model of wetting at large density ratio, with the three
+ * fluid-solid adhesion forces compared by Q. Li, K. H. Luo, Q. J. Kang and Q. Chen, "Contact
+ * angles in the pseudopotential lattice Boltzmann modeling of wetting" (2014).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - All functions are extern "C", return int: LBM_OK (0) or a negative LBM_E_* code. They never
+ *   abort or exit. lbm_strerror() names a code; lbm_last_error() gives the message of the last
+ *   failure on a context.
+ * - Arithmetic is IEEE binary64 throughout.
+ * - Lattice: nx columns (x, periodic) by ny rows (y). With walls = 1, rows y = 0 and y = ny-1
+ *   are solid nodes (flat walls; the wall planes of halfway bounce-back sit at y = 0.5 and
+ *   y = ny - 1.5) and the fluid occupies rows 1 .. ny-2. With walls = 0, y is periodic too.
+ * - Host arrays are row-major with x fastest: a field is [ny][nx]; populations are [9][ny][nx]
+ *   in the velocity order 0 rest; 1..4 = E, N, W, S; 5..8 = NE, NW, SW, SE.
+ * - Wall wettability G_w is given per solid node: gw[2][nx], row 0 for the bottom wall (y = 0),
+ *   row 1 for the top wall (y = ny-1).
+ * - Device memory: the library never allocates device memory. The caller passes one device
+ *   workspace of at least lbm_workspace_size() bytes; it must stay allocated until
+ *   lbm_destroy(). The library keeps f, psi, G_w and reduction partials inside it.
+ * - Streams: a context is bound to the hipStream_t given at creation (NULL = default stream).
+ *   Stepping calls are asynchronous on that stream; calls that return host data synchronise
+ *   it. A context is not thread-safe.
+ * - Parameters are validated before any HIP call, so invalid input is reported without a GPU.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1
+
+enum {
+    LBM_OK = 0,
+    LBM_E_INVAL = -1,     /* invalid argument or parameter */
+    LBM_E_SIZE = -2,      /* workspace or host buffer too small */
+    LBM_E_HIP = -3,       /* a HIP runtime call failed */
+    LBM_E_NONFINITE = -4, /* NaN/Inf or an undefined pseudopotential found in the state */
+    LBM_E_ABI = -5,       /* abi_version mismatch */
+    LBM_E_STATE = -6      /* state blob does not match this context */
+};
+
+/* Adhesion force (pre-sum factor of the fluid-solid interaction):
+ * density-based Eq. (10), pseudopotential-based Eq. (11), modified pseudopotential-based Eq. (14). */
+enum lbm_wall { LBM_WALL_RHO = 0, LBM_WALL_PSI = 1, LBM_WALL_MODPSI = 2 };
+
+/* Equation of state feeding psi = sqrt(2 (p_EOS - rho c_s^2) / (G c^2)) (Sec. II.B):
+ * Carnahan-Starling p = rho R T (1 + eta + eta^2 - eta^3)/(1 - eta)^3 - a rho^2, eta = b rho / 4,
+ * or the piecewise-linear Eq. (15) of Sec. III. */
+enum lbm_eos { LBM_EOS_CS = 0, LBM_EOS_PIECEWISE = 1 };
+
+typedef struct {
+    int32_t abi_version; /* must be LBM_ABI_VERSION */
+    int32_t nx, ny;      /* nx >= 3; ny >= 4 with walls, >= 3 without */
+    int32_t walls;       /* 1: solid rows 0 and ny-1 (halfway bounce-back); 0: periodic in y */
+    int32_t ghost_psi;   /* 1: Eq. (7) also acts across the wall: a solid row carries the psi of
+                            the adjacent fluid row (mirror about the wall plane), so G_w = 0 is
+                            neutral wetting (Sec. III.A); 0: psi = 0 on solid nodes */
+    int32_t eos;         /* enum lbm_eos */
+    int32_t wall_force;  /* enum lbm_wall */
+    int32_t reserved;    /* must be 0 */
+    double a, b, R, T;   /* Carnahan-Starling constants */
+    double rho1, rho2, th_v, th_m, th_l; /* Eq. (15): spinodal densities and slopes */
+    double G;            /* interaction strength of Eq. (7); must be < 0 */
+    double sigma;        /* mechanical-stability parameter of the forcing term Eq. (9) */
+    double s_rho, s_e, s_zeta, s_j, s_q; /* relaxation rates of Eq. (2), each in (0, 2) */
+    double tau_l, tau_v; /* tau_nu in liquid and vapour, each > 1/2; kinematic viscosity
+                            nu = (tau_nu - 1/2)/3 is interpolated linearly in the phase fraction
+                            (rho - rho_v)/(rho_l - rho_v), clamped to [0, 1] */
+    double rho_l, rho_v; /* coexistence densities (rho_l > rho_v > 0): viscosity interpolation,
+                            contact-angle contour rho_mid = (rho_l + rho_v)/2 */
+} lbm_params;
+
+typedef struct {
+    int64_t step;        /* time step n of the observed state f^n */
+    double rho_min, rho_max; /* over fluid nodes (Table I of the paper) */
+    double umax;         /* max |v| over fluid nodes, v of Eq. (6) (spurious currents, Fig. 9) */
+    double umax_liquid;  /* max |v| over nodes with rho >= rho_mid */
+    double mass;         /* sum of rho over fluid nodes */
+    double theta_deg;    /* static contact angle on the bottom wall, NaN if undefined */
+    double xc, yc, r;    /* fitted circle */
+    int32_t n_fit;       /* interface points used by the fit */
+    int32_t nonfinite;   /* number of fluid nodes with a non-finite rho, psi or v */
+} lbm_obs;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* ---- Thermodynamics (host only, no GPU) --------------------------------------------------- */
+
+/* Maxwell construction (equal-area rule in 1/rho together with p(rho_v) = p(rho_l) = p0) for the
+ * Carnahan-Starling EOS at temperature T. LBM_E_INVAL if T is not below the critical point. */
+int lbm_maxwell_cs(double a, double b, double R, double T, double *rho_v, double *rho_l,
+                   double *p0);
+/* Temperature at which the Carnahan-Starling Maxwell densities have ratio rho_l/rho_v = ratio. */
+int lbm_cs_temperature(double a, double b, double R, double ratio, double *T);
+
+/* ---- Single instance ---------------------------------------------------------------------- */
+
+/* Bytes of device workspace a context with these parameters needs. */
+int lbm_workspace_size(const lbm_params *p, size_t *bytes);
+
+/* Create a context in the caller's workspace d_ws (device pointer, >= lbm_workspace_size()).
+ * gw_host: [2][nx] host array of G_w per solid node (may be NULL with walls = 0; copied).
+ * rho0_host: [ny][nx] host array of the initial density (solid rows ignored; copied). The
+ * initial populations are the rest equilibrium f_a = t_a rho0 with t = 4/9, 1/9, 1/36.
+ * stream: hipStream_t (NULL = default). On success *out owns host memory only. */
+int lbm_create(const lbm_params *p, const double *gw_host, const double *rho0_host, void *d_ws,
+               size_t ws_bytes, void *stream, lbm_ctx **out);
+
+/* Advance n >= 0 time steps (Eqs. 1-9 with the adhesion force and halfway bounce-back).
+ * Asynchronous on the context stream. */
+int lbm_step(lbm_ctx *c, int64_t n);
+
+/* Observables of the current state f^n (Sec. III.B, III.C and the contact angle of Figs. 1-4):
+ * density extremes, spurious-current maxima, mass, and the contact angle from a Kasa circle fit
+ * of the rho_mid contour (crossings on lattice edges with y >= 3.5, the bottom wall plane plus
+ * about one interface width). Synchronises the stream. Returns LBM_E_NONFINITE (after filling
+ * *out) if any fluid node is not finite. */
+int lbm_observables(lbm_ctx *c, lbm_obs *out);
+
+/* Same, with the fit restricted to interface points with x_lo <= x < x_hi (one droplet of
+ * several). */
+int lbm_observables_window(lbm_ctx *c, double x_lo, double x_hi, lbm_obs *out);
+
+/* Copy rho^n ([ny][nx], count >= nx*ny) or the pre-collision populations f^n ([9][ny][nx]) to
+ * host memory. Synchronises the stream. Solid rows read 0. */
+int lbm_read_rho(lbm_ctx *c, double *host, size_t count);
+int lbm_read_f(lbm_ctx *c, double *host, size_t count);
+
+/* Checkpoint: the full state (step counter and populations) as an opaque host blob of
+ * lbm_state_size() bytes. Loading checks the blob's size and geometry (LBM_E_STATE). */
+int lbm_state_size(const lbm_ctx *c, size_t *bytes);
+int lbm_save_state(lbm_ctx *c, void *host, size_t bytes);
+int lbm_load_state(lbm_ctx *c, const void *host, size_t bytes);
+
+/* Replace the wall wettability pattern ([2][nx] host array, copied). */
+int lbm_set_gw(lbm_ctx *c, const double *gw_host);
+
+/* Kernel schedule of lbm_step: 0 = fused single pass (psi of the tile halo recomputed from the
+ * populations, 144 algorithmic bytes per lattice update), 1 = two passes (psi pass, then the
+ * fused force-collide-stream pass reading psi through an LDS tile). Results are identical up to
+ * floating-point contraction. */
+int lbm_set_schedule(lbm_ctx *c, int32_t schedule);
+
+int64_t lbm_current_step(const lbm_ctx *c);
+int lbm_destroy(lbm_ctx *c);
+const char *lbm_strerror(int code);
+const char *lbm_last_error(const lbm_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -1,0 +1,333 @@
+// lbm_kernels.hip -- gfx950 kernels of the wetting pseudopotential LB step and its observables.
+//
+// Step schedules (both call the same per-node arithmetic of lbm_device.h):
+//   fused     one kernel per time step. A workgroup owns a TX x TY tile; every thread pulls the
+//             9 populations of its node (Eq. 5 with bounce-back), forms rho and psi, and the
+//             psi of the one-node tile halo is recomputed from the (L2-resident) populations of
+//             the neighbouring tiles. psi lives only in LDS, so HBM sees 72 B read + 72 B
+//             written per lattice update.
+//   two-pass  psi pass (pull, rho, psi -> psi array with mirrored ghost rows), then the step
+//             kernel stages the psi tile plus halo in LDS: 72 + 8 B and 72 + 8 + 72 B per update.
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+namespace lbm {
+
+// ------------------------------------------------------------------------------------------------
+// Time step
+// ------------------------------------------------------------------------------------------------
+template <int TX, int TY, bool FUSED>
+__global__ __launch_bounds__(TX* TY) void k_step(KParams P, const double* __restrict__ gin,
+                                                 double* __restrict__ gout,
+                                                 const double* __restrict__ psi_g,
+                                                 const double* __restrict__ gw) {
+    constexpr int NT = TX * TY;
+    constexpr int LW = TX + 2;
+    constexpr int NH = 2 * LW + 2 * TY;  // halo slots of a (TX+2) x (TY+2) tile
+    __shared__ double sp[(TY + 2) * LW];
+
+    const int ntx = (P.nx + TX - 1) / TX;
+    const int nty = (P.y_hi - P.y_lo + TY) / TY;
+    const int tile = xcd_tile(blockIdx.x, ntx * nty);
+    const int x0 = (tile % ntx) * TX;
+    const int y0 = P.y_lo + (tile / ntx) * TY;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool active = x < P.nx && y <= P.y_hi;
+
+    double f[9];
+    double rho = 1.0, psi_c = 0.0;
+    if (active) {
+        pull9(P, gin, x, y, f);
+        rho = sum9(f);
+        if (FUSED) psi_c = psi_of_rho(P, rho);
+    }
+    if (FUSED) {
+        // own slot: computed above, or (outside the fluid) the value at that lattice position
+        sp[(ty + 1) * LW + tx + 1] = active ? psi_c : psi_at(P, gin, x, y);
+        for (int h = threadIdx.x; h < NH; h += NT) {
+            int hx, hy;  // tile-local coordinates in [-1, TX] x [-1, TY]
+            if (h < LW) { hx = h - 1; hy = -1; }
+            else if (h < 2 * LW) { hx = h - LW - 1; hy = TY; }
+            else if (h < 2 * LW + TY) { hx = -1; hy = h - 2 * LW; }
+            else { hx = TX; hy = h - 2 * LW - TY; }
+            sp[(hy + 1) * LW + hx + 1] = psi_at(P, gin, x0 + hx, y0 + hy);
+        }
+    } else {
+        // stage psi (ghost rows already mirrored by the psi pass) with its halo
+        for (int s = threadIdx.x; s < (TY + 2) * LW; s += NT) {
+            const int gy0 = y0 - 1 + s / LW;
+            const int gx = wrapx(x0 - 1 + s % LW, P.nx);
+            int gy = gy0;
+            double v = 0.0;
+            if (P.walls) {
+                if (gy >= 0 && gy < P.ny) v = psi_g[(long long)gy * P.pitch + gx];
+            } else {
+                gy = wrapx(gy, P.ny);
+                v = psi_g[(long long)gy * P.pitch + gx];
+            }
+            sp[s] = v;
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    if (!FUSED) psi_c = sp[(ty + 1) * LW + tx + 1];
+
+    const double* c = sp + (ty + 1) * LW + tx + 1;
+    double sx, sy;
+    cohesion_sum(c[-LW - 1], c[-LW], c[-LW + 1], c[-1], c[1], c[LW - 1], c[LW], c[LW + 1], sx,
+                 sy);
+    double Ax = 0.0, Ay = 0.0;
+    if (P.walls && (y == 1 || y == P.ny - 2)) adhesion_sum(P, gw, x, y, Ax, Ay);
+    collide(P, f, rho, psi_c, sx, sy, Ax, Ay);
+
+    double* o = gout + (long long)y * P.pitch + x;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) o[a * P.plane] = f[a];
+}
+
+// psi pass of the two-pass schedule; also writes the mirrored ghost rows.
+__global__ __launch_bounds__(256) void k_psi(KParams P, const double* __restrict__ gin,
+                                             double* __restrict__ psi_g,
+                                             double* __restrict__ rho_out) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = P.y_lo + blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= P.nx || y > P.y_hi) return;
+    double f[9];
+    pull9(P, gin, x, y, f);
+    const double rho = sum9(f);
+    const double ps = psi_of_rho(P, rho);
+    psi_g[(long long)y * P.pitch + x] = ps;
+    if (rho_out) rho_out[(long long)y * P.pitch + x] = rho;
+    if (P.walls && P.ghost) {
+        if (y == 1) psi_g[x] = ps;
+        if (y == P.ny - 2) psi_g[(long long)(P.ny - 1) * P.pitch + x] = ps;
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// State set-up and read-out
+// ------------------------------------------------------------------------------------------------
+
+// Inverse of streaming + bounce-back: writes g so that the first pull yields f_a = t_a rho0.
+// Every post-collision slot of a fluid node is the source of exactly one pulled population.
+__global__ __launch_bounds__(256) void k_init(KParams P, const double* __restrict__ rho0,
+                                              double* __restrict__ g) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = P.y_lo + blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= P.nx || y > P.y_hi) return;
+    const double r = rho0[(long long)y * P.pitch + x];
+    const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    const int op[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    for (int a = 0; a < 9; ++a) {
+        const double t = a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+        int sx = wrapx(x - ex[a], P.nx);
+        int sy = y - ey[a];
+        bool solid = false;
+        if (P.walls) solid = (sy == 0 || sy == P.ny - 1);
+        else sy = wrapx(sy, P.ny);
+        if (solid) g[op[a] * P.plane + (long long)y * P.pitch + x] = t * r;
+        else g[a * P.plane + (long long)sy * P.pitch + sx] = t * r;
+    }
+}
+
+// Pre-collision populations f^n (pulled) into a [9][ny][pitch] buffer.
+__global__ __launch_bounds__(256) void k_pull(KParams P, const double* __restrict__ gin,
+                                              double* __restrict__ fout) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = P.y_lo + blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= P.nx || y > P.y_hi) return;
+    double f[9];
+    pull9(P, gin, x, y, f);
+    for (int a = 0; a < 9; ++a) fout[a * P.plane + (long long)y * P.pitch + x] = f[a];
+}
+
+// ------------------------------------------------------------------------------------------------
+// Observables: per-block partials (wave-level shuffles, then LDS across waves), fixed-order final
+// reduction. No floating-point atomics, so results are bitwise reproducible.
+// ------------------------------------------------------------------------------------------------
+enum { O_MIN = 0, O_MAX, O_U, O_UL, O_MASS, O_BAD, O_N, O_SX, O_SY, O_SXX, O_SYY, O_SXY, O_SXR,
+       O_SYR, O_SR, O_NQ };
+
+__device__ __forceinline__ double op_combine(int q, double a, double b) {
+    if (q == O_MIN) return fmin(a, b);
+    if (q == O_MAX || q == O_U || q == O_UL) return fmax(a, b);
+    return a + b;
+}
+
+__device__ __forceinline__ double op_identity(int q) {
+    if (q == O_MIN) return __builtin_huge_val();
+    if (q == O_MAX || q == O_U || q == O_UL) return -__builtin_huge_val();
+    return 0.0;
+}
+
+__device__ __forceinline__ void add_point(double v[O_NQ], double px, double py, double cx,
+                                          double cy) {
+    const double X = px - cx, Y = py - cy, r2 = X * X + Y * Y;
+    v[O_N] += 1.0; v[O_SX] += X; v[O_SY] += Y; v[O_SXX] += X * X; v[O_SYY] += Y * Y;
+    v[O_SXY] += X * Y; v[O_SXR] += X * r2; v[O_SYR] += Y * r2; v[O_SR] += r2;
+}
+
+// Block of 256 threads over a 64 x 4 patch. rho_f: rho of every fluid node (from k_psi);
+// psi_g: psi with ghost rows. Writes O_NQ partials per block.
+__global__ __launch_bounds__(256) void k_obs(KParams P, const double* __restrict__ gin,
+                                             const double* __restrict__ rho_f,
+                                             const double* __restrict__ psi_g,
+                                             const double* __restrict__ gw, ObsArgs A,
+                                             double* __restrict__ part) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = P.y_lo + blockIdx.y * 4 + (threadIdx.x >> 6);
+    double v[O_NQ];
+    for (int q = 0; q < O_NQ; ++q) v[q] = op_identity(q);
+    if (x < P.nx && y <= P.y_hi) {
+        const long long i = (long long)y * P.pitch + x;
+        double f[9];
+        pull9(P, gin, x, y, f);
+        const double rho = rho_f[i], pc = psi_g[i];
+        const int xm = x == 0 ? P.nx - 1 : x - 1, xp = x == P.nx - 1 ? 0 : x + 1;
+        int ym = y - 1, yp = y + 1;
+        if (!P.walls) { ym = wrapx(ym, P.ny); yp = wrapx(yp, P.ny); }
+        const double* rm = psi_g + (long long)ym * P.pitch;
+        const double* r0 = psi_g + (long long)y * P.pitch;
+        const double* rp = psi_g + (long long)yp * P.pitch;
+        double sx, sy, Ax = 0.0, Ay = 0.0, vx, vy;
+        cohesion_sum(rm[xm], rm[x], rm[xp], r0[xm], r0[xp], rp[xm], rp[x], rp[xp], sx, sy);
+        adhesion_sum(P, gw, x, y, Ax, Ay);
+        velocity(P, f, rho, pc, sx, sy, Ax, Ay, vx, vy);
+        const double u = sqrt(vx * vx + vy * vy);
+        const bool ok = isfinite(rho) && isfinite(pc) && isfinite(u);
+        v[O_BAD] = ok ? 0.0 : 1.0;
+        if (ok) {
+            v[O_MIN] = rho; v[O_MAX] = rho; v[O_U] = u; v[O_MASS] = rho;
+            if (rho >= A.rho_mid) v[O_UL] = u;
+        }
+        // interface crossings on the edges to the right and upper neighbours
+        const bool la = rho >= A.rho_mid;
+        if (x + 1 < P.nx) {
+            const double rb = rho_f[i + 1];
+            if ((rb >= A.rho_mid) != la) {
+                const double t = (A.rho_mid - rho) / (rb - rho);
+                const double px = x + t, py = (double)y;
+                if (py >= A.y_min && px >= A.x_lo && px < A.x_hi) add_point(v, px, py, A.cx, A.cy);
+            }
+        }
+        if (y + 1 <= P.y_hi) {
+            const double rb = rho_f[i + P.pitch];
+            if ((rb >= A.rho_mid) != la) {
+                const double t = (A.rho_mid - rho) / (rb - rho);
+                const double px = (double)x, py = y + t;
+                if (py >= A.y_min && px >= A.x_lo && px < A.x_hi) add_point(v, px, py, A.cx, A.cy);
+            }
+        }
+    }
+    // wave-level tree (xor shuffles), then across the 4 waves of the block
+    __shared__ double red[4][O_NQ];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int q = 0; q < O_NQ; ++q) {
+        double s = v[q];
+        for (int off = 32; off > 0; off >>= 1) s = op_combine(q, s, __shfl_xor(s, off, 64));
+        if (lane == 0) red[wv][q] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < O_NQ) {
+        const int q = threadIdx.x;
+        double s = op_combine(q, op_combine(q, red[0][q], red[1][q]),
+                              op_combine(q, red[2][q], red[3][q]));
+        part[(long long)(blockIdx.y * gridDim.x + blockIdx.x) * O_NQ + q] = s;
+    }
+}
+
+// One block of 256 threads: thread t combines partials t, t+256, ... in order, then a fixed tree.
+__global__ __launch_bounds__(256) void k_obs_final(const double* __restrict__ part, int nblk,
+                                                   double* __restrict__ out) {
+    __shared__ double sh[256];
+    for (int q = 0; q < O_NQ; ++q) {
+        double s = op_identity(q);
+        for (int b = threadIdx.x; b < nblk; b += 256) s = op_combine(q, s, part[(long long)b * O_NQ + q]);
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) sh[threadIdx.x] = op_combine(q, sh[threadIdx.x], sh[threadIdx.x + w]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[q] = sh[0];
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Host-side launchers
+// ------------------------------------------------------------------------------------------------
+static dim3 node_grid(const KParams& P) {
+    return dim3((P.nx + 63) / 64, (P.y_hi - P.y_lo + 4) / 4);
+}
+
+template <int TX, int TY, bool FUSED>
+static hipError_t launch_step_t(const KParams& P, const double* gin, double* gout,
+                                const double* psi, const double* gw, hipStream_t s) {
+    const int ntx = (P.nx + TX - 1) / TX;
+    const int nty = (P.y_hi - P.y_lo + TY) / TY;
+    hipLaunchKernelGGL((k_step<TX, TY, FUSED>), dim3(ntx * nty), dim3(TX * TY), 0, s, P, gin,
+                       gout, psi, gw);
+    return hipGetLastError();
+}
+
+int n_tiles() { return 4; }
+
+void tile_shape(int tile, int* tx, int* ty) {
+    static const int T[4][2] = {{64, 4}, {64, 8}, {64, 16}, {128, 4}};
+    if (tile < 0 || tile >= 4) tile = 0;
+    *tx = T[tile][0];
+    *ty = T[tile][1];
+}
+
+hipError_t launch_step(const KParams& P, int schedule, int tile, const double* gin, double* gout,
+                       double* psi, const double* gw, hipStream_t s) {
+    if (schedule == 1) {
+        hipLaunchKernelGGL(k_psi, node_grid(P), dim3(256), 0, s, P, gin, psi, (double*)nullptr);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_step_t<64, 4, false>(P, gin, gout, psi, gw, s);
+    }
+    switch (tile) {
+        case 1: return launch_step_t<64, 8, true>(P, gin, gout, psi, gw, s);
+        case 2: return launch_step_t<64, 16, true>(P, gin, gout, psi, gw, s);
+        case 3: return launch_step_t<128, 4, true>(P, gin, gout, psi, gw, s);
+        default: return launch_step_t<64, 4, true>(P, gin, gout, psi, gw, s);
+    }
+}
+
+hipError_t launch_init(const KParams& P, const double* rho0, double* g, hipStream_t s) {
+    hipLaunchKernelGGL(k_init, node_grid(P), dim3(256), 0, s, P, rho0, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_pull(const KParams& P, const double* gin, double* fout, hipStream_t s) {
+    hipLaunchKernelGGL(k_pull, node_grid(P), dim3(256), 0, s, P, gin, fout);
+    return hipGetLastError();
+}
+
+hipError_t launch_rho_psi(const KParams& P, const double* gin, double* psi, double* rho,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_psi, node_grid(P), dim3(256), 0, s, P, gin, psi, rho);
+    return hipGetLastError();
+}
+
+int obs_blocks(const KParams& P) {
+    dim3 g = node_grid(P);
+    return (int)(g.x * g.y);
+}
+
+hipError_t launch_obs(const KParams& P, const double* gin, const double* rho, const double* psi,
+                      const double* gw, const ObsArgs& A, double* part, double* out,
+                      hipStream_t s) {
+    dim3 g = node_grid(P);
+    hipLaunchKernelGGL(k_obs, g, dim3(256), 0, s, P, gin, rho, psi, gw, A, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, s, part, (int)(g.x * g.y), out);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,229 @@
+"""Python binding of liblbm (argument marshalling only: every step of the path runs in the HIP
+kernels of the library; torch supplies device memory and the stream).
+
+The library must be built (``python -m paper_1410_2569_amd.build``); importing fails loudly when
+it is missing, and there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+ABI_VERSION = 1
+OK, E_INVAL, E_SIZE, E_HIP, E_NONFINITE, E_ABI, E_STATE = 0, -1, -2, -3, -4, -5, -6
+WALL = {"rho": 0, "psi": 1, "modpsi": 2}
+EOS = {"cs": 0, "piecewise": 1}
+SCHEDULE = {"fused": 0, "two_pass": 1}
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code: int, msg: str = ""):
+        self.code = code
+        super().__init__(f"liblbm error {code}: {msg}")
+
+
+class Params(C.Structure):
+    _fields_ = [("abi_version", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("walls", C.c_int32), ("ghost_psi", C.c_int32), ("eos", C.c_int32),
+                ("wall_force", C.c_int32), ("reserved", C.c_int32),
+                ("a", C.c_double), ("b", C.c_double), ("R", C.c_double), ("T", C.c_double),
+                ("rho1", C.c_double), ("rho2", C.c_double), ("th_v", C.c_double),
+                ("th_m", C.c_double), ("th_l", C.c_double),
+                ("G", C.c_double), ("sigma", C.c_double),
+                ("s_rho", C.c_double), ("s_e", C.c_double), ("s_zeta", C.c_double),
+                ("s_j", C.c_double), ("s_q", C.c_double),
+                ("tau_l", C.c_double), ("tau_v", C.c_double),
+                ("rho_l", C.c_double), ("rho_v", C.c_double)]
+
+
+class Obs(C.Structure):
+    _fields_ = [("step", C.c_int64), ("rho_min", C.c_double), ("rho_max", C.c_double),
+                ("umax", C.c_double), ("umax_liquid", C.c_double), ("mass", C.c_double),
+                ("theta_deg", C.c_double), ("xc", C.c_double), ("yc", C.c_double),
+                ("r", C.c_double), ("n_fit", C.c_int32), ("nonfinite", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# name -> (restype, argtypes); the exported C ABI of include/lbm.h
+_dp = C.POINTER(C.c_double)
+_P = C.POINTER(Params)
+SIGNATURES = {
+    "lbm_maxwell_cs": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double, _dp, _dp, _dp]),
+    "lbm_cs_temperature": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double, _dp]),
+    "lbm_workspace_size": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+    "lbm_create": (C.c_int, [_P, _dp, _dp, C.c_void_p, C.c_size_t, C.c_void_p,
+                             C.POINTER(C.c_void_p)]),
+    "lbm_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "lbm_observables": (C.c_int, [C.c_void_p, C.POINTER(Obs)]),
+    "lbm_observables_window": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.POINTER(Obs)]),
+    "lbm_read_rho": (C.c_int, [C.c_void_p, _dp, C.c_size_t]),
+    "lbm_read_f": (C.c_int, [C.c_void_p, _dp, C.c_size_t]),
+    "lbm_state_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "lbm_save_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "lbm_load_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "lbm_set_gw": (C.c_int, [C.c_void_p, _dp]),
+    "lbm_set_schedule": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lbm_current_step": (C.c_int64, [C.c_void_p]),
+    "lbm_destroy": (C.c_int, [C.c_void_p]),
+    "lbm_strerror": (C.c_char_p, [C.c_int]),
+    "lbm_last_error": (C.c_char_p, [C.c_void_p]),
+}
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load liblbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1410_2569_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _dptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def check(rc: int, ctx=None):
+    if rc != OK:
+        msg = lib().lbm_strerror(rc).decode()
+        if ctx:
+            extra = lib().lbm_last_error(ctx)
+            if extra:
+                msg += ": " + extra.decode()
+        raise LBMError(rc, msg)
+
+
+def maxwell_cs(a: float, b: float, R: float, T: float):
+    """(rho_v, rho_l, p0) of the Carnahan-Starling Maxwell construction (library's solver)."""
+    rv, rl, p0 = C.c_double(), C.c_double(), C.c_double()
+    check(lib().lbm_maxwell_cs(a, b, R, T, C.byref(rv), C.byref(rl), C.byref(p0)))
+    return rv.value, rl.value, p0.value
+
+
+def cs_temperature(a: float, b: float, R: float, ratio: float) -> float:
+    T = C.c_double()
+    check(lib().lbm_cs_temperature(a, b, R, ratio, C.byref(T)))
+    return T.value
+
+
+def make_params(p: dict) -> Params:
+    """C parameter block from a parameter dict (keys as in synth.base_params). rho_l/rho_v
+    default to the library's own Maxwell construction for the Carnahan-Starling EOS."""
+    q = Params()
+    q.abi_version = ABI_VERSION
+    q.nx, q.ny = int(p["nx"]), int(p["ny"])
+    q.walls = int(p.get("walls", 1))
+    q.ghost_psi = int(p.get("ghost", 1))
+    q.eos = EOS[p.get("eos", "cs")]
+    q.wall_force = WALL[p.get("wall_force", "psi")]
+    for k in ("a", "b", "R", "T", "rho1", "rho2", "th_v", "th_m", "th_l"):
+        setattr(q, k, float(p.get(k, 0.0)))
+    q.G = float(p.get("G", -1.0))
+    q.sigma = float(p["sigma"])
+    for k in ("s_rho", "s_e", "s_zeta", "s_j", "s_q", "tau_l", "tau_v"):
+        setattr(q, k, float(p[k]))
+    if "rho_l" in p and "rho_v" in p:
+        q.rho_l, q.rho_v = float(p["rho_l"]), float(p["rho_v"])
+    elif q.eos == EOS["cs"]:
+        q.rho_v, q.rho_l, _ = maxwell_cs(q.a, q.b, q.R, q.T)
+    else:
+        raise ValueError("piecewise EOS needs rho_l and rho_v")
+    return q
+
+
+def workspace_size(q: Params) -> int:
+    n = C.c_size_t()
+    check(lib().lbm_workspace_size(C.byref(q), C.byref(n)))
+    return n.value
+
+
+class Sim:
+    """One lattice on the current HIP device, in a torch-allocated workspace."""
+
+    def __init__(self, params, gw, rho0, device="cuda", stream=None):
+        import torch
+
+        self.q = params if isinstance(params, Params) else make_params(params)
+        self.nx, self.ny = self.q.nx, self.q.ny
+        nbytes = workspace_size(self.q)
+        # 256-byte aligned: torch's caching allocator hands out 512-byte aligned blocks
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
+        g = np.ascontiguousarray(gw if gw is not None else np.zeros((2, self.nx)),
+                                 dtype=np.float64)
+        r = np.ascontiguousarray(rho0, dtype=np.float64)
+        assert g.shape == (2, self.nx) and r.shape == (self.ny, self.nx)
+        h = C.c_void_p()
+        check(lib().lbm_create(C.byref(self.q), _dptr(g), _dptr(r), C.c_void_p(self.ws.data_ptr()),
+                               nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().lbm_destroy(h)
+            self.h = None
+
+    def _chk(self, rc):
+        check(rc, self.h)
+
+    def set_schedule(self, schedule):
+        s = SCHEDULE[schedule] if isinstance(schedule, str) else int(schedule)
+        self._chk(lib().lbm_set_schedule(self.h, s))
+
+    def step(self, n: int = 1):
+        self._chk(lib().lbm_step(self.h, int(n)))
+
+    @property
+    def current_step(self) -> int:
+        return lib().lbm_current_step(self.h)
+
+    def observables(self, x_lo=-math.inf, x_hi=math.inf, allow_nonfinite=False) -> dict:
+        o = Obs()
+        rc = lib().lbm_observables_window(self.h, x_lo, x_hi, C.byref(o))
+        if rc == E_NONFINITE and allow_nonfinite:
+            return o.as_dict()
+        self._chk(rc)
+        return o.as_dict()
+
+    def rho(self) -> np.ndarray:
+        out = np.empty((self.ny, self.nx))
+        self._chk(lib().lbm_read_rho(self.h, _dptr(out), out.size))
+        return out
+
+    def f(self) -> np.ndarray:
+        out = np.empty((9, self.ny, self.nx))
+        self._chk(lib().lbm_read_f(self.h, _dptr(out), out.size))
+        return out
+
+    def save_state(self) -> bytes:
+        n = C.c_size_t()
+        self._chk(lib().lbm_state_size(self.h, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._chk(lib().lbm_save_state(self.h, buf, n.value))
+        return buf.raw
+
+    def load_state(self, blob: bytes):
+        self._chk(lib().lbm_load_state(self.h, C.c_char_p(blob), len(blob)))
+
+    def set_gw(self, gw):
+        g = np.ascontiguousarray(gw, dtype=np.float64)
+        assert g.shape == (2, self.nx)
+        self._chk(lib().lbm_set_gw(self.h, _dptr(g)))

@@ -1,0 +1,233 @@
+"""GPU (HIP, gfx950) step vs the FP64 CPU oracle, element by element on the same seeded inputs.
+
+Tolerances: rho and every population to 1e-9 relative to the local density; contact angle to 0.1
+degree; spurious-current maxima to 1e-12 absolute + 1e-6 relative. The GPU may contract a*b+c into
+fused multiply-adds and sums in another order than the oracle, so agreement is to round-off, not
+bitwise; the schedules and tile shapes of the GPU must agree with each other bitwise.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-9
+
+
+def setup_case(orc, p, gw, centres, radii, seed, jitter=1e-3, walls=True):
+    q = orc.make_params(p)
+    rho0 = synth.droplet_rho(q.nx, q.ny, q.rho_l, q.rho_v, centres, radii, seed=seed,
+                             jitter=jitter, walls=walls)
+    # both sides get identical parameters, including the coexistence densities
+    pg = dict(p, rho_l=q.rho_l, rho_v=q.rho_v)
+    if p.get("eos") == "piecewise":
+        pg.update(rho1=q.rho1, rho2=q.rho2)
+    return q, pg, rho0
+
+
+def fluid(q):
+    m = np.ones((q.ny, q.nx), bool)
+    if q.walls:
+        m[0] = m[-1] = False
+    return m
+
+
+def assert_f_close(q, f_gpu, f_orc, tol=RTOL, what=""):
+    fl = fluid(q)
+    rho = f_orc.sum(0)
+    err = np.abs(f_gpu - f_orc).max(0)[fl] / rho[fl]
+    rel = float(err.max())
+    print(f"{what} max |df|/rho = {rel:.3e}", flush=True)
+    assert rel <= tol, f"{what}: populations differ by {rel:.3e} relative (tol {tol})"
+
+
+def assert_obs_close(o_gpu, o_orc, theta_tol=0.1):
+    for k in ("rho_min", "rho_max", "mass"):
+        assert abs(o_gpu[k] - o_orc[k]) <= RTOL * abs(o_orc[k]), (k, o_gpu[k], o_orc[k])
+    for k in ("umax", "umax_liquid"):
+        assert abs(o_gpu[k] - o_orc[k]) <= 1e-12 + 1e-6 * abs(o_orc[k]), (k, o_gpu[k], o_orc[k])
+    assert o_gpu["n_fit"] == o_orc["n_fit"]
+    if math.isnan(o_orc["theta"]):
+        assert math.isnan(o_gpu["theta_deg"])
+    else:
+        assert abs(o_gpu["theta_deg"] - o_orc["theta"]) <= theta_tol, (o_gpu["theta_deg"],
+                                                                      o_orc["theta"])
+
+
+def test_init_matches_oracle(orc, gpu):
+    p = synth.base_params(nx=70, ny=37, wall_force="modpsi")
+    q, pg, rho0 = setup_case(orc, p, None, [(35.0, 0.5)], [12.0], seed=11)
+    sim = gpu.Sim(pg, synth.gw_uniform(70, 0.1), rho0)
+    f0 = orc.init_rest(q, rho0)
+    assert np.array_equal(sim.f(), f0), "initial populations must be exactly t_a rho0"
+    fl = fluid(q)
+    assert np.abs(sim.rho() - f0.sum(0))[fl].max() <= 1e-15 * rho0[fl].max()
+
+
+@pytest.mark.parametrize("form", ["rho", "psi", "modpsi"])
+@pytest.mark.parametrize("schedule", ["fused", "two_pass"])
+def test_step_parity_walls(orc, gpu, form, schedule):
+    """Ragged lattice (several tiles plus a partial one in x and y), patterned G_w on both walls."""
+    nx, ny, steps = 150, 41, 300
+    gwv = {"rho": 0.1, "psi": -0.03, "modpsi": 0.2}[form]
+    p = synth.base_params(nx=nx, ny=ny, wall_force=form)
+    q, pg, rho0 = setup_case(orc, p, None, [(75.0, 0.5)], [14.0], seed=21)
+    gw = synth.gw_smooth(nx, gwv, 0.3 * abs(gwv), seed=5)
+    gw[1] = gw[0][::-1]
+    sim = gpu.Sim(pg, gw, rho0)
+    sim.set_schedule(schedule)
+    sim.step(steps)
+    f = orc.run(q, gw, orc.init_rest(q, rho0), steps)
+    assert_f_close(q, sim.f(), f, what=f"{form}/{schedule}")
+    assert_obs_close(sim.observables(), orc.observables(q, gw, f))
+
+
+def test_step_parity_periodic(orc, gpu):
+    """Fully periodic lattice (no walls): a free droplet."""
+    nx, ny, steps = 66, 45, 400
+    p = synth.base_params(nx=nx, ny=ny, walls=0)
+    q, pg, rho0 = setup_case(orc, p, None, [(30.0, 20.0)], [10.0], seed=3, walls=False)
+    sim = gpu.Sim(pg, None, rho0)
+    sim.step(steps)
+    f = orc.run(q, None, orc.init_rest(q, rho0), steps)
+    assert_f_close(q, sim.f(), f, what="periodic")
+
+
+def test_step_parity_viscosity_ratio(orc, gpu):
+    """Phase-dependent tau_nu (vapour/liquid kinematic viscosity ratio 15)."""
+    nx, ny, steps = 96, 48, 500
+    nu_l = 1.0 / 30.0
+    p = synth.base_params(nx=nx, ny=ny, wall_force="modpsi", tau_l=3 * nu_l + 0.5,
+                          tau_v=3 * 15 * nu_l + 0.5)
+    q, pg, rho0 = setup_case(orc, p, None, [(48.0, 0.5)], [16.0], seed=7)
+    gw = synth.gw_uniform(nx, 0.3)
+    sim = gpu.Sim(pg, gw, rho0)
+    sim.step(steps)
+    f = orc.run(q, gw, orc.init_rest(q, rho0), steps)
+    assert_f_close(q, sim.f(), f, what="visc ratio")
+    assert_obs_close(sim.observables(), orc.observables(q, gw, f))
+
+
+def test_step_parity_piecewise_eos(orc, gpu):
+    """The paper's own piecewise-linear EOS, Eq. (15), rho_l/rho_v = 500/1, sigma = 0.084."""
+    nx, ny, steps = 80, 40, 300
+    p = dict(nx=nx, ny=ny, walls=1, ghost=1, eos="piecewise", th_v=0.64 / 3, th_m=-0.04 / 3,
+             th_l=1 / 3, rho_v=1.0, rho_l=500.0, G=-1.0, sigma=0.084, tau_l=1.1, tau_v=1.1,
+             wall_force="modpsi", **synth.RATES)
+    q, pg, rho0 = setup_case(orc, p, None, [(40.0, 0.5)], [15.0], seed=9)
+    gw = synth.gw_uniform(nx, -0.1)
+    sim = gpu.Sim(pg, gw, rho0)
+    sim.step(steps)
+    f = orc.run(q, gw, orc.init_rest(q, rho0), steps)
+    assert_f_close(q, sim.f(), f, what="piecewise")
+
+
+def test_tile_shapes_and_schedules_bitwise(orc, gpu):
+    """Every fused tile shape gives bit-identical populations (LDS halo races would not)."""
+    nx, ny, steps = 200, 70, 150
+    p = synth.base_params(nx=nx, ny=ny, wall_force="rho")
+    q, pg, rho0 = setup_case(orc, p, None, [(100.0, 0.5)], [25.0], seed=13)
+    gw = synth.gw_uniform(nx, 0.1)
+    ref = None
+    for t in range(4):
+        sim = gpu.Sim(pg, gw, rho0)
+        sim.set_schedule(16 + t)
+        sim.step(steps)
+        f = sim.f()
+        if ref is None:
+            ref = f
+        else:
+            assert np.array_equal(f, ref), f"tile shape {t} differs from tile shape 0"
+    # rerun determinism
+    sim = gpu.Sim(pg, gw, rho0)
+    sim.set_schedule(16)
+    sim.step(steps)
+    assert np.array_equal(sim.f(), ref)
+
+
+def test_c1_geometry_10k_steps(orc, gpu):
+    """120x60 lattice, droplet R = 20 on the bottom wall, 10,000 steps. The psi-based wall force
+    at G_w = -0.05 (the specified G_w = -0.2 diverges, see test_c1_as_specified_diverges)."""
+    cfg = synth.c1_small()
+    p = dict(cfg["params"])
+    q, pg, rho0 = setup_case(orc, p, None, cfg["centres"], cfg["radii"], seed=cfg["seed"])
+    gw = synth.gw_uniform(q.nx, -0.05)
+    sim = gpu.Sim(pg, gw, rho0)
+    sim.step(cfg["steps"])
+    f = orc.run(q, gw, orc.init_rest(q, rho0), cfg["steps"])
+    assert_f_close(q, sim.f(), f, what="C1 10k")
+    og, oo = sim.observables(), orc.observables(q, gw, f)
+    print("gpu", og, "\noracle", oo)
+    assert_obs_close(og, oo)
+
+
+def test_c1_as_specified_diverges(orc, gpu):
+    """The 120x60 psi-based G_w = -0.2 case: both sides agree step by step until psi becomes
+    undefined next to the wall, and both report it at the same step."""
+    cfg = synth.c1_small()
+    p = dict(cfg["params"])
+    q, pg, rho0 = setup_case(orc, p, None, cfg["centres"], cfg["radii"], seed=cfg["seed"])
+    gw = cfg["gw"]
+    sim = gpu.Sim(pg, gw, rho0)
+    f = orc.init_rest(q, rho0)
+    fail_orc = fail_gpu = None
+    for n in range(1, 40):
+        try:
+            orc.run(q, gw, f, 1)
+            orc.fields(q, gw, f)
+        except orc.OracleError:
+            fail_orc = n
+        sim.step(1)
+        o = sim.observables(allow_nonfinite=True)
+        if o["nonfinite"]:
+            fail_gpu = n
+        if fail_orc or fail_gpu:
+            break
+        assert_f_close(q, sim.f(), f, tol=1e-7, what=f"C1 step {n}")
+    print("oracle fails at", fail_orc, "gpu at", fail_gpu)
+    assert fail_orc is not None and fail_orc == fail_gpu
+
+
+def test_save_load_state_bitwise(orc, gpu):
+    p = synth.base_params(nx=64, ny=32, wall_force="psi")
+    q, pg, rho0 = setup_case(orc, p, None, [(32.0, 0.5)], [10.0], seed=17)
+    gw = synth.gw_uniform(64, -0.02)
+    a = gpu.Sim(pg, gw, rho0)
+    a.step(50)
+    blob = a.save_state()
+    a.step(70)
+    b = gpu.Sim(pg, gw, rho0)
+    b.load_state(blob)
+    assert b.current_step == 50
+    b.step(70)
+    assert np.array_equal(a.f(), b.f())
+
+
+def test_mass_conservation_gpu(orc, gpu):
+    p = synth.base_params(nx=128, ny=64, wall_force="modpsi")
+    q, pg, rho0 = setup_case(orc, p, None, [(64.0, 0.5)], [20.0], seed=19)
+    sim = gpu.Sim(pg, synth.gw_uniform(128, -0.1), rho0)
+    m0 = sim.observables()["mass"]
+    sim.step(2000)
+    m1 = sim.observables()["mass"]
+    assert abs(m1 - m0) <= 1e-12 * m0
+
+
+def test_c2_full_size_sampled(orc, gpu):
+    """1024x512 with R = 150, the launch configuration of the benchmark: full populations after
+    60 steps for each wall-force form (oracle at full size)."""
+    runs = synth.c2_sweep()
+    seen = set()
+    for r in runs:
+        if r["form"] in seen:
+            continue
+        seen.add(r["form"])
+        p = dict(r["params"])
+        q, pg, rho0 = setup_case(orc, p, None, r["centres"], r["radii"], seed=r["seed"])
+        sim = gpu.Sim(pg, r["gw"], rho0)
+        sim.step(60)
+        f = orc.run(q, r["gw"], orc.init_rest(q, rho0), 60)
+        assert_f_close(q, sim.f(), f, what=f"C2 {r['form']} G_w={r['G_w']:.3f}")
