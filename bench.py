@@ -1,0 +1,192 @@
+"""Benchmark of the wetting pseudopotential LB step on one MI355X.
+
+Workload (one line of JSON on stdout): the 1024x512 sweep -- droplet of radius 150 on the bottom
+wall, Carnahan-Starling fluid at density ratio 500, the three wall-force forms x 8 values of G_w
+on a uniform grid (run order seeded) -- every run advanced by --steps time steps (50,000 by
+default, the full sweep). A "step" of this benchmark is one LB time step of all 24 runs.
+
+value: million fluid lattice updates per second (MLUPS) over the timed region, whole job.
+roofline: the dominant kernel (the fused step kernel) against HBM bandwidth, with algorithmic
+bytes = 144 B per lattice update (9 FP64 populations read + 9 written).
+cpu_baseline: the FP64 CPU oracle on a bounded slice of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & %HBM peak per LB step; batched-sweep and adjoint speedup vs plain"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LU = 144  # algorithmic: read and write the 9 FP64 populations once
+KERNEL_SOURCES = ["paper_1410_2569_amd/csrc/lbm_device.h", "paper_1410_2569_amd/csrc/lbm_kernels.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused_step_1024x512.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter summary, or None
+    when the counters were taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(budget_s: float = 12.0) -> dict:
+    """Oracle (plain C, FP64) on the first run of the sweep: as many steps as fit the budget."""
+    import numpy as np  # noqa: F401
+
+    import oracle
+    import synth
+
+    r = synth.c2_sweep()[0]
+    q = oracle.make_params(r["params"])
+    rho0 = synth.droplet_rho(q.nx, q.ny, q.rho_l, q.rho_v, r["centres"], r["radii"],
+                             seed=r["seed"])
+    f = oracle.init_rest(q, rho0)
+    oracle.run(q, r["gw"], f, 1)
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        oracle.run(q, r["gw"], f, 4)
+        steps += 4
+    dt = time.perf_counter() - t0
+    fluid = q.nx * (q.ny - 2)
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    return {"value": round(fluid * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps} steps of one 1024x512 run ({r['form']}, G_w={r['G_w']:.4f}), "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50_000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--schedule", default="fused")
+    ap.add_argument("--tile", type=int, default=None, help="fused tile shape index")
+    ap.add_argument("--runs", type=int, default=24, help="runs of the sweep to use (24 = all)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        log("bench.py: only --gpus 1 is supported (single-GPU build)")
+        sys.exit(2)
+
+    import torch
+
+    import paper_1410_2569_amd as L
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    runs = synth.c2_sweep()[: args.runs]
+    sims = []
+    for r in runs:
+        q = L.make_params(r["params"])
+        rho0 = synth.droplet_rho(q.nx, q.ny, q.rho_l, q.rho_v, r["centres"], r["radii"],
+                                 seed=r["seed"])
+        s = L.Sim(q, r["gw"], rho0, device=dev)
+        if args.tile is not None:
+            s.set_schedule(16 + args.tile)
+        else:
+            s.set_schedule(args.schedule)
+        sims.append(s)
+    nx, ny = runs[0]["params"]["nx"], runs[0]["params"]["ny"]
+    fluid = nx * (ny - 2)
+    log(f"bench: {len(sims)} runs of {nx}x{ny}, warmup {args.warmup}, steps {args.steps}")
+
+    for s in sims:
+        s.step(args.warmup)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    t0 = time.perf_counter()
+    chunk = 5000
+    done = 0
+    while done < args.steps:
+        n = min(chunk, args.steps - done)
+        for s in sims:
+            s.step(n)
+        done += n
+        if done % 20000 == 0 or done == args.steps:
+            log(f"bench: enqueued {done}/{args.steps} steps per run")
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    lu = fluid * args.steps * len(sims)
+    mlups = lu / (ms / 1e3) / 1e6
+    launches_per_step = 1 if sims[0] and args.schedule == "fused" else 2
+    step_launches = args.steps * len(sims)
+    avg_kernel_s = (ms / 1e3) / step_launches
+    achieved_gbs = BYTES_PER_LU * fluid / avg_kernel_s / 1e9
+    log(f"bench: {ms:.1f} ms (wall {wall:.1f} s), {mlups:.1f} MLUPS, "
+        f"{achieved_gbs:.1f} GB/s algorithmic")
+
+    # the timed state must be physical: report the observables of every run
+    phys = []
+    bad = 0
+    for r, s in zip(runs, sims):
+        o = s.observables(allow_nonfinite=True)
+        bad += o["nonfinite"] > 0
+        phys.append({"form": r["form"], "G_w": round(r["G_w"], 4),
+                     "theta": None if math.isnan(o["theta_deg"]) else round(o["theta_deg"], 2),
+                     "umax": o["umax"], "rho_min": o["rho_min"], "rho_max": o["rho_max"]})
+    for p in phys:
+        log("bench: run", p)
+
+    tr = traffic_per_launch()
+    roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+            "traffic": tr, "kernel": "lbm::k_step<fused>",
+            "bytes_per_lu": BYTES_PER_LU, "lu_per_launch": fluid,
+            "avg_launch_us": round(avg_kernel_s * 1e6, 3)}
+    out = {"metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms / args.steps, 6), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "1024x512 droplet R=150, CS EOS ratio 500, 3 wall forms x 8 "
+                                  "G_w, one LB step of all 24 runs per bench step",
+                      "lattice": [nx, ny], "runs": len(sims), "fluid_nodes_per_run": fluid,
+                      "schedule": args.schedule if args.tile is None else f"fused/tile{args.tile}"},
+           "hbm_frac_effective": round(BYTES_PER_LU * mlups * 1e6 / (HBM_PEAK_GBS * 1e9), 4),
+           "nonfinite_runs": bad,
+           "roofline": roof}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

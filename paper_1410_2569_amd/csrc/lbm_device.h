@@ -51,12 +51,15 @@ __device__ __forceinline__ double psi_of_rho(const KParams& P, double rho) {
 }
 
 // Pull the 9 pre-collision populations of fluid node (x, y) from post-collision buffer g.
+// Plane bases are uniform (scalar registers) and in-plane offsets 32-bit unsigned, so loads use
+// scalar-base + 32-bit vector-offset addressing.
 __device__ __forceinline__ void pull9(const KParams& P, const double* __restrict__ g, int x,
                                       int y, double f[9]) {
-    const int nx = P.nx;
-    const int xm = x == 0 ? nx - 1 : x - 1;
-    const int xp = x == nx - 1 ? 0 : x + 1;
-    int ym, yp;
+    const unsigned nx = P.nx, pitch = P.pitch;
+    const unsigned ux = x;
+    const unsigned xm = ux == 0 ? nx - 1 : ux - 1;
+    const unsigned xp = ux == nx - 1 ? 0 : ux + 1;
+    unsigned ym, yp;
     bool bot, top;
     if (P.walls) {
         ym = y - 1; yp = y + 1;
@@ -67,42 +70,44 @@ __device__ __forceinline__ void pull9(const KParams& P, const double* __restrict
         bot = top = false;
     }
     const long long pl = P.plane;
-    const long long r0 = (long long)y * P.pitch, rm = (long long)ym * P.pitch,
-                    rp = (long long)yp * P.pitch;
-    f[0] = g[r0 + x];
-    f[1] = g[1 * pl + r0 + xm];
-    f[3] = g[3 * pl + r0 + xp];
+    const unsigned r0 = (unsigned)y * pitch, rm = ym * pitch, rp = yp * pitch;
+    f[0] = g[r0 + ux];
+    f[1] = (g + 1 * pl)[r0 + xm];
+    f[3] = (g + 3 * pl)[r0 + xp];
     // populations arriving from below (e_y = +1): reflected at the bottom wall
-    f[2] = bot ? g[4 * pl + r0 + x] : g[2 * pl + rm + x];
-    f[5] = bot ? g[7 * pl + r0 + x] : g[5 * pl + rm + xm];
-    f[6] = bot ? g[8 * pl + r0 + x] : g[6 * pl + rm + xp];
+    f[2] = bot ? (g + 4 * pl)[r0 + ux] : (g + 2 * pl)[rm + ux];
+    f[5] = bot ? (g + 7 * pl)[r0 + ux] : (g + 5 * pl)[rm + xm];
+    f[6] = bot ? (g + 8 * pl)[r0 + ux] : (g + 6 * pl)[rm + xp];
     // populations arriving from above (e_y = -1): reflected at the top wall
-    f[4] = top ? g[2 * pl + r0 + x] : g[4 * pl + rp + x];
-    f[7] = top ? g[5 * pl + r0 + x] : g[7 * pl + rp + xp];
-    f[8] = top ? g[6 * pl + r0 + x] : g[8 * pl + rp + xm];
+    f[4] = top ? (g + 2 * pl)[r0 + ux] : (g + 4 * pl)[rp + ux];
+    f[7] = top ? (g + 5 * pl)[r0 + ux] : (g + 7 * pl)[rp + xp];
+    f[8] = top ? (g + 6 * pl)[r0 + ux] : (g + 8 * pl)[rp + xm];
 }
 
-// psi at lattice position (gx, gy), gx any integer (wrapped), gy possibly a solid or outside row:
-// fluid rows pull and evaluate; solid rows take the mirrored fluid row (ghost) or 0.
+// The fluid node whose psi a lattice slot (gx, gy) holds: gx wraps (periodic x); a solid row
+// takes the adjacent fluid row (mirrored ghost psi) or nothing (psi = 0); rows outside the
+// lattice hold nothing. Returns false when the slot's psi is 0.
+__device__ __forceinline__ bool slot_source(const KParams& P, int gx, int gy, int& sx, int& sy) {
+    sx = wrapx(gx, P.nx);
+    if (P.walls) {
+        if (gy < 0 || gy > P.ny - 1) return false;
+        if (gy == 0) { sy = 1; return P.ghost != 0; }
+        if (gy == P.ny - 1) { sy = P.ny - 2; return P.ghost != 0; }
+        sy = gy;
+        return true;
+    }
+    sy = wrapx(gy, P.ny);
+    return true;
+}
+
+// psi at lattice position (gx, gy) (see slot_source), evaluated from the pulled populations.
 __device__ __forceinline__ double psi_at(const KParams& P, const double* __restrict__ g, int gx,
                                          int gy) {
-    int x = wrapx(gx, P.nx);
-    if (P.walls) {
-        if (gy < 0 || gy > P.ny - 1) return 0.0;
-        if (gy == 0) {
-            if (!P.ghost) return 0.0;
-            gy = 1;
-        } else if (gy == P.ny - 1) {
-            if (!P.ghost) return 0.0;
-            gy = P.ny - 2;
-        }
-    } else {
-        gy = wrapx(gy, P.ny);
-    }
+    int sx, sy;
+    if (!slot_source(P, gx, gy, sx, sy)) return 0.0;
     double f[9];
-    pull9(P, g, x, gy, f);
-    double rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-    return psi_of_rho(P, rho);
+    pull9(P, g, sx, sy, f);
+    return psi_of_rho(P, ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8]);
 }
 
 __device__ __forceinline__ double sum9(const double f[9]) {

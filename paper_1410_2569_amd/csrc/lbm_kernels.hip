@@ -81,9 +81,54 @@ __global__ __launch_bounds__(TX* TY) void k_step(KParams P, const double* __rest
     if (P.walls && (y == 1 || y == P.ny - 2)) adhesion_sum(P, gw, x, y, Ax, Ay);
     collide(P, f, rho, psi_c, sx, sy, Ax, Ay);
 
-    double* o = gout + (long long)y * P.pitch + x;
+    const unsigned i = (unsigned)y * P.pitch + x;
 #pragma unroll
-    for (int a = 0; a < 9; ++a) o[a * P.plane] = f[a];
+    for (int a = 0; a < 9; ++a) (gout + a * P.plane)[i] = f[a];
+}
+
+// Overlapped tiles: one 64-lane wave spans TXI = 62 interior columns plus the halo column on each
+// side, and the workgroup has TYI interior rows plus a halo row above and below. Every thread
+// pulls exactly one node and evaluates its psi (one memory round trip per tile, all loads
+// coalesced rows); the interior threads then collide and store.
+template <int TYI>
+__global__ __launch_bounds__(64 * (TYI + 2)) void k_step_ov(KParams P,
+                                                            const double* __restrict__ gin,
+                                                            double* __restrict__ gout,
+                                                            const double* __restrict__ gw) {
+    constexpr int TXI = 62, LW = 64;
+    __shared__ double sp[(TYI + 2) * LW];
+    const int ntx = (P.nx + TXI - 1) / TXI;
+    const int nty = (P.y_hi - P.y_lo + TYI) / TYI;
+    const int tile = xcd_tile(blockIdx.x, ntx * nty);
+    const int x0 = (tile % ntx) * TXI;
+    const int y0 = P.y_lo + (tile / ntx) * TYI;
+    const int l = threadIdx.x & 63, r = threadIdx.x >> 6;
+    const int gx = x0 - 1 + l, gy = y0 - 1 + r;
+    const bool interior = l >= 1 && l <= TXI && r >= 1 && r <= TYI && gx < P.nx && gy <= P.y_hi;
+
+    int sx, sy;
+    const bool has = slot_source(P, gx, gy, sx, sy);
+    double f[9];
+    double rho = 1.0, psi_c = 0.0;
+    if (has) {
+        pull9(P, gin, sx, sy, f);
+        rho = sum9(f);
+        psi_c = psi_of_rho(P, rho);
+    }
+    sp[r * LW + l] = psi_c;
+    __syncthreads();
+    if (!interior) return;
+
+    const double* c = sp + r * LW + l;
+    double sxx, syy;
+    cohesion_sum(c[-LW - 1], c[-LW], c[-LW + 1], c[-1], c[1], c[LW - 1], c[LW], c[LW + 1], sxx,
+                 syy);
+    double Ax = 0.0, Ay = 0.0;
+    if (P.walls && (gy == 1 || gy == P.ny - 2)) adhesion_sum(P, gw, gx, gy, Ax, Ay);
+    collide(P, f, rho, psi_c, sxx, syy, Ax, Ay);
+    const unsigned i = (unsigned)gy * P.pitch + gx;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) (gout + a * P.plane)[i] = f[a];
 }
 
 // psi pass of the two-pass schedule; also writes the mirrored ghost rows.
@@ -273,13 +318,26 @@ static hipError_t launch_step_t(const KParams& P, const double* gin, double* gou
     return hipGetLastError();
 }
 
-int n_tiles() { return 4; }
+template <int TYI>
+static hipError_t launch_step_ov(const KParams& P, const double* gin, double* gout,
+                                 const double* gw, hipStream_t s) {
+    const int ntx = (P.nx + 61) / 62;
+    const int nty = (P.y_hi - P.y_lo + TYI) / TYI;
+    hipLaunchKernelGGL((k_step_ov<TYI>), dim3(ntx * nty), dim3(64 * (TYI + 2)), 0, s, P, gin,
+                       gout, gw);
+    return hipGetLastError();
+}
+
+// Fused tile shapes: 0-3 halo-recompute tiles TX x TY; 4-7 overlapped tiles 62 x TYI.
+static const int kTiles[8][3] = {{64, 4, 0}, {64, 8, 0}, {64, 16, 0}, {128, 4, 0},
+                                 {62, 4, 1}, {62, 6, 1}, {62, 8, 1}, {62, 14, 1}};
+
+int n_tiles() { return 8; }
 
 void tile_shape(int tile, int* tx, int* ty) {
-    static const int T[4][2] = {{64, 4}, {64, 8}, {64, 16}, {128, 4}};
-    if (tile < 0 || tile >= 4) tile = 0;
-    *tx = T[tile][0];
-    *ty = T[tile][1];
+    if (tile < 0 || tile >= 8) tile = 0;
+    *tx = kTiles[tile][0];
+    *ty = kTiles[tile][1];
 }
 
 hipError_t launch_step(const KParams& P, int schedule, int tile, const double* gin, double* gout,
@@ -294,6 +352,10 @@ hipError_t launch_step(const KParams& P, int schedule, int tile, const double* g
         case 1: return launch_step_t<64, 8, true>(P, gin, gout, psi, gw, s);
         case 2: return launch_step_t<64, 16, true>(P, gin, gout, psi, gw, s);
         case 3: return launch_step_t<128, 4, true>(P, gin, gout, psi, gw, s);
+        case 4: return launch_step_ov<4>(P, gin, gout, gw, s);
+        case 5: return launch_step_ov<6>(P, gin, gout, gw, s);
+        case 6: return launch_step_ov<8>(P, gin, gout, gw, s);
+        case 7: return launch_step_ov<14>(P, gin, gout, gw, s);
         default: return launch_step_t<64, 4, true>(P, gin, gout, psi, gw, s);
     }
 }

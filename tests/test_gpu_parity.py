@@ -132,7 +132,7 @@ def test_tile_shapes_and_schedules_bitwise(orc, gpu):
     q, pg, rho0 = setup_case(orc, p, None, [(100.0, 0.5)], [25.0], seed=13)
     gw = synth.gw_uniform(nx, 0.1)
     ref = None
-    for t in range(4):
+    for t in range(8):
         sim = gpu.Sim(pg, gw, rho0)
         sim.set_schedule(16 + t)
         sim.step(steps)
@@ -146,6 +146,28 @@ def test_tile_shapes_and_schedules_bitwise(orc, gpu):
     sim.set_schedule(16)
     sim.step(steps)
     assert np.array_equal(sim.f(), ref)
+
+
+@pytest.mark.parametrize("nx,ny,walls", [(3, 4, 1), (5, 6, 1), (7, 3, 0), (61, 9, 1), (63, 10, 0),
+                                         (125, 17, 1)])
+def test_tiny_and_ragged_lattices_all_tiles(orc, gpu, nx, ny, walls):
+    """Edge cases: the smallest lattices (every halo wraps several times), widths just below and
+    above one overlapped tile, every tile shape and both schedules against the oracle."""
+    steps = 40
+    p = synth.base_params(nx=nx, ny=ny, walls=walls, wall_force="modpsi")
+    q = orc.make_params(p)
+    rng = np.random.default_rng(nx * 100 + ny)
+    rho0 = synth.droplet_rho(nx, ny, q.rho_l, q.rho_v, [(nx / 2.0, 0.5 if walls else ny / 2.0)],
+                             [max(1.0, min(nx, ny) / 3.0)], jitter=1e-2, seed=nx + ny,
+                             walls=bool(walls))
+    pg = dict(p, rho_l=q.rho_l, rho_v=q.rho_v)
+    gw = rng.uniform(-0.1, 0.1, (2, nx))
+    f = orc.run(q, gw, orc.init_rest(q, rho0), steps)
+    for sched in [0, 1] + [16 + t for t in range(8)]:
+        sim = gpu.Sim(pg, gw, rho0)
+        sim.set_schedule(sched)
+        sim.step(steps)
+        assert_f_close(q, sim.f(), f, what=f"{nx}x{ny} walls={walls} schedule {sched}")
 
 
 def test_c1_geometry_10k_steps(orc, gpu):
