@@ -81,6 +81,35 @@ def cpu_baseline(budget_s: float = 12.0) -> dict:
                       f"{dt:.1f} s"}
 
 
+COPY_BYTES = 9 * 512 * 1024 * 8  # one population buffer of the 1024x512 workload
+
+
+def profile_probe(args):
+    """Workload for rocprofv3 counter runs: three copies of COPY_BYTES (a plain copy kernel that
+    reads and writes a known number of bytes, used to scale the counters) and 20 launches of the
+    step kernel on the first run of the sweep."""
+    import torch
+
+    import paper_1410_2569_amd as L
+    import synth
+
+    a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    r = synth.c2_sweep()[0]
+    q = L.make_params(r["params"])
+    rho0 = synth.droplet_rho(q.nx, q.ny, q.rho_l, q.rho_v, r["centres"], r["radii"],
+                             seed=r["seed"])
+    s = L.Sim(q, r["gw"], rho0)
+    if args.tile is not None:
+        s.set_schedule(16 + args.tile)
+    s.step(20)
+    torch.cuda.synchronize()
+    log(f"profile probe: copy {COPY_BYTES} B x3, 20 step launches of {q.nx}x{q.ny}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +119,9 @@ def main():
     ap.add_argument("--tile", type=int, default=None, help="fused tile shape index")
     ap.add_argument("--runs", type=int, default=24, help="runs of the sweep to use (24 = all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-probe", action="store_true",
+                    help="for counter runs: a device copy of known size, then 20 step launches "
+                         "of one run of the workload; prints no JSON")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -106,6 +138,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.profile_probe:
+        profile_probe(args)
+        return
     runs = synth.c2_sweep()[: args.runs]
     sims = []
     for r in runs:
