@@ -81,6 +81,125 @@ def cpu_baseline(budget_s: float = 12.0) -> dict:
                       f"{dt:.1f} s"}
 
 
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def batched_speedup(args) -> dict:
+    """96-instance uneven ensemble: one lbm_batch_step(n) (autotuned tile and schedule) against
+    the plain loop that advances each instance alone with lbm_step(n)."""
+    import numpy as np
+
+    import paper_1410_2569_amd as L
+    import synth
+    from paper_1410_2569_amd import tune as T
+
+    ens = synth.c3_ensemble()
+    n = args.batch_steps
+    prm, gws, rhos = [], [], []
+    for e in ens:
+        q = L.make_params(e["params"])
+        prm.append(dict(e["params"], rho_l=q.rho_l, rho_v=q.rho_v))
+        gws.append(e["gw"])
+        rhos.append(synth.droplet_rho(q.nx, q.ny, q.rho_l, q.rho_v, e["centres"], e["radii"],
+                                      seed=e["seed"]))
+    fluid = sum(p["nx"] * (p["ny"] - 2) for p in prm)
+    best = T.tuned(prm, gws, rhos, steps=200)
+    log(f"bench: ensemble of {len(prm)} ({fluid} fluid nodes), tune {best}")
+    b = L.Batch(prm, gws, rhos, tune=best)
+    b.step(2)  # warm-up; the timed call captures its graph once (well under a millisecond)
+    t_batch = _timed(lambda: b.step(n))
+    obs = b.observables(allow_nonfinite=True)
+    sims = [L.Sim(p, g, r) for p, g, r in zip(prm, gws, rhos)]
+    for s in sims:
+        s.step(2)
+
+    def plain():
+        for s in sims:
+            s.step(n)
+
+    t_plain = _timed(plain)
+    same = all(np.array_equal(b.f(i), sims[i].f()) for i in (0, len(sims) // 2, len(sims) - 1))
+    bad = sum(1 for o in obs if o["nonfinite"])
+    log(f"bench: batched {t_batch:.2f} s vs plain loop {t_plain:.2f} s")
+    return {"value": round(t_plain / t_batch, 3), "unit": "x (plain loop time / batched time)",
+            "mlups_batched": round(fluid * n / t_batch / 1e6, 1),
+            "mlups_plain_loop": round(fluid * n / t_plain / 1e6, 1),
+            "instances": len(prm), "fluid_nodes": fluid, "steps": n,
+            "tune": {k: best[k] for k in ("tile", "schedule", "waves_per_cu")},
+            "bitwise_equal_to_plain": bool(same), "nonfinite_instances": bad,
+            "workload": "96 uneven lattices 128x64..512x256, 3 forms x G_w sweep x viscosity "
+                        "ratios {1,5,15}"}
+
+
+def adjoint_speedup(args) -> dict:
+    """dL/dG_w on 256x128 after 4,000 steps: checkpointed forward + hand-written adjoint against
+    central differences of the plain GPU forward over all 256 bottom-wall nodes (512 runs; the
+    time of --adj-fd-runs of them is scaled to 512, the runs being identical in work)."""
+    import numpy as np
+
+    import paper_1410_2569_amd as L
+    import synth
+
+    cfg = synth.c4_adjoint()
+    N, K = cfg["steps"], cfg["K"]
+    q = L.make_params(cfg["params"])
+    rho0 = synth.droplet_rho(q.nx, q.ny, q.rho_l, q.rho_v, cfg["centres"], cfg["radii"],
+                             seed=cfg["seed"])
+    gw = cfg["gw"]
+    sim = L.Sim(q, gw, rho0)
+    blob = sim.save_state()
+    ws = sim.adjoint_workspace(N, K)
+    sim.forward_ckpt(N, K, ws)
+    sim.backward(N, K, ws)  # warm-up
+    sim.load_state(blob)
+
+    def adj():
+        sim.forward_ckpt(N, K, ws)
+        sim.loss()
+        return sim.backward(N, K, ws)
+
+    holder = {}
+    t_adj = _timed(lambda: holder.setdefault("g", adj()))
+    g = holder["g"].cpu().numpy()
+    h = 1e-5
+    nodes = list(range(0, q.nx, max(1, q.nx // max(1, args.adj_fd_runs // 2))))[
+        : max(1, args.adj_fd_runs // 2)]
+    fd = {}
+
+    def fd_runs():
+        for x in nodes:
+            vals = []
+            for sgn in (1, -1):
+                gg = gw.copy()
+                gg[0, x] += sgn * h
+                sim.load_state(blob)
+                sim.set_gw(gg)
+                sim.step(N)
+                vals.append(sim.loss())
+            fd[x] = (vals[0] - vals[1]) / (2 * h)
+
+    t_fd_part = _timed(fd_runs)
+    runs = 2 * len(nodes)
+    t_fd = t_fd_part * 512 / runs
+    scale = np.abs(g[0]).max()
+    err = max(abs(g[0, x] - v) / scale for x, v in fd.items())
+    fluid = q.nx * (q.ny - 2)
+    log(f"bench: adjoint {t_adj:.3f} s vs FD {t_fd:.2f} s (from {runs} runs), err {err:.2e}")
+    return {"value": round(t_fd / t_adj, 1), "unit": "x (FD gradient time / adjoint time)",
+            "t_adjoint_s": round(t_adj, 4), "t_fd_512_runs_s": round(t_fd, 3),
+            "fd_runs_timed": runs, "max_rel_err_vs_fd": float(err),
+            "mlups_forward_ckpt_plus_backward": round(2 * fluid * N / t_adj / 1e6, 1),
+            "workload": "256x128, R=40, modified form, smooth G_w, 4,000 steps, K=200"}
+
+
 COPY_BYTES = 9 * 512 * 1024 * 8  # one population buffer of the 1024x512 workload
 
 
@@ -119,6 +238,11 @@ def main():
     ap.add_argument("--tile", type=int, default=None, help="fused tile shape index")
     ap.add_argument("--runs", type=int, default=24, help="runs of the sweep to use (24 = all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched-ensemble and adjoint speedup measurements")
+    ap.add_argument("--batch-steps", type=int, default=20_000)
+    ap.add_argument("--adj-fd-runs", type=int, default=64,
+                    help="forward runs timed for the finite-difference baseline (of 512)")
     ap.add_argument("--profile-probe", action="store_true",
                     help="for counter runs: a device copy of known size, then 20 step launches "
                          "of one run of the workload; prints no JSON")
@@ -218,6 +342,9 @@ def main():
            "hbm_frac_effective": round(BYTES_PER_LU * mlups * 1e6 / (HBM_PEAK_GBS * 1e9), 4),
            "nonfinite_runs": bad,
            "roofline": roof}
+    if not args.no_extras:
+        out["batched"] = batched_speedup(args)
+        out["adjoint"] = adjoint_speedup(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -149,6 +149,77 @@ int lbm_set_gw(lbm_ctx *c, const double *gw_host);
  * floating-point contraction. */
 int lbm_set_schedule(lbm_ctx *c, int32_t schedule);
 
+/* ---- Gradients of a wetting objective with respect to the wall wettability G_w ------------- */
+/*
+ * Objective on the state f^N after N steps (walls = 1 only): with the phase fraction
+ * phi = (rho - rho_v)/(rho_l - rho_v) over fluid nodes, the centroid height
+ * y_c = sum phi (y - 1/2) / sum phi and the wetted length l_w = sum_x phi(x, 1),
+ *     L = w_centroid * y_c + w_wet * l_w.
+ * The gradient dL/dG_w (the G_w of every solid node of both walls, which enter the adhesion
+ * forces Eqs. 10, 11, 14) is obtained by a hand-written adjoint of Eqs. (1)-(11), (14), the
+ * pseudopotential and the halfway bounce-back, with checkpoint-every-K recomputation:
+ *  1. lbm_forward_ckpt(c, N, K, ws, bytes) advances c by N steps and stores the state every K
+ *     steps in the device workspace ws (>= lbm_adjoint_workspace_size() bytes, 256-aligned,
+ *     caller-owned);
+ *  2. lbm_loss() evaluates L on the current state (synchronises);
+ *  3. lbm_backward(c, N, K, ws, bytes, w_centroid, w_wet, d_grad) must follow the matching
+ *     lbm_forward_ckpt on the same context (LBM_E_STATE otherwise). It recomputes each segment of
+ *     K steps from its checkpoint, runs the adjoint steps in reverse and writes dL/dG_w into the
+ *     device array d_grad [2][nx] (row 0 bottom wall, row 1 top wall). Asynchronous on the
+ *     context stream; the context's own state is left at step N.
+ * Memory: ceil(N/K) + K states of 9 * ny * round_up(nx, 32) doubles, plus about 24 planes.
+ */
+int lbm_adjoint_workspace_size(const lbm_params *p, int64_t nsteps, int32_t K, size_t *bytes);
+int lbm_forward_ckpt(lbm_ctx *c, int64_t nsteps, int32_t K, void *d_ws, size_t bytes);
+int lbm_loss(lbm_ctx *c, double w_centroid, double w_wet, double *L);
+int lbm_backward(lbm_ctx *c, int64_t nsteps, int32_t K, void *d_ws, size_t bytes,
+                 double w_centroid, double w_wet, double *d_grad_gw);
+
+/* ---- Ensembles of uneven lattices -------------------------------------------------------- */
+/*
+ * `count` independent instances (each with its own lbm_params: lattice size, wall force, G_w,
+ * viscosities ...) advanced together. All instances' tiles form one work-list, executed either
+ * one launch per time step (schedule 0, replayed from a captured hipGraph) or by one persistent
+ * launch for n steps (schedule 1: an occupancy-sized grid with a grid barrier between steps;
+ * lbm_batch_step is then a single hipGraphLaunch). Both run the same per-tile arithmetic as
+ * lbm_step, so every instance evolves bit-for-bit as it would alone.
+ */
+typedef struct {
+    int32_t tile;         /* tile shape 0..3: 64x4, 64x8, 64x16, 128x4 */
+    int32_t reserved;     /* must be 0 */
+    int32_t waves_per_cu; /* persistent schedule: workgroups per compute unit (0 = occupancy) */
+    int32_t schedule;     /* 0 per-step launches, 1 persistent */
+} lbm_tune;
+
+typedef struct lbm_batch lbm_batch;
+
+/* Device workspace bytes for the ensemble (tune may be NULL: tile 1, per-step schedule). */
+int lbm_batch_workspace_size(const lbm_params *p, int32_t count, const lbm_tune *tune,
+                             size_t *bytes);
+/* p[count]: parameters; gw_host[count] ([2][nx] each) and rho0_host[count] ([ny][nx] each):
+ * host arrays, copied; d_ws: caller-owned device workspace (256-byte aligned). */
+int lbm_batch_create(const lbm_params *p, int32_t count, const double *const *gw_host,
+                     const double *const *rho0_host, const lbm_tune *tune, void *d_ws,
+                     size_t bytes, void *hip_stream, lbm_batch **out);
+/* Advance every instance by n steps (asynchronous). */
+int lbm_batch_step(lbm_batch *b, int64_t n);
+/* Observables of every instance into out[count]; synchronises. LBM_E_HIP if a persistent run
+ * was aborted by the grid-barrier time-out (workgroups not co-resident). */
+int lbm_batch_observables(lbm_batch *b, lbm_obs *out);
+/* Pre-collision populations f^n of instance `index` ([9][ny][nx] host array). */
+int lbm_batch_read_f(lbm_batch *b, int32_t index, double *host, size_t count);
+int64_t lbm_batch_current_step(const lbm_batch *b);
+/* The tune in use and the persistent grid size (workgroups). */
+int lbm_batch_get_tune(const lbm_batch *b, lbm_tune *t, int32_t *grid);
+int lbm_batch_destroy(lbm_batch *b);
+const char *lbm_batch_last_error(const lbm_batch *b);
+/* Autotuner: times every tile shape x schedule (persistent at full and half occupancy) for
+ * `steps` steps on this ensemble in the given workspace and returns the fastest tune and its
+ * time in milliseconds. */
+int lbm_autotune(const lbm_params *p, int32_t count, const double *const *gw_host,
+                 const double *const *rho0_host, void *d_ws, size_t bytes, void *hip_stream,
+                 int32_t steps, lbm_tune *best, double *best_ms);
+
 int64_t lbm_current_step(const lbm_ctx *c);
 int lbm_destroy(lbm_ctx *c);
 const char *lbm_strerror(int code);

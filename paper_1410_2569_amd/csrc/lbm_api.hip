@@ -3,11 +3,14 @@
 // and the Carnahan-Starling Maxwell construction.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
+#include <vector>
 
 #include "../../include/lbm.h"
 #include "lbm_internal.h"
@@ -29,6 +32,10 @@ struct lbm_ctx {
     int64_t step;
     int schedule;
     int tile;
+    // last lbm_forward_ckpt: where it started, its length and checkpoint interval
+    int64_t adj_start, adj_nsteps;
+    int32_t adj_K;
+    const void* adj_ws;
     std::string err;
 };
 
@@ -208,6 +215,38 @@ int maxwell_cs_impl(double a, double b, double R, double T, double* rv, double* 
     return LBM_OK;
 }
 
+struct AdjLayout {
+    int64_t nck;
+    size_t fbytes, pbytes;
+    size_t off_ck, off_seg, off_a, off_c, off_q, off_p0, off_dpsi, off_rv, off_gg, off_part,
+        off_fin, total;
+};
+
+AdjLayout adj_layout_of(const lbm_params* p, int64_t nsteps, int32_t K) {
+    AdjLayout A;
+    Layout L = layout_of(p);
+    A.nck = (nsteps + K - 1) / K;
+    A.fbytes = align_up((size_t)(9 * L.plane) * sizeof(double), kAlign);
+    A.pbytes = align_up((size_t)L.plane * sizeof(double), kAlign);
+    KParams tmp{};
+    tmp.nx = p->nx; tmp.ny = p->ny;
+    tmp.y_lo = p->walls ? 1 : 0; tmp.y_hi = p->walls ? p->ny - 2 : p->ny - 1;
+    size_t o = 0;
+    A.off_ck = o; o += (size_t)A.nck * A.fbytes;
+    A.off_seg = o; o += (size_t)K * A.fbytes;
+    A.off_a = o; o += 2 * A.fbytes;   // a ping-pong
+    A.off_c = o; o += 2 * A.pbytes;   // c ping-pong
+    A.off_q = o; o += 2 * A.pbytes;   // q_x, q_y
+    A.off_p0 = o; o += A.pbytes;
+    A.off_dpsi = o; o += A.pbytes;
+    A.off_rv = o; o += align_up((size_t)4 * L.pitch * sizeof(double), kAlign);
+    A.off_gg = o; o += align_up((size_t)2 * L.pitch * sizeof(double), kAlign);
+    A.off_part = o; o += align_up((size_t)lbm::loss_blocks(tmp) * 3 * sizeof(double), kAlign);
+    A.off_fin = o; o += kAlign;
+    A.total = o;
+    return A;
+}
+
 }  // namespace
 
 // =============================================================================================
@@ -305,6 +344,10 @@ int lbm_create(const lbm_params* p, const double* gw_host, const double* rho0_ho
     c->step = 0;
     c->schedule = 0;
     c->tile = 1;
+    c->adj_start = -1;
+    c->adj_nsteps = 0;
+    c->adj_K = 0;
+    c->adj_ws = nullptr;
 
     hipStream_t s = c->stream;
     hipError_t e;
@@ -350,30 +393,13 @@ int lbm_step(lbm_ctx* c, int64_t n) {
 
 int64_t lbm_current_step(const lbm_ctx* c) { return c ? c->step : -1; }
 
-int lbm_observables_window(lbm_ctx* c, double x_lo, double x_hi, lbm_obs* out) {
-    if (!c || !out) return LBM_E_INVAL;
-    const KParams& P = c->kp;
-    lbm::ObsArgs A;
-    A.rho_mid = 0.5 * (c->p.rho_l + c->p.rho_v);
-    A.y_min = 0.5 + 3.0;
-    A.x_lo = x_lo;
-    A.x_hi = x_hi;
-    A.cx = std::isfinite(x_lo) && std::isfinite(x_hi) ? 0.5 * (x_lo + x_hi) : 0.5 * P.nx;
-    A.cy = 0.5;
-    double* rho = c->g[c->cur ^ 1];  // the idle population buffer serves as scratch
-    hipError_t e = lbm::launch_rho_psi(P, c->g[c->cur], c->psi, rho, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "observables psi");
-    e = lbm::launch_obs(P, c->g[c->cur], rho, c->psi, c->gw, A, c->part, c->fin, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "observables");
-    double q[32];
-    e = hipMemcpyAsync(q, c->fin, lbm::OBS_NQ * sizeof(double), hipMemcpyDeviceToHost, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "observables copy");
-    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "observables sync");
-
+// Observables record from the reduced sums of the observables kernel: density extremes,
+// velocity maxima, mass, and the Kasa circle fit solved from its 3x3 normal equations.
+static void obs_from_sums(const double* q, const lbm::ObsArgs& A, int64_t step, lbm_obs* out) {
     enum { O_MIN = 0, O_MAX, O_U, O_UL, O_MASS, O_BAD, O_N, O_SX, O_SY, O_SXX, O_SYY, O_SXY,
            O_SXR, O_SYR, O_SR };
     lbm_obs o{};
-    o.step = c->step;
+    o.step = step;
     o.rho_min = q[O_MIN];
     o.rho_max = q[O_MAX];
     o.umax = q[O_U];
@@ -408,7 +434,30 @@ int lbm_observables_window(lbm_ctx* c, double x_lo, double x_hi, lbm_obs* out) {
         if (std::isfinite(cth) && std::fabs(cth) <= 1.0) o.theta_deg = std::acos(cth) * 180.0 / M_PI;
     }
     *out = o;
-    return o.nonfinite ? LBM_E_NONFINITE : LBM_OK;
+}
+
+int lbm_observables_window(lbm_ctx* c, double x_lo, double x_hi, lbm_obs* out) {
+    if (!c || !out) return LBM_E_INVAL;
+    const KParams& P = c->kp;
+    lbm::ObsArgs A;
+    A.rho_mid = 0.5 * (c->p.rho_l + c->p.rho_v);
+    A.y_min = 0.5 + 3.0;
+    A.x_lo = x_lo;
+    A.x_hi = x_hi;
+    A.cx = std::isfinite(x_lo) && std::isfinite(x_hi) ? 0.5 * (x_lo + x_hi) : 0.5 * P.nx;
+    A.cy = 0.5;
+    double* rho = c->g[c->cur ^ 1];  // the idle population buffer serves as scratch
+    hipError_t e = lbm::launch_rho_psi(P, c->g[c->cur], c->psi, rho, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "observables psi");
+    e = lbm::launch_obs(P, c->g[c->cur], rho, c->psi, c->gw, A, c->part, c->fin, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "observables");
+    double q[32];
+    e = hipMemcpyAsync(q, c->fin, lbm::OBS_NQ * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "observables copy");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "observables sync");
+
+    obs_from_sums(q, A, c->step, out);
+    return out->nonfinite ? LBM_E_NONFINITE : LBM_OK;
 }
 
 int lbm_observables(lbm_ctx* c, lbm_obs* out) {
@@ -509,6 +558,514 @@ int lbm_set_gw(lbm_ctx* c, const double* gw_host) {
     if (e != hipSuccess) return hip_fail(c, e, "set_gw");
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "set_gw sync");
     return LBM_OK;
+}
+
+
+// ---- adjoint ------------------------------------------------------------------------------
+
+int lbm_adjoint_workspace_size(const lbm_params* p, int64_t nsteps, int32_t K, size_t* bytes) {
+    if (!bytes || nsteps < 1 || K < 1) return LBM_E_INVAL;
+    int rc = validate(p, nullptr);
+    if (rc) return rc;
+    if (!p->walls) return LBM_E_INVAL;
+    *bytes = adj_layout_of(p, nsteps, K).total;
+    return LBM_OK;
+}
+
+static int run_loss(lbm_ctx* c, double* sums) {
+    hipError_t e = lbm::launch_loss(c->kp, c->g[c->cur], c->part, c->fin, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "loss");
+    e = hipMemcpyAsync(sums, c->fin, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "loss copy");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "loss sync");
+    return LBM_OK;
+}
+
+int lbm_loss(lbm_ctx* c, double w_centroid, double w_wet, double* L) {
+    if (!c || !L || !c->p.walls) return LBM_E_INVAL;
+    double s[3];
+    int rc = run_loss(c, s);
+    if (rc) return rc;
+    *L = w_centroid * s[1] / s[0] + w_wet * s[2];
+    return std::isfinite(*L) ? LBM_OK : fail(c, LBM_E_NONFINITE, "non-finite loss");
+}
+
+int lbm_forward_ckpt(lbm_ctx* c, int64_t nsteps, int32_t K, void* d_adj, size_t bytes) {
+    if (!c || !d_adj || nsteps < 1 || K < 1 || !c->p.walls) return LBM_E_INVAL;
+    AdjLayout A = adj_layout_of(&c->p, nsteps, K);
+    if (bytes < A.total) return fail(c, LBM_E_SIZE, "adjoint workspace too small");
+    if (((uintptr_t)d_adj) % kAlign) return fail(c, LBM_E_INVAL, "adjoint workspace misaligned");
+    char* w = (char*)d_adj;
+    const size_t fb = (size_t)9 * c->kp.plane * sizeof(double);
+    c->adj_start = c->step;
+    c->adj_nsteps = nsteps;
+    c->adj_K = K;
+    c->adj_ws = d_adj;
+    for (int64_t i = 0; i < nsteps; ++i) {
+        if (i % K == 0) {
+            hipError_t e = hipMemcpyAsync(w + A.off_ck + (size_t)(i / K) * A.fbytes, c->g[c->cur], fb,
+                                          hipMemcpyDeviceToDevice, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "checkpoint");
+        }
+        int rc = lbm_step(c, 1);
+        if (rc) return rc;
+    }
+    return LBM_OK;
+}
+
+int lbm_backward(lbm_ctx* c, int64_t nsteps, int32_t K, void* d_adj, size_t bytes,
+                 double w_centroid, double w_wet, double* d_grad_gw) {
+    if (!c || !d_adj || !d_grad_gw || nsteps < 1 || K < 1 || !c->p.walls) return LBM_E_INVAL;
+    AdjLayout A = adj_layout_of(&c->p, nsteps, K);
+    if (bytes < A.total) return fail(c, LBM_E_SIZE, "adjoint workspace too small");
+    if (c->adj_ws != d_adj || c->adj_nsteps != nsteps || c->adj_K != K ||
+        c->step != c->adj_start + nsteps)
+        return fail(c, LBM_E_STATE, "backward does not follow the matching lbm_forward_ckpt");
+    const KParams& P = c->kp;
+    hipStream_t s = c->stream;
+    char* w = (char*)d_adj;
+    const size_t fb = (size_t)9 * P.plane * sizeof(double);
+    hipError_t e = hipMemsetAsync(w + A.off_a, 0, A.total - A.off_a, s);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint clear");
+
+    double sums[3];
+    int rc = run_loss(c, sums);
+    if (rc) return rc;
+    const double yc = sums[1] / sums[0];
+    if (!std::isfinite(yc)) return fail(c, LBM_E_NONFINITE, "non-finite loss");
+    double* a_buf[2] = {(double*)(w + A.off_a), (double*)(w + A.off_a + A.fbytes)};
+    double* c_buf[2] = {(double*)(w + A.off_c), (double*)(w + A.off_c + A.pbytes)};
+    double* q = (double*)(w + A.off_q);
+    double* p0 = (double*)(w + A.off_p0);
+    double* dpsi = (double*)(w + A.off_dpsi);
+    double* rv = (double*)(w + A.off_rv);
+    double* gg = (double*)(w + A.off_gg);
+    if ((e = lbm::launch_loss_seed(P, w_centroid, w_wet, yc, sums[0], c_buf[0], s)) != hipSuccess)
+        return hip_fail(c, e, "loss seed");
+    int ca = 0;
+    for (int64_t j = A.nck - 1; j >= 0; --j) {
+        const int64_t k0 = j * K;
+        const int64_t len = std::min<int64_t>(K, nsteps - k0);
+        char* seg = w + A.off_seg;
+        e = hipMemcpyAsync(seg, w + A.off_ck + (size_t)j * A.fbytes, fb, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(c, e, "segment restore");
+        for (int64_t i = 0; i + 1 < len; ++i) {
+            e = lbm::launch_step(P, c->schedule, c->tile, (const double*)(seg + i * A.fbytes),
+                                 (double*)(seg + (i + 1) * A.fbytes), c->psi, c->gw, s);
+            if (e != hipSuccess) return hip_fail(c, e, "segment recompute");
+        }
+        for (int64_t i = len - 1; i >= 0; --i) {
+            e = lbm::launch_adj_step(P, (const double*)(seg + i * A.fbytes), a_buf[ca], c_buf[ca],
+                                     c->gw, a_buf[ca ^ 1], q, p0, dpsi, rv, c_buf[ca ^ 1], gg, s);
+            if (e != hipSuccess) return hip_fail(c, e, "adjoint step");
+            ca ^= 1;
+        }
+    }
+    e = hipMemcpy2DAsync(d_grad_gw, P.nx * sizeof(double), gg, P.pitch * sizeof(double),
+                         P.nx * sizeof(double), 2, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(c, e, "gradient copy");
+    return LBM_OK;
+}
+
+
+// ---- ensembles ------------------------------------------------------------------------------
+
+struct lbm_batch {
+    int32_t count;
+    std::vector<lbm_params> p;
+    std::vector<KParams> kp;
+    std::vector<lbm::InstDesc> desc;  // host copy of the device table
+    hipStream_t stream;
+    char* ws;
+    size_t bytes;
+    lbm::InstDesc* d_inst;
+    int* d_tile_inst;
+    unsigned* d_bar;
+    int* d_flag;
+    std::vector<double*> psi, part, fin;
+    int ntiles;
+    int cur;
+    int64_t step;
+    lbm_tune tune;
+    int grid;  // persistent grid size
+    hipGraphExec_t graph[2];  // per-step schedule: kGraphChunk launches starting at parity 0 / 1
+    hipGraphExec_t pgraph;    // persistent schedule: reset + persistent kernel for pgraph_n steps
+    int64_t pgraph_n;
+    int pgraph_cur;
+    std::string err;
+};
+
+namespace {
+
+constexpr int kGraphChunk = 64;
+constexpr int kSpinLimit = 1 << 22;
+
+struct BatchLayout {
+    size_t off_desc, off_tiles, off_bar, total;
+    std::vector<size_t> off_inst;  // per instance: g0, g1, gw, psi, part, fin
+    std::vector<Layout> L;
+    int ntiles;
+    std::vector<int> tile0, ntx, nty;
+};
+
+bool batch_layout(const lbm_params* p, int32_t count, int tile, BatchLayout* B) {
+    int TX = 64, TY = 4;
+    lbm::tile_shape(tile, &TX, &TY);
+    size_t o = 0;
+    B->off_desc = o;
+    o += align_up((size_t)count * sizeof(lbm::InstDesc), kAlign);
+    long long nt = 0;
+    B->tile0.resize(count); B->ntx.resize(count); B->nty.resize(count); B->L.resize(count);
+    for (int i = 0; i < count; ++i) {
+        const int ylo = p[i].walls ? 1 : 0, yhi = p[i].walls ? p[i].ny - 2 : p[i].ny - 1;
+        B->ntx[i] = (p[i].nx + TX - 1) / TX;
+        B->nty[i] = (yhi - ylo + TY) / TY;
+        B->tile0[i] = (int)nt;
+        nt += (long long)B->ntx[i] * B->nty[i];
+        B->L[i] = layout_of(&p[i]);
+    }
+    if (nt > (1LL << 30)) return false;
+    B->ntiles = (int)nt;
+    B->off_tiles = o;
+    o += align_up((size_t)nt * sizeof(int), kAlign);
+    B->off_bar = o;
+    o += kAlign;
+    B->off_inst.resize(count);
+    for (int i = 0; i < count; ++i) {
+        B->off_inst[i] = o;
+        o += B->L[i].total;
+    }
+    B->total = o;
+    return true;
+}
+
+int batch_fail(lbm_batch* b, int code, const std::string& m) {
+    if (b) b->err = m;
+    return code;
+}
+
+int validate_tune(const lbm_tune* t) {
+    if (!t) return LBM_OK;
+    if (t->tile < 0 || t->tile > 3 || t->schedule < 0 || t->schedule > 1 || t->waves_per_cu < 0)
+        return LBM_E_INVAL;
+    return LBM_OK;
+}
+
+}  // namespace
+
+int lbm_batch_workspace_size(const lbm_params* p, int32_t count, const lbm_tune* tune,
+                             size_t* bytes) {
+    if (!p || count < 1 || !bytes) return LBM_E_INVAL;
+    if (validate_tune(tune)) return LBM_E_INVAL;
+    for (int i = 0; i < count; ++i) {
+        int rc = validate(&p[i], nullptr);
+        if (rc) return rc;
+    }
+    BatchLayout B;
+    if (!batch_layout(p, count, tune ? tune->tile : 0, &B)) return LBM_E_INVAL;
+    *bytes = B.total;
+    return LBM_OK;
+}
+
+int lbm_batch_create(const lbm_params* p, int32_t count, const double* const* gw_host,
+                     const double* const* rho0_host, const lbm_tune* tune, void* d_ws,
+                     size_t bytes, void* stream, lbm_batch** out) {
+    if (!out) return LBM_E_INVAL;
+    *out = nullptr;
+    if (!p || count < 1 || !rho0_host || !gw_host || !d_ws) return LBM_E_INVAL;
+    if (validate_tune(tune)) return LBM_E_INVAL;
+    for (int i = 0; i < count; ++i) {
+        int rc = validate(&p[i], nullptr);
+        if (rc) return rc;
+        if (!rho0_host[i] || (p[i].walls && !gw_host[i])) return LBM_E_INVAL;
+    }
+    lbm_tune tn = tune ? *tune : lbm_tune{1, 0, 0, 0};
+    BatchLayout B;
+    if (!batch_layout(p, count, tn.tile, &B)) return LBM_E_INVAL;
+    if (bytes < B.total) return LBM_E_SIZE;
+    if (((uintptr_t)d_ws) % kAlign) return LBM_E_INVAL;
+
+    lbm_batch* b = new lbm_batch();
+    b->count = count;
+    b->p.assign(p, p + count);
+    b->stream = (hipStream_t)stream;
+    b->ws = (char*)d_ws;
+    b->bytes = bytes;
+    b->d_inst = (lbm::InstDesc*)(b->ws + B.off_desc);
+    b->d_tile_inst = (int*)(b->ws + B.off_tiles);
+    b->d_bar = (unsigned*)(b->ws + B.off_bar);
+    b->d_flag = (int*)(b->ws + B.off_bar + 64);
+    b->ntiles = B.ntiles;
+    b->cur = 0;
+    b->step = 0;
+    b->tune = tn;
+    b->graph[0] = b->graph[1] = nullptr;
+    b->pgraph = nullptr;
+    b->pgraph_n = -1;
+    b->pgraph_cur = -1;
+    hipStream_t s = b->stream;
+    hipError_t e = hipMemsetAsync(b->ws, 0, B.total, s);
+    if (e != hipSuccess) { delete b; return LBM_E_HIP; }
+    std::vector<int> tile_inst(B.ntiles);
+    for (int i = 0; i < count; ++i) {
+        const Layout& L = B.L[i];
+        char* base = b->ws + B.off_inst[i];
+        KParams kp = kparams_of(&p[i], L);
+        b->kp.push_back(kp);
+        lbm::InstDesc d{};
+        d.P = kp;
+        d.g[0] = (double*)(base + L.off_g0);
+        d.g[1] = (double*)(base + L.off_g1);
+        d.gw = (double*)(base + L.off_gw);
+        d.tile0 = B.tile0[i];
+        d.ntx = B.ntx[i];
+        d.nty = B.nty[i];
+        b->desc.push_back(d);
+        b->psi.push_back((double*)(base + L.off_psi));
+        b->part.push_back((double*)(base + L.off_part));
+        b->fin.push_back((double*)(base + L.off_fin));
+        for (int t = 0; t < B.ntx[i] * B.nty[i]; ++t) tile_inst[B.tile0[i] + t] = i;
+        for (long long k = 0; k < (long long)p[i].nx * p[i].ny; ++k) {
+            const int y = (int)(k / p[i].nx);
+            if (p[i].walls && (y == 0 || y == p[i].ny - 1)) continue;
+            if (!finite_pos(rho0_host[i][k])) { delete b; return LBM_E_INVAL; }
+        }
+        if (gw_host[i]) {
+            e = hipMemcpy2DAsync(d.gw, L.pitch * sizeof(double), gw_host[i],
+                                 p[i].nx * sizeof(double), p[i].nx * sizeof(double), 2,
+                                 hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) { delete b; return LBM_E_HIP; }
+        }
+        e = hipMemcpy2DAsync(d.g[1], L.pitch * sizeof(double), rho0_host[i],
+                             p[i].nx * sizeof(double), p[i].nx * sizeof(double), p[i].ny,
+                             hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) { delete b; return LBM_E_HIP; }
+        if ((e = lbm::launch_init(kp, d.g[1], d.g[0], s)) != hipSuccess) { delete b; return LBM_E_HIP; }
+    }
+    e = hipMemcpyAsync(b->d_inst, b->desc.data(), count * sizeof(lbm::InstDesc),
+                       hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) { delete b; return LBM_E_HIP; }
+    e = hipMemcpyAsync(b->d_tile_inst, tile_inst.data(), B.ntiles * sizeof(int),
+                       hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) { delete b; return LBM_E_HIP; }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) { delete b; return LBM_E_HIP; }
+    // persistent grid: co-resident workgroups only (occupancy x compute units)
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int occ = lbm::batch_persistent_occupancy(tn.tile);
+    if (tn.waves_per_cu > 0 && tn.waves_per_cu < occ) occ = tn.waves_per_cu;
+    b->grid = std::max(1, std::min(occ * cus, b->ntiles));
+    *out = b;
+    return LBM_OK;
+}
+
+static int batch_direct(lbm_batch* b, int64_t n) {
+    for (int64_t i = 0; i < n; ++i) {
+        hipError_t e = lbm::launch_batch_step(b->tune.tile, b->d_inst, b->d_tile_inst, b->ntiles,
+                                              b->cur, b->stream);
+        if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, std::string("batch step: ") + hipGetErrorString(e));
+        b->cur ^= 1;
+        b->step += 1;
+    }
+    return LBM_OK;
+}
+
+static int capture(lbm_batch* b, hipGraphExec_t* out, const std::function<hipError_t()>& body) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "begin capture");
+    hipError_t e1 = body();
+    e = hipStreamEndCapture(b->stream, &g);
+    if (e1 != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return batch_fail(b, LBM_E_HIP, "capture");
+    }
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "graph instantiate");
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch* b, int64_t n) {
+    if (!b || n < 0) return LBM_E_INVAL;
+    if (n == 0) return LBM_OK;
+    if (b->tune.schedule == 1) {
+        if (!b->pgraph || b->pgraph_n != n || b->pgraph_cur != b->cur) {
+            if (b->pgraph) { (void)hipGraphExecDestroy(b->pgraph); b->pgraph = nullptr; }
+            const int cur = b->cur;
+            int rc = capture(b, &b->pgraph, [&]() {
+                return lbm::launch_batch_persistent(b->tune.tile, b->grid, b->d_inst,
+                                                    b->d_tile_inst, b->ntiles, (int)n, cur,
+                                                    b->d_bar, b->d_flag, kSpinLimit, b->stream);
+            });
+            if (rc) return rc;
+            b->pgraph_n = n;
+            b->pgraph_cur = cur;
+        }
+        hipError_t e = hipGraphLaunch(b->pgraph, b->stream);
+        if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "graph launch");
+        b->cur ^= (int)(n & 1);
+        b->step += n;
+        return LBM_OK;
+    }
+    // per-step schedule: replay a graph of kGraphChunk launches, then the remainder directly
+    int64_t chunks = n / kGraphChunk;
+    for (int64_t k = 0; k < chunks; ++k) {
+        const int cur = b->cur;
+        if (!b->graph[cur]) {
+            int rc = capture(b, &b->graph[cur], [&]() {
+                for (int i = 0; i < kGraphChunk; ++i) {
+                    hipError_t e = lbm::launch_batch_step(b->tune.tile, b->d_inst,
+                                                          b->d_tile_inst, b->ntiles,
+                                                          (cur + i) & 1, b->stream);
+                    if (e != hipSuccess) return e;
+                }
+                return hipSuccess;
+            });
+            if (rc) return rc;
+        }
+        hipError_t e = hipGraphLaunch(b->graph[cur], b->stream);
+        if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "graph launch");
+        b->step += kGraphChunk;  // kGraphChunk is even: parity unchanged
+    }
+    return batch_direct(b, n - chunks * kGraphChunk);
+}
+
+static int batch_check_abort(lbm_batch* b) {
+    int flag = 0;
+    hipError_t e = hipMemcpyAsync(&flag, b->d_flag, sizeof(int), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "flag read");
+    if (flag) return batch_fail(b, LBM_E_HIP, "grid barrier timed out: workgroups not co-resident");
+    return LBM_OK;
+}
+
+int lbm_batch_observables(lbm_batch* b, lbm_obs* out) {
+    if (!b || !out) return LBM_E_INVAL;
+    int rc = batch_check_abort(b);
+    if (rc) return rc;
+    std::vector<double> q((size_t)b->count * 32);
+    std::vector<lbm::ObsArgs> args(b->count);
+    for (int i = 0; i < b->count; ++i) {
+        const KParams& P = b->kp[i];
+        const lbm::InstDesc& d = b->desc[i];
+        lbm::ObsArgs& A = args[i];
+        A.rho_mid = 0.5 * (b->p[i].rho_l + b->p[i].rho_v);
+        A.y_min = 3.5;
+        A.x_lo = -INFINITY;
+        A.x_hi = INFINITY;
+        A.cx = 0.5 * P.nx;
+        A.cy = 0.5;
+        double* rho = d.g[b->cur ^ 1];
+        hipError_t e = lbm::launch_rho_psi(P, d.g[b->cur], b->psi[i], rho, b->stream);
+        if (e == hipSuccess)
+            e = lbm::launch_obs(P, d.g[b->cur], rho, b->psi[i], d.gw, A, b->part[i], b->fin[i],
+                                b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(q.data() + (size_t)i * 32, b->fin[i], lbm::OBS_NQ * sizeof(double),
+                               hipMemcpyDeviceToHost, b->stream);
+        if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "batch observables");
+    }
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "batch observables sync");
+    int bad = 0;
+    for (int i = 0; i < b->count; ++i) {
+        obs_from_sums(q.data() + (size_t)i * 32, args[i], b->step, &out[i]);
+        bad |= out[i].nonfinite != 0;
+    }
+    return bad ? LBM_E_NONFINITE : LBM_OK;
+}
+
+int lbm_batch_read_f(lbm_batch* b, int32_t index, double* host, size_t count) {
+    if (!b || !host || index < 0 || index >= b->count) return LBM_E_INVAL;
+    int rc = batch_check_abort(b);
+    if (rc) return rc;
+    const KParams& P = b->kp[index];
+    if (count < (size_t)9 * P.nx * P.ny) return LBM_E_SIZE;
+    const lbm::InstDesc& d = b->desc[index];
+    double* scratch = d.g[b->cur ^ 1];
+    hipError_t e = hipMemsetAsync(scratch, 0, (size_t)9 * P.plane * sizeof(double), b->stream);
+    if (e == hipSuccess) e = lbm::launch_pull(P, d.g[b->cur], scratch, b->stream);
+    for (int a = 0; a < 9 && e == hipSuccess; ++a)
+        e = hipMemcpy2DAsync(host + (size_t)a * P.nx * P.ny, P.nx * sizeof(double),
+                             scratch + a * P.plane, P.pitch * sizeof(double),
+                             P.nx * sizeof(double), P.ny, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "batch read");
+    return LBM_OK;
+}
+
+int64_t lbm_batch_current_step(const lbm_batch* b) { return b ? b->step : -1; }
+
+int lbm_batch_get_tune(const lbm_batch* b, lbm_tune* t, int32_t* grid) {
+    if (!b || !t) return LBM_E_INVAL;
+    *t = b->tune;
+    if (grid) *grid = b->grid;
+    return LBM_OK;
+}
+
+int lbm_batch_destroy(lbm_batch* b) {
+    if (!b) return LBM_E_INVAL;
+    for (auto& g : b->graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (b->pgraph) (void)hipGraphExecDestroy(b->pgraph);
+    delete b;
+    return LBM_OK;
+}
+
+const char* lbm_batch_last_error(const lbm_batch* b) { return b ? b->err.c_str() : ""; }
+
+// Try every tile shape x schedule (and, for the persistent schedule, the full and half
+// occupancy) on the given ensemble for `steps` steps each; return the fastest in *best and its
+// time in *ms. The workspace must hold lbm_batch_workspace_size(p, count, NULL) bytes.
+int lbm_autotune(const lbm_params* p, int32_t count, const double* const* gw_host,
+                 const double* const* rho0_host, void* d_ws, size_t bytes, void* stream,
+                 int32_t steps, lbm_tune* best, double* best_ms) {
+    if (!best || steps < 1) return LBM_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LBM_E_HIP;
+    double best_t = INFINITY;
+    int rc_all = LBM_E_INVAL;
+    for (int tile = 0; tile < 4; ++tile) {
+        for (int sched = 0; sched < 2; ++sched) {
+            for (int half = 0; half < (sched == 1 ? 2 : 1); ++half) {
+                lbm_tune t{tile, 0, 0, sched};
+                size_t need;
+                if (lbm_batch_workspace_size(p, count, &t, &need) || need > bytes) continue;
+                if (half) {
+                    int occ = lbm::batch_persistent_occupancy(tile);
+                    if (occ < 2) continue;
+                    t.waves_per_cu = occ / 2;
+                }
+                lbm_batch* b = nullptr;
+                if (lbm_batch_create(p, count, gw_host, rho0_host, &t, d_ws, bytes, stream, &b))
+                    continue;
+                int rc = lbm_batch_step(b, 2);  // warm-up (captures graphs)
+                if (!rc) rc = lbm_batch_step(b, steps);  // same step count as timed: graph reused
+                (void)hipStreamSynchronize(s);
+                (void)hipEventRecord(e0, s);
+                if (!rc) rc = lbm_batch_step(b, steps);
+                (void)hipEventRecord(e1, s);
+                (void)hipEventSynchronize(e1);
+                if (!rc) rc = batch_check_abort(b);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                lbm_batch_destroy(b);
+                if (rc) continue;
+                rc_all = LBM_OK;
+                if (ms < best_t) {
+                    best_t = ms;
+                    *best = t;
+                }
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best_ms) *best_ms = best_t;
+    return rc_all;
 }
 
 int lbm_destroy(lbm_ctx* c) {

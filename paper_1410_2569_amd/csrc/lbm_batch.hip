@@ -1,0 +1,164 @@
+// lbm_batch.hip -- ensembles of uneven lattices advanced together.
+//
+// The tiles of every instance form one flattened work-list. Two schedules run the same per-tile
+// device function as the single-instance step (so results are bitwise identical to it):
+//   per-step   one launch per time step over the whole work-list (replayed from a hipGraph);
+//   persistent one launch for n steps: an occupancy-sized grid in which each workgroup owns a
+//              contiguous chunk of the work-list (contiguous per XCD), with a grid barrier
+//              between steps. The barrier publishes the step's stores at agent scope (release),
+//              waits for every workgroup, then acquires; its wait is bounded and raises an abort
+//              flag on timeout so every workgroup always exits.
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+namespace lbm {
+
+__device__ __forceinline__ void batch_tile_origin(const InstDesc* D, int t, int TX, int TY,
+                                                  int& x0, int& y0) {
+    const int lt = t - D->tile0;
+    x0 = (lt % D->ntx) * TX;
+    y0 = D->P.y_lo + (lt / D->ntx) * TY;
+}
+
+template <int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_batch_step(const InstDesc* __restrict__ inst,
+                                                       const int* __restrict__ tile_inst,
+                                                       int ntiles, int cur) {
+    __shared__ double sp[(TY + 2) * (TX + 2)];
+    const int t = xcd_tile(blockIdx.x, ntiles);
+    const InstDesc* D = inst + tile_inst[t];
+    int x0, y0;
+    batch_tile_origin(D, t, TX, TY, x0, y0);
+    step_tile<TX, TY, true>(D->P, D->g[cur], D->g[cur ^ 1], nullptr, D->gw, x0, y0, sp);
+}
+
+// Grid-wide barrier number `target / gridDim.x`. Returns false when the run was aborted.
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, int* flag,
+                                             int spin_limit, int* verdict) {
+    __syncthreads();  // every wave's stores of this step have completed
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1;
+        for (int n = 0;; ++n) {
+            if (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+            if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                ok = 0;
+                break;
+            }
+            if (n >= spin_limit) {
+                __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *verdict = ok;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return *verdict != 0;
+}
+
+template <int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_batch_persistent(const InstDesc* __restrict__ inst,
+                                                             const int* __restrict__ tile_inst,
+                                                             int ntiles, int nsteps, int cur0,
+                                                             unsigned* bar, int* flag,
+                                                             int spin_limit) {
+    __shared__ double sp[(TY + 2) * (TX + 2)];
+    __shared__ int verdict;
+    const int G = gridDim.x;
+    const int L = xcd_tile(blockIdx.x, G);
+    const int t_lo = (int)((long long)L * ntiles / G);
+    const int t_hi = (int)((long long)(L + 1) * ntiles / G);
+    for (int s = 0; s < nsteps; ++s) {
+        const int cur = (cur0 + s) & 1;
+        for (int t = t_lo; t < t_hi; ++t) {
+            const InstDesc* D = inst + tile_inst[t];
+            int x0, y0;
+            batch_tile_origin(D, t, TX, TY, x0, y0);
+            step_tile<TX, TY, true>(D->P, D->g[cur], D->g[cur ^ 1], nullptr, D->gw, x0, y0, sp);
+            __syncthreads();  // the LDS tile is reused by the next tile
+        }
+        if (!grid_barrier(bar, (unsigned)(s + 1) * (unsigned)G, flag, spin_limit, &verdict)) return;
+    }
+}
+
+// Clears the barrier counter and abort flag (a kernel rather than a memset node, so the pair can
+// sit in a hipGraph).
+__global__ void k_batch_reset(unsigned* bar, int* flag) {
+    if (threadIdx.x == 0) {
+        *bar = 0u;
+        *flag = 0;
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+template <int TX, int TY>
+static hipError_t launch_batch_t(const InstDesc* inst, const int* tile_inst, int ntiles, int cur,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL((k_batch_step<TX, TY>), dim3(ntiles), dim3(TX * TY), 0, s, inst, tile_inst,
+                       ntiles, cur);
+    return hipGetLastError();
+}
+
+template <int TX, int TY>
+static hipError_t launch_persist_t(int grid, const InstDesc* inst, const int* tile_inst,
+                                   int ntiles, int nsteps, int cur, unsigned* bar, int* flag,
+                                   int spin_limit, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, bar, flag);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_batch_persistent<TX, TY>), dim3(grid), dim3(TX * TY), 0, s, inst,
+                       tile_inst, ntiles, nsteps, cur, bar, flag, spin_limit);
+    return hipGetLastError();
+}
+
+template <int TX, int TY>
+static int occupancy_t() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_persistent<TX, TY>, TX * TY, 0) !=
+        hipSuccess)
+        return 0;
+    return n;
+}
+
+int batch_tiles(int tile) { return tile >= 0 && tile < 4; }
+
+hipError_t launch_batch_step(int tile, const InstDesc* inst, const int* tile_inst, int ntiles,
+                             int cur, hipStream_t s) {
+    switch (tile) {
+        case 1: return launch_batch_t<64, 8>(inst, tile_inst, ntiles, cur, s);
+        case 2: return launch_batch_t<64, 16>(inst, tile_inst, ntiles, cur, s);
+        case 3: return launch_batch_t<128, 4>(inst, tile_inst, ntiles, cur, s);
+        default: return launch_batch_t<64, 4>(inst, tile_inst, ntiles, cur, s);
+    }
+}
+
+hipError_t launch_batch_persistent(int tile, int grid, const InstDesc* inst,
+                                   const int* tile_inst, int ntiles, int nsteps, int cur,
+                                   unsigned* bar, int* flag, int spin_limit, hipStream_t s) {
+    switch (tile) {
+        case 1: return launch_persist_t<64, 8>(grid, inst, tile_inst, ntiles, nsteps, cur, bar,
+                                               flag, spin_limit, s);
+        case 2: return launch_persist_t<64, 16>(grid, inst, tile_inst, ntiles, nsteps, cur, bar,
+                                                flag, spin_limit, s);
+        case 3: return launch_persist_t<128, 4>(grid, inst, tile_inst, ntiles, nsteps, cur, bar,
+                                                flag, spin_limit, s);
+        default: return launch_persist_t<64, 4>(grid, inst, tile_inst, ntiles, nsteps, cur, bar,
+                                                flag, spin_limit, s);
+    }
+}
+
+int batch_persistent_occupancy(int tile) {
+    switch (tile) {
+        case 1: return occupancy_t<64, 8>();
+        case 2: return occupancy_t<64, 16>();
+        case 3: return occupancy_t<128, 4>();
+        default: return occupancy_t<64, 4>();
+    }
+}
+
+}  // namespace lbm

@@ -245,3 +245,267 @@ __device__ __forceinline__ int xcd_tile(int i, int T) {
 }
 
 }  // namespace lbm
+
+namespace lbm {
+
+// One TX x TY tile of the step at origin (x0, y0), executed by a whole workgroup of TX * TY
+// threads with the LDS array sp of (TY + 2) * (TX + 2) doubles. FUSED: psi of the tile and its
+// halo is evaluated from the pulled populations; otherwise it is staged from psi_g. Contains
+// __syncthreads() and no early return, so it can run inside loops over tiles.
+template <int TX, int TY, bool FUSED>
+__device__ __forceinline__ void step_tile(const KParams& P, const double* __restrict__ gin,
+                                          double* __restrict__ gout,
+                                          const double* __restrict__ psi_g,
+                                          const double* __restrict__ gw, int x0, int y0,
+                                          double* sp) {
+    constexpr int NT = TX * TY;
+    constexpr int LW = TX + 2;
+    constexpr int NH = 2 * LW + 2 * TY;  // halo slots of a (TX+2) x (TY+2) tile
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool active = x < P.nx && y <= P.y_hi;
+
+    double f[9];
+    double rho = 1.0, psi_c = 0.0;
+    if (active) {
+        pull9(P, gin, x, y, f);
+        rho = sum9(f);
+        if (FUSED) psi_c = psi_of_rho(P, rho);
+    }
+    if (FUSED) {
+        // own slot: computed above, or (outside the fluid) the value at that lattice position
+        sp[(ty + 1) * LW + tx + 1] = active ? psi_c : psi_at(P, gin, x, y);
+        for (int h = threadIdx.x; h < NH; h += NT) {
+            int hx, hy;  // tile-local coordinates in [-1, TX] x [-1, TY]
+            if (h < LW) { hx = h - 1; hy = -1; }
+            else if (h < 2 * LW) { hx = h - LW - 1; hy = TY; }
+            else if (h < 2 * LW + TY) { hx = -1; hy = h - 2 * LW; }
+            else { hx = TX; hy = h - 2 * LW - TY; }
+            sp[(hy + 1) * LW + hx + 1] = psi_at(P, gin, x0 + hx, y0 + hy);
+        }
+    } else {
+        // stage psi (ghost rows already mirrored by the psi pass) with its halo
+        for (int s = threadIdx.x; s < (TY + 2) * LW; s += NT) {
+            const int gy = y0 - 1 + s / LW;
+            const int gx = wrapx(x0 - 1 + s % LW, P.nx);
+            double v = 0.0;
+            if (P.walls) {
+                if (gy >= 0 && gy < P.ny) v = psi_g[(long long)gy * P.pitch + gx];
+            } else {
+                v = psi_g[(long long)wrapx(gy, P.ny) * P.pitch + gx];
+            }
+            sp[s] = v;
+        }
+    }
+    __syncthreads();
+    if (active) {
+        if (!FUSED) psi_c = sp[(ty + 1) * LW + tx + 1];
+        const double* c = sp + (ty + 1) * LW + tx + 1;
+        double sx, sy;
+        cohesion_sum(c[-LW - 1], c[-LW], c[-LW + 1], c[-1], c[1], c[LW - 1], c[LW], c[LW + 1],
+                     sx, sy);
+        double Ax = 0.0, Ay = 0.0;
+        if (P.walls && (y == 1 || y == P.ny - 2)) adhesion_sum(P, gw, x, y, Ax, Ay);
+        collide(P, f, rho, psi_c, sx, sy, Ax, Ay);
+        const unsigned i = (unsigned)y * P.pitch + x;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) (gout + a * P.plane)[i] = f[a];
+    }
+}
+
+}  // namespace lbm
+
+// ================================================================================================
+// Adjoint (reverse mode) of the per-node arithmetic
+// ================================================================================================
+namespace lbm {
+
+// dpsi/drho = (p'(rho) - 1/3) / (G psi), from psi^2 = 2 (p - rho/3)/G.
+__device__ __forceinline__ double dpsi_drho(const KParams& P, double rho, double psi) {
+    double dp;
+    if (P.eos == 0) {
+        const double e = P.b4 * rho, om = 1.0 - e;
+        const double om2 = om * om;
+        const double D1 = (1.0 + e * (4.0 + e * (4.0 + e * (-4.0 + e)))) / (om2 * om2);
+        dp = P.RT * D1 - 2.0 * P.a * rho;
+    } else {
+        dp = rho <= P.rho1 ? P.th_v : (rho <= P.rho2 ? P.th_m : P.th_l);
+    }
+    // 2/G * (dp - 1/3) / (2 psi)
+    return 0.5 * P.two_over_G * (dp - 1.0 / 3.0) / psi;
+}
+
+// Reverse mode of collide() at one node. In: the forward inputs (f pre-collision, rho = sum f,
+// psi_c, cohesion sum s, adhesion sum A) and nu = dL/df* (9). Out: fb = dL/df through every path
+// that does not pass through psi (9, including the rho = sum f dependence of v, m_eq, tau_nu and
+// a density pre-sum factor), pb = dL/dpsi_c as the node's own pre-factor, (qx, qy) = dL/ds, and
+// (rx, ry) = dL/dA.
+__device__ __forceinline__ void collide_adj(const KParams& P, const double f[9], double rho,
+                                            double psi_c, double sx, double sy, double Ax,
+                                            double Ay, const double nu[9], double fb[9],
+                                            double& pb, double& qx, double& qy, double& rx,
+                                            double& ry) {
+    // ---- forward recomputation (same expressions as collide) ----
+    const double fmx = P.negG * psi_c * sx, fmy = P.negG * psi_c * sy;
+    const double pre = P.wall_force == 0 ? rho : (P.wall_force == 1 ? psi_c : psi_c * psi_c);
+    const double Fx = fmx - pre * Ax, Fy = fmy - pre * Ay;
+    const double ax = f[1] + f[3], ay = f[2] + f[4];
+    const double d58 = f[5] - f[7], d68 = f[6] - f[8];
+    const double jx = (f[1] - f[3]) + d58 - d68;
+    const double jy = (f[2] - f[4]) + d58 + d68;
+    const double m7 = ax - ay;
+    const double m8 = (f[5] + f[7]) - (f[6] + f[8]);
+    const double ir = 1.0 / rho;
+    const double vx = (jx + 0.5 * Fx) * ir, vy = (jy + 0.5 * Fy) * ir;
+    const double v2 = vx * vx + vy * vy;
+    double snu, dsnu_drho = 0.0;
+    if (P.visc_const) {
+        snu = P.s_nu_c;
+    } else {
+        const double phr = (rho - P.rho_v) * P.inv_drho;
+        const double ph = fmin(fmax(phr, 0.0), 1.0);
+        snu = 1.0 / (3.0 * (P.nu_v + ph * P.dnu) + 0.5);
+        if (phr > 0.0 && phr < 1.0) dsnu_drho = -snu * snu * 3.0 * P.dnu * P.inv_drho;
+    }
+    const double hnu = 1.0 - 0.5 * snu;
+    const double S7 = 2.0 * (vx * Fx - vy * Fy);
+    const double S8 = vx * Fy + vy * Fx;
+
+    // ---- mu = dL/dm* = D (M nu), D = diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) ----
+    const double nax = nu[1] + nu[3], nay = nu[2] + nu[4];
+    const double nsa = nax + nay, nsd = (nu[5] + nu[7]) + (nu[6] + nu[8]);
+    const double n58 = nu[5] - nu[7], n68 = nu[6] - nu[8];
+    const double mu0 = (nu[0] + nsa + nsd) * (1.0 / 9.0);
+    const double mu1 = (-4.0 * nu[0] - nsa + 2.0 * nsd) * (1.0 / 36.0);
+    const double mu2 = (4.0 * nu[0] - 2.0 * nsa + nsd) * (1.0 / 36.0);
+    const double mu3 = ((nu[1] - nu[3]) + n58 - n68) * (1.0 / 6.0);
+    const double mu4 = (-2.0 * (nu[1] - nu[3]) + n58 - n68) * (1.0 / 12.0);
+    const double mu5 = ((nu[2] - nu[4]) + n58 + n68) * (1.0 / 6.0);
+    const double mu6 = (-2.0 * (nu[2] - nu[4]) + n58 + n68) * (1.0 / 12.0);
+    const double mu7 = (nax - nay) * 0.25;
+    const double mu8 = ((nu[5] + nu[7]) - (nu[6] + nu[8])) * 0.25;
+
+    // ---- Eq. (4) relaxation, reversed ----
+    double rb = mu0;  // m*_0 = rho
+    double vxb = 0.0, vyb = 0.0, v2b = 0.0, Fxb = 0.0, Fyb = 0.0;
+    const double m1b = mu1 * (1.0 - P.s_e);
+    rb += mu1 * P.s_e * (-2.0 + 3.0 * v2);
+    v2b += mu1 * P.s_e * rho * 3.0;
+    const double S1b = mu1 * P.h_e;
+    const double m2b = mu2 * (1.0 - P.s_z);
+    rb += mu2 * P.s_z * (1.0 - 3.0 * v2);
+    v2b -= mu2 * P.s_z * rho * 3.0;
+    const double S2b = mu2 * P.h_z;
+    const double jxb = mu3 * (1.0 - P.s_j);
+    rb += mu3 * P.s_j * vx;
+    vxb += mu3 * P.s_j * rho;
+    Fxb += mu3 * P.h_j;
+    const double m4b = mu4 * (1.0 - P.s_q);
+    rb -= mu4 * P.s_q * vx;
+    vxb -= mu4 * P.s_q * rho;
+    Fxb -= mu4 * P.h_q;
+    const double jyb = mu5 * (1.0 - P.s_j);
+    rb += mu5 * P.s_j * vy;
+    vyb += mu5 * P.s_j * rho;
+    Fyb += mu5 * P.h_j;
+    const double m6b = mu6 * (1.0 - P.s_q);
+    rb -= mu6 * P.s_q * vy;
+    vyb -= mu6 * P.s_q * rho;
+    Fyb -= mu6 * P.h_q;
+    const double m7b = mu7 * (1.0 - snu);
+    double snub = mu7 * (-(m7 - rho * (vx * vx - vy * vy)) - 0.5 * S7);
+    rb += mu7 * snu * (vx * vx - vy * vy);
+    vxb += mu7 * snu * rho * 2.0 * vx;
+    vyb -= mu7 * snu * rho * 2.0 * vy;
+    const double S7b = mu7 * hnu;
+    const double m8b = mu8 * (1.0 - snu);
+    snub += mu8 * (-(m8 - rho * vx * vy) - 0.5 * S8);
+    rb += mu8 * snu * vx * vy;
+    vxb += mu8 * snu * rho * vy;
+    vyb += mu8 * snu * rho * vx;
+    const double S8b = mu8 * hnu;
+
+    // ---- Eq. (9) forcing, reversed ----
+    const double vFb = 6.0 * (S1b - S2b);
+    const double s2b = P.c_sig_e * S1b - P.c_sig_z * S2b;
+    vxb += 2.0 * S7b * Fx + S8b * Fy + vFb * Fx;
+    vyb += -2.0 * S7b * Fy + S8b * Fx + vFb * Fy;
+    Fxb += 2.0 * S7b * vx + S8b * vy + vFb * vx;
+    Fyb += -2.0 * S7b * vy + S8b * vx + vFb * vy;
+    double sxb = 2.0 * sx * s2b, syb = 2.0 * sy * s2b;
+
+    // ---- shear rate, |v|^2, velocity (Eq. 6) ----
+    rb += snub * dsnu_drho;
+    vxb += 2.0 * vx * v2b;
+    vyb += 2.0 * vy * v2b;
+    const double jxb2 = jxb + vxb * ir, jyb2 = jyb + vyb * ir;
+    Fxb += 0.5 * vxb * ir;
+    Fyb += 0.5 * vyb * ir;
+    rb -= (vxb * vx + vyb * vy) * ir;
+
+    // ---- forces (Eqs. 7, 10, 11, 14) ----
+    rx = -pre * Fxb;
+    ry = -pre * Fyb;
+    const double preb = -(Fxb * Ax + Fyb * Ay);
+    pb = P.negG * (sx * Fxb + sy * Fyb);
+    if (P.wall_force == 0) rb += preb;
+    else if (P.wall_force == 1) pb += preb;
+    else pb += 2.0 * psi_c * preb;
+    sxb += P.negG * psi_c * Fxb;
+    syb += P.negG * psi_c * Fyb;
+    qx = sxb;
+    qy = syb;
+
+    // ---- m = M f reversed, plus rho = sum f ----
+    // fb_a = sum_k M[k][a] mb_k + rb, with mb = (0, m1b, m2b, jxb2, m4b, jyb2, m6b, m7b, m8b)
+    const double ba = -m1b - 2.0 * m2b, bd = 2.0 * m1b + m2b;
+    const double X = jxb2 + m4b, Y = jyb2 + m6b;
+    fb[0] = rb - 4.0 * m1b + 4.0 * m2b;
+    fb[1] = rb + ba + jxb2 - 2.0 * m4b + m7b;
+    fb[3] = rb + ba - jxb2 + 2.0 * m4b + m7b;
+    fb[2] = rb + ba + jyb2 - 2.0 * m6b - m7b;
+    fb[4] = rb + ba - jyb2 + 2.0 * m6b - m7b;
+    fb[5] = rb + bd + X + Y + m8b;
+    fb[6] = rb + bd - X + Y - m8b;
+    fb[7] = rb + bd - X - Y + m8b;
+    fb[8] = rb + bd + X - Y - m8b;
+}
+
+// nu = dL/dg at fluid node (x, y): the transpose of pull streaming with bounce-back applied to
+// lambda = a + c 1 (a: 9 planes, c: one plane), i.e. g_b(y) feeds f_b(y + e_b), or f_opp(b)(y)
+// when y + e_b is solid.
+__device__ __forceinline__ void push_gather(const KParams& P, const double* __restrict__ a,
+                                            const double* __restrict__ c, int x, int y,
+                                            double nu[9]) {
+    const unsigned nx = P.nx, pitch = P.pitch;
+    const unsigned ux = x;
+    const unsigned xm = ux == 0 ? nx - 1 : ux - 1;
+    const unsigned xp = ux == nx - 1 ? 0 : ux + 1;
+    unsigned ym, yp;
+    bool bot, top;
+    if (P.walls) {
+        ym = y - 1; yp = y + 1;
+        bot = (y == 1); top = (y == P.ny - 2);
+    } else {
+        ym = y == 0 ? P.ny - 1 : y - 1;
+        yp = y == P.ny - 1 ? 0 : y + 1;
+        bot = top = false;
+    }
+    const long long pl = P.plane;
+    const unsigned r0 = (unsigned)y * pitch, rm = ym * pitch, rp = yp * pitch;
+    const unsigned i0 = r0 + ux;
+    const double c0 = c[i0];
+    nu[0] = a[i0] + c0;
+    nu[1] = (a + 1 * pl)[r0 + xp] + c[r0 + xp];
+    nu[3] = (a + 3 * pl)[r0 + xm] + c[r0 + xm];
+    // e_y = +1 populations travel up: reflected at the top wall
+    nu[2] = top ? (a + 4 * pl)[i0] + c0 : (a + 2 * pl)[rp + ux] + c[rp + ux];
+    nu[5] = top ? (a + 7 * pl)[i0] + c0 : (a + 5 * pl)[rp + xp] + c[rp + xp];
+    nu[6] = top ? (a + 8 * pl)[i0] + c0 : (a + 6 * pl)[rp + xm] + c[rp + xm];
+    // e_y = -1 populations travel down: reflected at the bottom wall
+    nu[4] = bot ? (a + 2 * pl)[i0] + c0 : (a + 4 * pl)[rm + ux] + c[rm + ux];
+    nu[7] = bot ? (a + 5 * pl)[i0] + c0 : (a + 7 * pl)[rm + xm] + c[rm + xm];
+    nu[8] = bot ? (a + 6 * pl)[i0] + c0 : (a + 8 * pl)[rm + xp] + c[rm + xp];
+}
+
+}  // namespace lbm

@@ -16,6 +16,16 @@ struct ObsArgs {
 
 enum { OBS_NQ = 15 };
 
+// One instance of an ensemble, as the batch kernels see it (device memory).
+struct InstDesc {
+    KParams P;
+    double* g[2];  // population buffers (post-collision), ping-pong
+    double* gw;    // [2][pitch] G_w
+    int tile0;     // first tile of this instance in the flattened work-list
+    int ntx, nty;  // tiles in x and y
+    int pad;
+};
+
 int n_tiles();
 void tile_shape(int tile, int* tx, int* ty);
 hipError_t launch_step(const KParams& P, int schedule, int tile, const double* gin, double* gout,
@@ -28,5 +38,25 @@ int obs_blocks(const KParams& P);
 hipError_t launch_obs(const KParams& P, const double* gin, const double* rho, const double* psi,
                       const double* gw, const ObsArgs& A, double* part, double* out,
                       hipStream_t s);
+
+// adjoint
+hipError_t launch_adj_step(const KParams& P, const double* gprev, const double* a_in,
+                           const double* c_in, const double* gw, double* a_out, double* qbuf,
+                           double* p0buf, double* dpsibuf, double* rvec, double* c_out,
+                           double* gwgrad, hipStream_t s);
+int loss_blocks(const KParams& P);
+hipError_t launch_loss(const KParams& P, const double* g, double* part, double* out,
+                       hipStream_t s);
+hipError_t launch_loss_seed(const KParams& P, double w_c, double w_w, double yc, double sum_phi,
+                            double* c, hipStream_t s);
+
+// batch
+int batch_tiles(int tile);
+hipError_t launch_batch_step(int tile, const InstDesc* inst, const int* tile_inst, int ntiles,
+                             int cur, hipStream_t s);
+hipError_t launch_batch_persistent(int tile, int grid, const InstDesc* inst,
+                                   const int* tile_inst, int ntiles, int nsteps, int cur,
+                                   unsigned* bar, int* flag, int spin_limit, hipStream_t s);
+int batch_persistent_occupancy(int tile);
 
 }  // namespace lbm

@@ -21,69 +21,12 @@ __global__ __launch_bounds__(TX* TY) void k_step(KParams P, const double* __rest
                                                  double* __restrict__ gout,
                                                  const double* __restrict__ psi_g,
                                                  const double* __restrict__ gw) {
-    constexpr int NT = TX * TY;
-    constexpr int LW = TX + 2;
-    constexpr int NH = 2 * LW + 2 * TY;  // halo slots of a (TX+2) x (TY+2) tile
-    __shared__ double sp[(TY + 2) * LW];
-
+    __shared__ double sp[(TY + 2) * (TX + 2)];
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
     const int tile = xcd_tile(blockIdx.x, ntx * nty);
-    const int x0 = (tile % ntx) * TX;
-    const int y0 = P.y_lo + (tile / ntx) * TY;
-    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-    const int x = x0 + tx, y = y0 + ty;
-    const bool active = x < P.nx && y <= P.y_hi;
-
-    double f[9];
-    double rho = 1.0, psi_c = 0.0;
-    if (active) {
-        pull9(P, gin, x, y, f);
-        rho = sum9(f);
-        if (FUSED) psi_c = psi_of_rho(P, rho);
-    }
-    if (FUSED) {
-        // own slot: computed above, or (outside the fluid) the value at that lattice position
-        sp[(ty + 1) * LW + tx + 1] = active ? psi_c : psi_at(P, gin, x, y);
-        for (int h = threadIdx.x; h < NH; h += NT) {
-            int hx, hy;  // tile-local coordinates in [-1, TX] x [-1, TY]
-            if (h < LW) { hx = h - 1; hy = -1; }
-            else if (h < 2 * LW) { hx = h - LW - 1; hy = TY; }
-            else if (h < 2 * LW + TY) { hx = -1; hy = h - 2 * LW; }
-            else { hx = TX; hy = h - 2 * LW - TY; }
-            sp[(hy + 1) * LW + hx + 1] = psi_at(P, gin, x0 + hx, y0 + hy);
-        }
-    } else {
-        // stage psi (ghost rows already mirrored by the psi pass) with its halo
-        for (int s = threadIdx.x; s < (TY + 2) * LW; s += NT) {
-            const int gy0 = y0 - 1 + s / LW;
-            const int gx = wrapx(x0 - 1 + s % LW, P.nx);
-            int gy = gy0;
-            double v = 0.0;
-            if (P.walls) {
-                if (gy >= 0 && gy < P.ny) v = psi_g[(long long)gy * P.pitch + gx];
-            } else {
-                gy = wrapx(gy, P.ny);
-                v = psi_g[(long long)gy * P.pitch + gx];
-            }
-            sp[s] = v;
-        }
-    }
-    __syncthreads();
-    if (!active) return;
-    if (!FUSED) psi_c = sp[(ty + 1) * LW + tx + 1];
-
-    const double* c = sp + (ty + 1) * LW + tx + 1;
-    double sx, sy;
-    cohesion_sum(c[-LW - 1], c[-LW], c[-LW + 1], c[-1], c[1], c[LW - 1], c[LW], c[LW + 1], sx,
-                 sy);
-    double Ax = 0.0, Ay = 0.0;
-    if (P.walls && (y == 1 || y == P.ny - 2)) adhesion_sum(P, gw, x, y, Ax, Ay);
-    collide(P, f, rho, psi_c, sx, sy, Ax, Ay);
-
-    const unsigned i = (unsigned)y * P.pitch + x;
-#pragma unroll
-    for (int a = 0; a < 9; ++a) (gout + a * P.plane)[i] = f[a];
+    step_tile<TX, TY, FUSED>(P, gin, gout, psi_g, gw, (tile % ntx) * TX,
+                             P.y_lo + (tile / ntx) * TY, sp);
 }
 
 // Overlapped tiles: one 64-lane wave spans TXI = 62 interior columns plus the halo column on each

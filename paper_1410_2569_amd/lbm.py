@@ -42,6 +42,14 @@ class Params(C.Structure):
                 ("rho_l", C.c_double), ("rho_v", C.c_double)]
 
 
+class Tune(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("reserved", C.c_int32), ("waves_per_cu", C.c_int32),
+                ("schedule", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {"tile": self.tile, "waves_per_cu": self.waves_per_cu, "schedule": self.schedule}
+
+
 class Obs(C.Structure):
     _fields_ = [("step", C.c_int64), ("rho_min", C.c_double), ("rho_max", C.c_double),
                 ("umax", C.c_double), ("umax_liquid", C.c_double), ("mass", C.c_double),
@@ -72,6 +80,24 @@ SIGNATURES = {
     "lbm_set_gw": (C.c_int, [C.c_void_p, _dp]),
     "lbm_set_schedule": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_current_step": (C.c_int64, [C.c_void_p]),
+    "lbm_adjoint_workspace_size": (C.c_int, [_P, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]),
+    "lbm_forward_ckpt": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_size_t]),
+    "lbm_loss": (C.c_int, [C.c_void_p, C.c_double, C.c_double, _dp]),
+    "lbm_backward": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_size_t,
+                               C.c_double, C.c_double, C.c_void_p]),
+    "lbm_batch_workspace_size": (C.c_int, [_P, C.c_int32, C.c_void_p, C.POINTER(C.c_size_t)]),
+    "lbm_batch_create": (C.c_int, [_P, C.c_int32, C.POINTER(_dp), C.POINTER(_dp), C.c_void_p,
+                                   C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "lbm_batch_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "lbm_batch_observables": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lbm_batch_read_f": (C.c_int, [C.c_void_p, C.c_int32, _dp, C.c_size_t]),
+    "lbm_batch_current_step": (C.c_int64, [C.c_void_p]),
+    "lbm_batch_get_tune": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
+    "lbm_batch_destroy": (C.c_int, [C.c_void_p]),
+    "lbm_batch_last_error": (C.c_char_p, [C.c_void_p]),
+    "lbm_autotune": (C.c_int, [_P, C.c_int32, C.POINTER(_dp), C.POINTER(_dp), C.c_void_p,
+                               C.c_size_t, C.c_void_p, C.c_int32, C.c_void_p,
+                               C.POINTER(C.c_double)]),
     "lbm_destroy": (C.c_int, [C.c_void_p]),
     "lbm_strerror": (C.c_char_p, [C.c_int]),
     "lbm_last_error": (C.c_char_p, [C.c_void_p]),
@@ -227,3 +253,128 @@ class Sim:
         g = np.ascontiguousarray(gw, dtype=np.float64)
         assert g.shape == (2, self.nx)
         self._chk(lib().lbm_set_gw(self.h, _dptr(g)))
+
+    # ---- adjoint -----------------------------------------------------------------------------
+    def adjoint_workspace(self, nsteps: int, K: int):
+        """A device workspace (torch uint8 tensor) for lbm_forward_ckpt / lbm_backward."""
+        import torch
+        n = C.c_size_t()
+        check(lib().lbm_adjoint_workspace_size(C.byref(self.q), int(nsteps), int(K), C.byref(n)))
+        return torch.empty(n.value, dtype=torch.uint8, device=self.ws.device)
+
+    def forward_ckpt(self, nsteps: int, K: int, ws):
+        self._chk(lib().lbm_forward_ckpt(self.h, int(nsteps), int(K), C.c_void_p(ws.data_ptr()),
+                                         ws.numel()))
+
+    def loss(self, w_centroid: float = 1.0, w_wet: float = 1.0) -> float:
+        L = C.c_double()
+        self._chk(lib().lbm_loss(self.h, w_centroid, w_wet, C.byref(L)))
+        return L.value
+
+    def backward(self, nsteps: int, K: int, ws, w_centroid: float = 1.0, w_wet: float = 1.0):
+        """dL/dG_w as a (2, nx) float64 device tensor (row 0 bottom wall, row 1 top wall)."""
+        import torch
+        g = torch.empty((2, self.nx), dtype=torch.float64, device=self.ws.device)
+        self._chk(lib().lbm_backward(self.h, int(nsteps), int(K), C.c_void_p(ws.data_ptr()),
+                                     ws.numel(), w_centroid, w_wet, C.c_void_p(g.data_ptr())))
+        return g
+
+
+class Batch:
+    """An ensemble of uneven lattices advanced together by the batch kernels."""
+
+    def __init__(self, params_list, gw_list, rho0_list, tune=None, device="cuda", stream=None):
+        import torch
+
+        self.n = len(params_list)
+        arr = (Params * self.n)()
+        for i, pr in enumerate(params_list):
+            arr[i] = pr if isinstance(pr, Params) else make_params(pr)
+        self.params = arr
+        self._gw = [np.ascontiguousarray(g if g is not None else np.zeros((2, arr[i].nx)),
+                                         dtype=np.float64) for i, g in enumerate(gw_list)]
+        self._rho = [np.ascontiguousarray(r, dtype=np.float64) for r in rho0_list]
+        for i in range(self.n):
+            assert self._gw[i].shape == (2, arr[i].nx)
+            assert self._rho[i].shape == (arr[i].ny, arr[i].nx)
+        gwp = (_dp * self.n)(*[_dptr(g) for g in self._gw])
+        rp = (_dp * self.n)(*[_dptr(r) for r in self._rho])
+        t = None
+        if tune is not None:
+            t = tune if isinstance(tune, Tune) else Tune(int(tune.get("tile", 1)), 0,
+                                                          int(tune.get("waves_per_cu", 0)),
+                                                          int(tune.get("schedule", 0)))
+        tp = C.byref(t) if t is not None else None
+        nbytes = C.c_size_t()
+        check(lib().lbm_batch_workspace_size(arr, self.n, tp, C.byref(nbytes)))
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
+        h = C.c_void_p()
+        rc = lib().lbm_batch_create(arr, self.n, gwp, rp, tp, C.c_void_p(self.ws.data_ptr()),
+                                    nbytes.value, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        check(rc)
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().lbm_batch_destroy(h)
+            self.h = None
+
+    def _chk(self, rc):
+        if rc != OK:
+            msg = lib().lbm_strerror(rc).decode()
+            extra = lib().lbm_batch_last_error(self.h)
+            raise LBMError(rc, msg + (": " + extra.decode() if extra else ""))
+
+    def step(self, n: int = 1):
+        self._chk(lib().lbm_batch_step(self.h, int(n)))
+
+    @property
+    def current_step(self) -> int:
+        return lib().lbm_batch_current_step(self.h)
+
+    def tune(self):
+        t, g = Tune(), C.c_int32()
+        self._chk(lib().lbm_batch_get_tune(self.h, C.byref(t), C.byref(g)))
+        return dict(t.as_dict(), grid=g.value)
+
+    def observables(self, allow_nonfinite=False) -> list:
+        out = (Obs * self.n)()
+        rc = lib().lbm_batch_observables(self.h, out)
+        if not (rc == E_NONFINITE and allow_nonfinite):
+            self._chk(rc)
+        return [o.as_dict() for o in out]
+
+    def f(self, index: int) -> np.ndarray:
+        q = self.params[index]
+        out = np.empty((9, q.ny, q.nx))
+        self._chk(lib().lbm_batch_read_f(self.h, int(index), _dptr(out), out.size))
+        return out
+
+
+def autotune(params_list, gw_list, rho0_list, steps=200, device="cuda"):
+    """Fastest lbm_tune for this ensemble (every tile shape x schedule timed on the device)."""
+    import torch
+
+    n = len(params_list)
+    arr = (Params * n)()
+    for i, pr in enumerate(params_list):
+        arr[i] = pr if isinstance(pr, Params) else make_params(pr)
+    gws = [np.ascontiguousarray(g, dtype=np.float64) for g in gw_list]
+    rhos = [np.ascontiguousarray(r, dtype=np.float64) for r in rho0_list]
+    gwp = (_dp * n)(*[_dptr(g) for g in gws])
+    rp = (_dp * n)(*[_dptr(r) for r in rhos])
+    need = 0
+    for tile in range(4):
+        b = C.c_size_t()
+        t = Tune(tile, 0, 0, 0)
+        check(lib().lbm_batch_workspace_size(arr, n, C.byref(t), C.byref(b)))
+        need = max(need, b.value)
+    ws = torch.empty(need, dtype=torch.uint8, device=device)
+    best, ms = Tune(), C.c_double()
+    stream = torch.cuda.current_stream(ws.device)
+    check(lib().lbm_autotune(arr, n, gwp, rp, C.c_void_p(ws.data_ptr()), need,
+                             C.c_void_p(stream.cuda_stream), int(steps), C.byref(best),
+                             C.byref(ms)))
+    return dict(best.as_dict(), ms=ms.value, steps=steps)

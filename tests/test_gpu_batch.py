@@ -1,0 +1,98 @@
+"""Ensembles of uneven lattices (batch kernels, per-step graph and persistent schedules).
+
+Every instance of a batch must evolve bit-for-bit as the same lattice stepped alone by lbm_step
+(both run the same per-tile arithmetic), for every tile shape and schedule; a stale read across
+the persistent grid barrier or a wrong tile-to-instance mapping breaks that equality.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def ensemble(orc, n=5, seed=11):
+    d = synth.Draws(seed)
+    cases = []
+    for i in range(n):
+        nx = d.choice([37, 64, 96, 130, 200])
+        ny = d.choice([12, 24, 41, 64])
+        form = synth.FORMS[i % 3]
+        tau_v = (1.1, 2.0, 0.6)[i % 3]
+        p = synth.base_params(nx=nx, ny=ny, wall_force=form, tau_v=tau_v)
+        q = orc.make_params(p)
+        r = max(3.0, min(nx, ny) * d.uniform(0.25, 0.4))
+        rho0 = synth.droplet_rho(nx, ny, q.rho_l, q.rho_v, [(nx / 2, 0.5)], [r], seed=seed + i)
+        g = synth.gw_smooth(nx, {"rho": 0.05, "psi": -0.02, "modpsi": 0.1}[form], 0.02, seed=i)
+        cases.append((dict(p, rho_l=q.rho_l, rho_v=q.rho_v), g, rho0, q))
+    return cases
+
+
+def plain_states(gpu, cases, steps):
+    out = []
+    for p, g, r, _ in cases:
+        s = gpu.Sim(p, g, r)
+        s.set_schedule(16 + 1)  # tile 64x8 (any tile gives the same bits)
+        s.step(steps)
+        out.append(s.f())
+    return out
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+def test_batch_bitwise_equals_plain(orc, gpu, tile, schedule):
+    cases = ensemble(orc)
+    steps = 131  # more than one captured graph chunk, odd
+    ref = plain_states(gpu, cases, steps)
+    b = gpu.Batch([c[0] for c in cases], [c[1] for c in cases], [c[2] for c in cases],
+                  tune={"tile": tile, "schedule": schedule})
+    b.step(60)
+    b.step(71)
+    assert b.current_step == steps
+    for i in range(len(cases)):
+        assert np.array_equal(b.f(i), ref[i]), f"instance {i} differs (tile {tile}, sched {schedule})"
+    obs = b.observables()
+    for i, (p, g, r, q) in enumerate(cases):
+        s = gpu.Sim(p, g, r)
+        s.step(steps)
+        o = s.observables()
+        assert o["rho_min"] == obs[i]["rho_min"] and o["mass"] == obs[i]["mass"]
+        assert o["n_fit"] == obs[i]["n_fit"]
+
+
+def test_batch_matches_oracle(orc, gpu):
+    cases = ensemble(orc, n=3, seed=5)
+    steps = 200
+    b = gpu.Batch([c[0] for c in cases], [c[1] for c in cases], [c[2] for c in cases],
+                  tune={"tile": 1, "schedule": 1})
+    b.step(steps)
+    for i, (p, g, r, q) in enumerate(cases):
+        f = orc.run(q, g, orc.init_rest(q, r), steps)
+        fl = orc.fluid_mask(q)
+        rel = (np.abs(b.f(i) - f).max(0)[fl] / f.sum(0)[fl]).max()
+        assert rel <= 1e-9, (i, rel)
+
+
+def test_persistent_repeated_and_single_steps(orc, gpu):
+    cases = ensemble(orc, n=4, seed=9)
+    ref = plain_states(gpu, cases, 10)
+    b = gpu.Batch([c[0] for c in cases], [c[1] for c in cases], [c[2] for c in cases],
+                  tune={"tile": 0, "schedule": 1})
+    for n in (1, 1, 3, 3, 2):  # reused and rebuilt graphs, both parities
+        b.step(n)
+    for i in range(len(cases)):
+        assert np.array_equal(b.f(i), ref[i])
+
+
+def test_autotune_picks_a_valid_schedule(orc, gpu):
+    cases = ensemble(orc, n=6, seed=3)
+    best = gpu.autotune([c[0] for c in cases], [c[1] for c in cases], [c[2] for c in cases],
+                        steps=20)
+    print("autotune:", best)
+    assert best["tile"] in (0, 1, 2, 3) and best["schedule"] in (0, 1) and best["ms"] > 0
+    b = gpu.Batch([c[0] for c in cases], [c[1] for c in cases], [c[2] for c in cases], tune=best)
+    b.step(7)
+    ref = plain_states(gpu, cases, 7)
+    for i in range(len(cases)):
+        assert np.array_equal(b.f(i), ref[i])
