@@ -81,13 +81,15 @@ def cpu_baseline(budget_s: float = 12.0) -> dict:
                       f"{dt:.1f} s"}
 
 
-def _timed(fn):
+def _timed(fn, stream=None):
+    """Seconds of device time of fn(), with HIP events on the stream its work is launched on."""
     import torch
     torch.cuda.synchronize()
+    st = stream if stream is not None else torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    e0.record(st)
     fn()
-    e1.record()
+    e1.record(st)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / 1e3
 
@@ -115,7 +117,7 @@ def batched_speedup(args) -> dict:
     log(f"bench: ensemble of {len(prm)} ({fluid} fluid nodes), tune {best}")
     b = L.Batch(prm, gws, rhos, tune=best)
     b.step(2)  # warm-up; the timed call captures its graph once (well under a millisecond)
-    t_batch = _timed(lambda: b.step(n))
+    t_batch = _timed(lambda: b.step(n), b.stream)
     obs = b.observables(allow_nonfinite=True)
     sims = [L.Sim(p, g, r) for p, g, r in zip(prm, gws, rhos)]
     for s in sims:

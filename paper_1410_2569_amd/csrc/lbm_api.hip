@@ -328,6 +328,7 @@ int lbm_create(const lbm_params* p, const double* gw_host, const double* rho0_ho
     if (ws_bytes < L.total) return LBM_E_SIZE;
     if (((uintptr_t)d_ws) % kAlign) return LBM_E_INVAL;
 
+    (void)hipGetLastError();  // report only errors of this call
     lbm_ctx* c = new lbm_ctx();
     c->p = *p;
     c->kp = kparams_of(p, L);
@@ -381,6 +382,7 @@ int lbm_set_schedule(lbm_ctx* c, int32_t schedule) {
 
 int lbm_step(lbm_ctx* c, int64_t n) {
     if (!c || n < 0) return LBM_E_INVAL;
+    (void)hipGetLastError();  // report only errors of this call
     for (int64_t i = 0; i < n; ++i) {
         hipError_t e = lbm::launch_step(c->kp, c->schedule, c->tile, c->g[c->cur],
                                         c->g[c->cur ^ 1], c->psi, c->gw, c->stream);
@@ -438,6 +440,7 @@ static void obs_from_sums(const double* q, const lbm::ObsArgs& A, int64_t step, 
 
 int lbm_observables_window(lbm_ctx* c, double x_lo, double x_hi, lbm_obs* out) {
     if (!c || !out) return LBM_E_INVAL;
+    (void)hipGetLastError();  // report only errors of this call
     const KParams& P = c->kp;
     lbm::ObsArgs A;
     A.rho_mid = 0.5 * (c->p.rho_l + c->p.rho_v);
@@ -625,6 +628,7 @@ int lbm_backward(lbm_ctx* c, int64_t nsteps, int32_t K, void* d_adj, size_t byte
     hipStream_t s = c->stream;
     char* w = (char*)d_adj;
     const size_t fb = (size_t)9 * P.plane * sizeof(double);
+    (void)hipGetLastError();  // report only errors of this call
     hipError_t e = hipMemsetAsync(w + A.off_a, 0, A.total - A.off_a, s);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint clear");
 
@@ -785,6 +789,7 @@ int lbm_batch_create(const lbm_params* p, int32_t count, const double* const* gw
     if (bytes < B.total) return LBM_E_SIZE;
     if (((uintptr_t)d_ws) % kAlign) return LBM_E_INVAL;
 
+    (void)hipGetLastError();  // report only errors of this call
     lbm_batch* b = new lbm_batch();
     b->count = count;
     b->p.assign(p, p + count);
@@ -871,10 +876,17 @@ static int batch_direct(lbm_batch* b, int64_t n) {
     return LBM_OK;
 }
 
+// Captures `body` into an executable graph. The legacy default stream cannot be captured: there
+// the caller launches directly (returns 1).
 static int capture(lbm_batch* b, hipGraphExec_t* out, const std::function<hipError_t()>& body) {
+    if (b->stream == nullptr) return 1;
     hipGraph_t g = nullptr;
+    (void)hipGetLastError();
     hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "begin capture");
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
     hipError_t e1 = body();
     e = hipStreamEndCapture(b->stream, &g);
     if (e1 != hipSuccess || e != hipSuccess) {
@@ -883,28 +895,35 @@ static int capture(lbm_batch* b, hipGraphExec_t* out, const std::function<hipErr
     }
     e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "graph instantiate");
+    if (e != hipSuccess) {
+        *out = nullptr;
+        (void)hipGetLastError();
+        return 1;
+    }
     return LBM_OK;
 }
 
 int lbm_batch_step(lbm_batch* b, int64_t n) {
     if (!b || n < 0) return LBM_E_INVAL;
     if (n == 0) return LBM_OK;
+    (void)hipGetLastError();
     if (b->tune.schedule == 1) {
-        if (!b->pgraph || b->pgraph_n != n || b->pgraph_cur != b->cur) {
+        if (n > (int64_t)1 << 30) return batch_fail(b, LBM_E_INVAL, "too many steps in one call");
+        const int cur = b->cur;
+        auto persistent = [&]() {
+            return lbm::launch_batch_persistent(b->tune.tile, b->grid, b->d_inst, b->d_tile_inst,
+                                                b->ntiles, (int)n, cur, b->d_bar, b->d_flag,
+                                                kSpinLimit, b->stream);
+        };
+        if (!b->pgraph || b->pgraph_n != n || b->pgraph_cur != cur) {
             if (b->pgraph) { (void)hipGraphExecDestroy(b->pgraph); b->pgraph = nullptr; }
-            const int cur = b->cur;
-            int rc = capture(b, &b->pgraph, [&]() {
-                return lbm::launch_batch_persistent(b->tune.tile, b->grid, b->d_inst,
-                                                    b->d_tile_inst, b->ntiles, (int)n, cur,
-                                                    b->d_bar, b->d_flag, kSpinLimit, b->stream);
-            });
-            if (rc) return rc;
-            b->pgraph_n = n;
-            b->pgraph_cur = cur;
+            if (capture(b, &b->pgraph, persistent) == LBM_OK) {
+                b->pgraph_n = n;
+                b->pgraph_cur = cur;
+            }
         }
-        hipError_t e = hipGraphLaunch(b->pgraph, b->stream);
-        if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "graph launch");
+        hipError_t e = b->pgraph ? hipGraphLaunch(b->pgraph, b->stream) : persistent();
+        if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "persistent launch");
         b->cur ^= (int)(n & 1);
         b->step += n;
         return LBM_OK;
@@ -923,7 +942,7 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
                 }
                 return hipSuccess;
             });
-            if (rc) return rc;
+            if (rc != LBM_OK) return batch_direct(b, n - k * kGraphChunk);  // no graph here
         }
         hipError_t e = hipGraphLaunch(b->graph[cur], b->stream);
         if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "graph launch");

@@ -35,17 +35,23 @@ __device__ __forceinline__ int wrapx(int x, int nx) {
     return r < 0 ? r + nx : r;
 }
 
+// Floating-point contraction is switched off inside the per-node arithmetic and the multiply-adds
+// are written as explicit fma(): the rounding of every result is then fixed by the source alone,
+// so every kernel that inlines these functions (plain step, every tile shape, ensembles,
+// persistent loop, adjoint recomputation) produces the same bits.
+
 // p_EOS(rho) and psi(rho); a negative radicand yields NaN, caught by the observables.
 __device__ __forceinline__ double psi_of_rho(const KParams& P, double rho) {
+#pragma clang fp contract(off)
     double p;
     if (P.eos == 0) {
-        double eta = P.b4 * rho;
-        double om = 1.0 - eta;
-        double num = 1.0 + eta * (1.0 + eta * (1.0 - eta));
-        p = rho * P.RT * num / (om * om * om) - P.a * rho * rho;
+        const double eta = P.b4 * rho;
+        const double om = 1.0 - eta;
+        const double num = fma(eta, fma(eta, om, 1.0), 1.0);  // 1 + eta + eta^2 - eta^3
+        p = fma(-P.a * rho, rho, (rho * P.RT) * num / (om * om * om));
     } else {
         p = rho <= P.rho1 ? rho * P.th_v
-          : (rho <= P.rho2 ? P.p1 + (rho - P.rho1) * P.th_m : P.p2 + (rho - P.rho2) * P.th_l);
+          : (rho <= P.rho2 ? fma(rho - P.rho1, P.th_m, P.p1) : fma(rho - P.rho2, P.th_l, P.p2));
     }
     return sqrt(P.two_over_G * (p - rho * (1.0 / 3.0)));
 }
@@ -103,6 +109,7 @@ __device__ __forceinline__ bool slot_source(const KParams& P, int gx, int gy, in
 // psi at lattice position (gx, gy) (see slot_source), evaluated from the pulled populations.
 __device__ __forceinline__ double psi_at(const KParams& P, const double* __restrict__ g, int gx,
                                          int gy) {
+#pragma clang fp contract(off)
     int sx, sy;
     if (!slot_source(P, gx, gy, sx, sy)) return 0.0;
     double f[9];
@@ -111,6 +118,7 @@ __device__ __forceinline__ double psi_at(const KParams& P, const double* __restr
 }
 
 __device__ __forceinline__ double sum9(const double f[9]) {
+#pragma clang fp contract(off)
     return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
 }
 
@@ -118,6 +126,7 @@ __device__ __forceinline__ double sum9(const double f[9]) {
 // node next to a flat wall; F_ads = -P A with P = rho, psi or psi^2 (Eqs. 10, 11, 14).
 __device__ __forceinline__ void adhesion_sum(const KParams& P, const double* __restrict__ gw,
                                              int x, int y, double& Ax, double& Ay) {
+#pragma clang fp contract(off)
     Ax = 0.0; Ay = 0.0;
     if (!P.walls) return;
     const int xm = x == 0 ? P.nx - 1 : x - 1;
@@ -125,13 +134,13 @@ __device__ __forceinline__ void adhesion_sum(const KParams& P, const double* __r
     if (y == 1) {  // bottom wall below: e4 (0,-1) w 1/9, e7 (-1,-1) and e8 (1,-1) w 1/36
         const double gc = gw[x], gm = gw[xm], gp = gw[xp];
         Ax += (gp - gm) * (1.0 / 36.0);
-        Ay -= gc * (1.0 / 9.0) + (gm + gp) * (1.0 / 36.0);
+        Ay -= fma(gc, 1.0 / 9.0, (gm + gp) * (1.0 / 36.0));
     }
     if (y == P.ny - 2) {  // top wall above: e2 (0,1), e5 (1,1), e6 (-1,1)
         const double* gt = gw + P.pitch;  // rows of the G_w array are pitch apart
         const double gc = gt[x], gm = gt[xm], gp = gt[xp];
         Ax += (gp - gm) * (1.0 / 36.0);
-        Ay += gc * (1.0 / 9.0) + (gm + gp) * (1.0 / 36.0);
+        Ay += fma(gc, 1.0 / 9.0, (gm + gp) * (1.0 / 36.0));
     }
 }
 
@@ -140,10 +149,11 @@ __device__ __forceinline__ void adhesion_sum(const KParams& P, const double* __r
 __device__ __forceinline__ void cohesion_sum(double pmm, double p0m, double ppm, double pm0,
                                              double pp0, double pmp, double p0p, double ppp,
                                              double& sx, double& sy) {
+#pragma clang fp contract(off)
     // axial w = 1/3, diagonal w = 1/12 (Eq. 7)
     const double dpx = ppp - pmm, dmx = ppm - pmp;  // (+1,+1)-(-1,-1), (+1,-1)-(-1,+1)
-    sx = (pp0 - pm0) * (1.0 / 3.0) + (dpx + dmx) * (1.0 / 12.0);
-    sy = (p0p - p0m) * (1.0 / 3.0) + (dpx - dmx) * (1.0 / 12.0);
+    sx = fma(pp0 - pm0, 1.0 / 3.0, (dpx + dmx) * (1.0 / 12.0));
+    sy = fma(p0p - p0m, 1.0 / 3.0, (dpx - dmx) * (1.0 / 12.0));
 }
 
 // Forces, velocity and MRT collision of one node (Eqs. 2-4, 6, 7, 9 and 10/11/14):
@@ -151,10 +161,11 @@ __device__ __forceinline__ void cohesion_sum(double pmm, double p0m, double ppm,
 // out f[9] overwritten with f* = M^-1 m*.
 __device__ __forceinline__ void collide(const KParams& P, double f[9], double rho, double psi_c,
                                         double sx, double sy, double Ax, double Ay) {
+#pragma clang fp contract(off)
     // Eq. (7): F_m = -G psi(x) s;  adhesion pre-sum factor
     const double fmx = P.negG * psi_c * sx, fmy = P.negG * psi_c * sy;
     const double pre = P.wall_force == 0 ? rho : (P.wall_force == 1 ? psi_c : psi_c * psi_c);
-    const double Fx = fmx - pre * Ax, Fy = fmy - pre * Ay;
+    const double Fx = fma(-pre, Ax, fmx), Fy = fma(-pre, Ay, fmy);
 
     // moments m = M f (rows rho, e, epsilon, jx, qx, jy, qy, pxx, pxy)
     const double ax = f[1] + f[3], ay = f[2] + f[4];
@@ -173,7 +184,7 @@ __device__ __forceinline__ void collide(const KParams& P, double f[9], double rh
     // Eq. (6): velocity with half the force
     const double ir = 1.0 / rho;
     const double vx = (jx + 0.5 * Fx) * ir, vy = (jy + 0.5 * Fy) * ir;
-    const double v2 = vx * vx + vy * vy;
+    const double v2 = fma(vx, vx, vy * vy);
 
     // shear relaxation rate from the phase-interpolated viscosity
     double snu;
@@ -182,27 +193,27 @@ __device__ __forceinline__ void collide(const KParams& P, double f[9], double rh
     } else {
         double phi = (rho - P.rho_v) * P.inv_drho;
         phi = fmin(fmax(phi, 0.0), 1.0);
-        snu = 1.0 / (3.0 * (P.nu_v + phi * P.dnu) + 0.5);
+        snu = 1.0 / fma(3.0, fma(phi, P.dnu, P.nu_v), 0.5);
     }
     const double hnu = 1.0 - 0.5 * snu;
 
     // Eq. (9) forcing; |F_m|^2 / psi^2 = G^2 |s|^2
-    const double vF = vx * Fx + vy * Fy;
-    const double s2 = sx * sx + sy * sy;
-    const double S1 = 6.0 * vF + P.c_sig_e * s2;
-    const double S2 = -6.0 * vF - P.c_sig_z * s2;
-    const double S7 = 2.0 * (vx * Fx - vy * Fy);
-    const double S8 = vx * Fy + vy * Fx;
+    const double vF = fma(vx, Fx, vy * Fy);
+    const double s2 = fma(sx, sx, sy * sy);
+    const double S1 = fma(P.c_sig_e, s2, 6.0 * vF);
+    const double S2 = fma(-P.c_sig_z, s2, -6.0 * vF);
+    const double S7 = 2.0 * fma(vx, Fx, -(vy * Fy));
+    const double S8 = fma(vx, Fy, vy * Fx);
 
     // Eq. (4) with Eq. (3) equilibria; m*_0 = rho
-    const double ms1 = m1 - P.s_e * (m1 - rho * (-2.0 + 3.0 * v2)) + P.h_e * S1;
-    const double ms2 = m2 - P.s_z * (m2 - rho * (1.0 - 3.0 * v2)) + P.h_z * S2;
-    const double ms3 = jx - P.s_j * (jx - rho * vx) + P.h_j * Fx;
-    const double ms4 = m4 - P.s_q * (m4 + rho * vx) - P.h_q * Fx;
-    const double ms5 = jy - P.s_j * (jy - rho * vy) + P.h_j * Fy;
-    const double ms6 = m6 - P.s_q * (m6 + rho * vy) - P.h_q * Fy;
-    const double ms7 = m7 - snu * (m7 - rho * (vx * vx - vy * vy)) + hnu * S7;
-    const double ms8 = m8 - snu * (m8 - rho * vx * vy) + hnu * S8;
+    const double ms1 = fma(P.h_e, S1, fma(-P.s_e, m1 - rho * fma(3.0, v2, -2.0), m1));
+    const double ms2 = fma(P.h_z, S2, fma(-P.s_z, m2 - rho * fma(-3.0, v2, 1.0), m2));
+    const double ms3 = fma(P.h_j, Fx, fma(-P.s_j, fma(-rho, vx, jx), jx));
+    const double ms4 = fma(-P.h_q, Fx, fma(-P.s_q, fma(rho, vx, m4), m4));
+    const double ms5 = fma(P.h_j, Fy, fma(-P.s_j, fma(-rho, vy, jy), jy));
+    const double ms6 = fma(-P.h_q, Fy, fma(-P.s_q, fma(rho, vy, m6), m6));
+    const double ms7 = fma(hnu, S7, fma(-snu, fma(-rho, fma(vx, vx, -(vy * vy)), m7), m7));
+    const double ms8 = fma(hnu, S8, fma(-snu, fma(-rho, vx * vy, m8), m8));
 
     // f* = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m*
     const double a0 = rho * (1.0 / 9.0), a1 = ms1 * (1.0 / 36.0), a2 = ms2 * (1.0 / 36.0);
@@ -226,8 +237,9 @@ __device__ __forceinline__ void collide(const KParams& P, double f[9], double rh
 __device__ __forceinline__ void velocity(const KParams& P, const double f[9], double rho,
                                          double psi_c, double sx, double sy, double Ax,
                                          double Ay, double& vx, double& vy) {
+#pragma clang fp contract(off)
     const double pre = P.wall_force == 0 ? rho : (P.wall_force == 1 ? psi_c : psi_c * psi_c);
-    const double Fx = P.negG * psi_c * sx - pre * Ax, Fy = P.negG * psi_c * sy - pre * Ay;
+    const double Fx = fma(-pre, Ax, P.negG * psi_c * sx), Fy = fma(-pre, Ay, P.negG * psi_c * sy);
     const double d58 = f[5] - f[7], d68 = f[6] - f[8];
     const double jx = (f[1] - f[3]) + d58 - d68;
     const double jy = (f[2] - f[4]) + d58 + d68;

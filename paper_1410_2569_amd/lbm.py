@@ -308,7 +308,10 @@ class Batch:
         nbytes = C.c_size_t()
         check(lib().lbm_batch_workspace_size(arr, self.n, tp, C.byref(nbytes)))
         self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
+        # a stream of its own (default priority): the legacy default stream cannot be captured
+        # into the hipGraphs the ensemble replays
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.ws.device)
+        torch.cuda.current_stream(self.ws.device).synchronize()
         h = C.c_void_p()
         rc = lib().lbm_batch_create(arr, self.n, gwp, rp, tp, C.c_void_p(self.ws.data_ptr()),
                                     nbytes.value, C.c_void_p(self.stream.cuda_stream), C.byref(h))
@@ -373,7 +376,8 @@ def autotune(params_list, gw_list, rho0_list, steps=200, device="cuda"):
         need = max(need, b.value)
     ws = torch.empty(need, dtype=torch.uint8, device=device)
     best, ms = Tune(), C.c_double()
-    stream = torch.cuda.current_stream(ws.device)
+    stream = torch.cuda.Stream(ws.device)  # capturable (see Batch)
+    torch.cuda.current_stream(ws.device).synchronize()
     check(lib().lbm_autotune(arr, n, gwp, rp, C.c_void_p(ws.data_ptr()), need,
                              C.c_void_p(stream.cuda_stream), int(steps), C.byref(best),
                              C.byref(ms)))

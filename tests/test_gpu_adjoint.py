@@ -99,6 +99,7 @@ def test_autograd_function(orc, gpu):
     gw = torch.tensor(gw0, dtype=torch.float64, device="cuda", requires_grad=True)
     L = lbm_run(gw, sim, state0, 120, 40)
     L.backward()
+    sim.load_state(state0)
     L2, g2 = gpu_grad(sim, 120, 40)
     assert abs(float(L) - L2) <= 1e-12 * abs(L2)
     assert np.array_equal(gw.grad.cpu().numpy(), g2)
