@@ -6,8 +6,10 @@ on a uniform grid (run order seeded) -- every run advanced by --steps time steps
 default, the full sweep). A "step" of this benchmark is one LB time step of all 24 runs.
 
 value: million fluid lattice updates per second (MLUPS) over the timed region, whole job.
-roofline: the dominant kernel (the fused step kernel) against HBM bandwidth, with algorithmic
-bytes = 144 B per lattice update (9 FP64 populations read + 9 written).
+roofline: the dominant kernel (by default the kernel that advances two time steps per launch)
+against HBM bandwidth, with algorithmic bytes = 144 B per lattice update (9 FP64 populations
+read + 9 written, the floor of a scheme that sweeps the state once per step) times the lattice
+updates of one launch; `traffic` gives the bytes the counters measured per launch.
 cpu_baseline: the FP64 CPU oracle on a bounded slice of the same workload.
 """
 from __future__ import annotations
@@ -202,13 +204,105 @@ def adjoint_speedup(args) -> dict:
             "workload": "256x128, R=40, modified form, smooth G_w, 4,000 steps, K=200"}
 
 
+def c5_run(args) -> dict:
+    """8 x 2048x1024 lattices, six droplets each on a striped wall (G_w -0.1 / +0.2, width 64),
+    modified form. Forward: the ensemble with the autotuned schedule (graph-replayed launches or
+    one persistent launch). Adjoint: for every instance,
+    dL/dG_w over the last `c5_adj_steps` steps (checkpoint every K) from its exported state;
+    finite differences on 16 seeded nodes of instance 0."""
+    import numpy as np
+    import torch
+
+    import paper_1410_2569_amd as L
+    import synth
+
+    insts = synth.c5_batch()
+    N, NA, K = args.c5_steps, args.c5_adj_steps, args.c5_K
+    prm, gws, rhos = [], [], []
+    for e in insts:
+        q = L.make_params(e["params"])
+        prm.append(dict(e["params"], rho_l=q.rho_l, rho_v=q.rho_v))
+        gws.append(e["gw"])
+        rhos.append(synth.droplet_rho(q.nx, q.ny, q.rho_l, q.rho_v, e["centres"], e["radii"],
+                                      seed=e["seed"]))
+    fluid = sum(p["nx"] * (p["ny"] - 2) for p in prm)
+    from paper_1410_2569_amd import tune as T
+    best = T.tuned(prm, gws, rhos, steps=40)
+    torch.cuda.reset_peak_memory_stats()
+    b = L.Batch(prm, gws, rhos, tune=best)
+    log(f"c5: {len(prm)} x {prm[0]['nx']}x{prm[0]['ny']}, tune {b.tune()}")
+    t_fwd1 = _timed(lambda: b.step(N - NA), b.stream)
+    states = [b.save_state(i) for i in range(len(prm))]
+    t_fwd2 = _timed(lambda: b.step(NA), b.stream)
+    t_fwd = t_fwd1 + t_fwd2
+    obs = b.observables(allow_nonfinite=True)
+    log(f"c5: forward {N} steps in {t_fwd:.2f} s")
+    del b
+    torch.cuda.empty_cache()
+
+    grads, t_adj = [], 0.0
+    sim = L.Sim(prm[0], gws[0], rhos[0])
+    ws = sim.adjoint_workspace(NA, K)
+    angles = []
+    for i in range(len(prm)):
+        if i:
+            sim = L.Sim(prm[i], gws[i], rhos[i])
+        sim.load_state(states[i])
+        for (xc, _), r in zip(insts[i]["centres"], insts[i]["radii"]):
+            o = sim.observables(xc - 1.6 * r, xc + 1.6 * r, allow_nonfinite=True)
+            angles.append(None if math.isnan(o["theta_deg"]) else round(o["theta_deg"], 2))
+
+        def adj():
+            sim.forward_ckpt(NA, K, ws)
+            sim.loss()
+            return sim.backward(NA, K, ws)
+
+        holder = {}
+        t_adj += _timed(lambda: holder.setdefault("g", adj()))
+        grads.append(holder["g"].cpu().numpy())
+        if i == 0:
+            sim0_state = states[0]
+            # finite differences on 16 seeded bottom-wall nodes of instance 0
+            d = synth.Draws(99)
+            nodes = sorted({int(d.u01() * prm[0]["nx"]) for _ in range(40)})[:16]
+            h = 1e-5
+            errs = []
+            scale = np.abs(grads[0][0]).max()
+            for x in nodes:
+                vals = []
+                for sgn in (1, -1):
+                    gg = gws[0].copy()
+                    gg[0, x] += sgn * h
+                    sim.load_state(sim0_state)
+                    sim.set_gw(gg)
+                    sim.step(NA)
+                    vals.append(sim.loss())
+                errs.append(abs(grads[0][0, x] - (vals[0] - vals[1]) / (2 * h)) / scale)
+            sim.set_gw(gws[0])
+            log(f"c5: FD check on {len(nodes)} nodes, max rel err {max(errs):.2e}")
+    peak = torch.cuda.max_memory_allocated()
+    lu_adj = 2 * fluid * NA  # forward_ckpt + backward, every instance
+    return {"metric": "c5 large batched + adjoint", "workload": "8 x 2048x1024, 6 droplets "
+            "each, striped G_w (-0.1/+0.2, width 64), modified form",
+            "forward": {"steps": N, "seconds": round(t_fwd, 3),
+                        "mlups": round(fluid * N / t_fwd / 1e6, 1),
+                        "tune": {k: best[k] for k in ("tile", "schedule", "waves_per_cu")},
+                        "hbm_frac_effective": round(BYTES_PER_LU * fluid * N / t_fwd
+                                                    / (HBM_PEAK_GBS * 1e9), 4),
+                        "nonfinite_instances": sum(1 for o in obs if o["nonfinite"])},
+            "adjoint": {"steps": NA, "K": K, "seconds": round(t_adj, 3),
+                        "mlups_forward_ckpt_plus_backward": round(lu_adj / t_adj / 1e6, 1),
+                        "fd_nodes": 16, "max_rel_err_vs_fd": float(max(errs))},
+            "peak_device_bytes": int(peak), "droplet_angles_deg": angles, "dtype": "f64"}
+
+
 COPY_BYTES = 9 * 512 * 1024 * 8  # one population buffer of the 1024x512 workload
 
 
 def profile_probe(args):
     """Workload for rocprofv3 counter runs: three copies of COPY_BYTES (a plain copy kernel that
-    reads and writes a known number of bytes, used to scale the counters) and 20 launches of the
-    step kernel on the first run of the sweep."""
+    reads and writes a known number of bytes, used to scale the counters) and 20 time steps of
+    the first run of the sweep with the benchmark's schedule (10 two-step launches)."""
     import torch
 
     import paper_1410_2569_amd as L
@@ -224,20 +318,26 @@ def profile_probe(args):
     rho0 = synth.droplet_rho(q.nx, q.ny, q.rho_l, q.rho_v, r["centres"], r["radii"],
                              seed=r["seed"])
     s = L.Sim(q, r["gw"], rho0)
-    if args.tile is not None:
+    if args.tile2 is not None:
+        s.set_schedule(32 + args.tile2)
+    elif args.tile is not None:
         s.set_schedule(16 + args.tile)
+    else:
+        s.set_schedule(args.schedule)
     s.step(20)
     torch.cuda.synchronize()
-    log(f"profile probe: copy {COPY_BYTES} B x3, 20 step launches of {q.nx}x{q.ny}")
+    log(f"profile probe: copy {COPY_BYTES} B x3, 20 steps of {q.nx}x{q.ny}")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50_000)
+    ap.add_argument("--steps", type=int, default=50_000, help="time steps per run (even)")
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--schedule", default="fused")
+    ap.add_argument("--schedule", default="two_step", choices=["two_step", "fused", "two_pass"])
     ap.add_argument("--tile", type=int, default=None, help="fused tile shape index")
+    ap.add_argument("--tile2", type=int, default=None,
+                    help="output tile of the two-steps-per-launch schedule")
     ap.add_argument("--runs", type=int, default=24, help="runs of the sweep to use (24 = all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -245,11 +345,20 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=20_000)
     ap.add_argument("--adj-fd-runs", type=int, default=64,
                     help="forward runs timed for the finite-difference baseline (of 512)")
+    ap.add_argument("--workload", default="sweep", choices=["sweep", "c5"],
+                    help="sweep: the 1024x512 sweep (default); c5: 8 x 2048x1024 ensemble with "
+                         "six droplets each, forward in one persistent launch, adjoint over "
+                         "the last 2,000 steps")
+    ap.add_argument("--c5-steps", type=int, default=30_000)
+    ap.add_argument("--c5-adj-steps", type=int, default=2_000)
+    ap.add_argument("--c5-K", type=int, default=45)
     ap.add_argument("--profile-probe", action="store_true",
                     help="for counter runs: a device copy of known size, then 20 step launches "
                          "of one run of the workload; prints no JSON")
     args = ap.parse_args()
 
+    if args.steps % 2:
+        args.steps += 1  # two steps per launch: keep the timed region a whole number of launches
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -267,6 +376,9 @@ def main():
     if args.profile_probe:
         profile_probe(args)
         return
+    if args.workload == "c5":
+        print(json.dumps(c5_run(args)), flush=True)
+        return
     runs = synth.c2_sweep()[: args.runs]
     sims = []
     for r in runs:
@@ -274,7 +386,9 @@ def main():
         rho0 = synth.droplet_rho(q.nx, q.ny, q.rho_l, q.rho_v, r["centres"], r["radii"],
                                  seed=r["seed"])
         s = L.Sim(q, r["gw"], rho0, device=dev)
-        if args.tile is not None:
+        if args.tile2 is not None:
+            s.set_schedule(32 + args.tile2)
+        elif args.tile is not None:
             s.set_schedule(16 + args.tile)
         else:
             s.set_schedule(args.schedule)
@@ -308,10 +422,13 @@ def main():
     ms = e0.elapsed_time(e1)
     lu = fluid * args.steps * len(sims)
     mlups = lu / (ms / 1e3) / 1e6
-    launches_per_step = 1 if sims[0] and args.schedule == "fused" else 2
-    step_launches = args.steps * len(sims)
-    avg_kernel_s = (ms / 1e3) / step_launches
-    achieved_gbs = BYTES_PER_LU * fluid / avg_kernel_s / 1e9
+    two_step = args.tile2 is not None or (args.tile is None and args.schedule == "two_step")
+    # the dominant kernel and its lattice updates per launch (two-pass: the step kernel's share
+    # of the time is not separable from events, so its figure covers both kernels)
+    lu_per_launch = (2 if two_step else 1) * fluid
+    launches = (args.steps // 2 if two_step else args.steps) * len(sims)
+    avg_kernel_s = (ms / 1e3) / launches
+    achieved_gbs = BYTES_PER_LU * lu_per_launch / avg_kernel_s / 1e9
     log(f"bench: {ms:.1f} ms (wall {wall:.1f} s), {mlups:.1f} MLUPS, "
         f"{achieved_gbs:.1f} GB/s algorithmic")
 
@@ -330,8 +447,10 @@ def main():
     tr = traffic_per_launch()
     roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-            "traffic": tr, "kernel": "lbm::k_step<fused>",
-            "bytes_per_lu": BYTES_PER_LU, "lu_per_launch": fluid,
+            "traffic": tr,
+            "kernel": ("lbm::k_step2<64,8>" if two_step else
+                       ("lbm::k_step<64,8,true>" if args.schedule == "fused" else "k_psi+k_step")),
+            "bytes_per_lu": BYTES_PER_LU, "lu_per_launch": lu_per_launch,
             "avg_launch_us": round(avg_kernel_s * 1e6, 3)}
     out = {"metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup,
@@ -340,7 +459,9 @@ def main():
            "config": {"workload": "1024x512 droplet R=150, CS EOS ratio 500, 3 wall forms x 8 "
                                   "G_w, one LB step of all 24 runs per bench step",
                       "lattice": [nx, ny], "runs": len(sims), "fluid_nodes_per_run": fluid,
-                      "schedule": args.schedule if args.tile is None else f"fused/tile{args.tile}"},
+                      "schedule": ("two_step/tile%d" % args.tile2 if args.tile2 is not None else
+                                   (args.schedule if args.tile is None
+                                    else f"fused/tile{args.tile}"))},
            "hbm_frac_effective": round(BYTES_PER_LU * mlups * 1e6 / (HBM_PEAK_GBS * 1e9), 4),
            "nonfinite_runs": bad,
            "roofline": roof}

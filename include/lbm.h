@@ -143,10 +143,16 @@ int lbm_load_state(lbm_ctx *c, const void *host, size_t bytes);
 /* Replace the wall wettability pattern ([2][nx] host array, copied). */
 int lbm_set_gw(lbm_ctx *c, const double *gw_host);
 
-/* Kernel schedule of lbm_step: 0 = fused single pass (psi of the tile halo recomputed from the
- * populations, 144 algorithmic bytes per lattice update), 1 = two passes (psi pass, then the
- * fused force-collide-stream pass reading psi through an LDS tile). Results are identical up to
- * floating-point contraction. */
+/* Kernel schedule of lbm_step:
+ *   0      fused single pass (psi of the tile halo recomputed from the populations; 144
+ *          algorithmic bytes per lattice update), tile 64x8;
+ *   1      two passes (psi pass, then the force-collide-stream pass reading psi through LDS);
+ *   2      (default) two time steps per launch (the first step's populations stay in LDS;
+ *          72 bytes per lattice update), an odd remainder step runs fused;
+ *   16+t   fused with tile shape t (0..7: 64x4, 64x8, 64x16, 128x4, and the overlapped
+ *          62-column tiles with 4, 6, 8, 14 rows);
+ *   32+t   two steps per launch with output tile t (0..3: 64x8, 64x4, 128x4, 64x16).
+ * All schedules give bit-identical populations. */
 int lbm_set_schedule(lbm_ctx *c, int32_t schedule);
 
 /* ---- Gradients of a wetting objective with respect to the wall wettability G_w ------------- */
@@ -188,7 +194,8 @@ typedef struct {
     int32_t tile;         /* tile shape 0..3: 64x4, 64x8, 64x16, 128x4 */
     int32_t reserved;     /* must be 0 */
     int32_t waves_per_cu; /* persistent schedule: workgroups per compute unit (0 = occupancy) */
-    int32_t schedule;     /* 0 per-step launches, 1 persistent */
+    int32_t schedule;     /* 0 per-step launches, 1 persistent, 2 two steps per launch (tile 1
+                             or 2 only: 64x8 or 64x16 output tiles) */
 } lbm_tune;
 
 typedef struct lbm_batch lbm_batch;
@@ -208,12 +215,16 @@ int lbm_batch_step(lbm_batch *b, int64_t n);
 int lbm_batch_observables(lbm_batch *b, lbm_obs *out);
 /* Pre-collision populations f^n of instance `index` ([9][ny][nx] host array). */
 int lbm_batch_read_f(lbm_batch *b, int32_t index, double *host, size_t count);
+/* State of instance `index` as a checkpoint blob (the format of lbm_save_state, loadable into
+ * a single-instance context with the same parameters by lbm_load_state); synchronises. */
+int lbm_batch_save_state(lbm_batch *b, int32_t index, void *host, size_t bytes);
 int64_t lbm_batch_current_step(const lbm_batch *b);
 /* The tune in use and the persistent grid size (workgroups). */
 int lbm_batch_get_tune(const lbm_batch *b, lbm_tune *t, int32_t *grid);
 int lbm_batch_destroy(lbm_batch *b);
 const char *lbm_batch_last_error(const lbm_batch *b);
-/* Autotuner: times every tile shape x schedule (persistent at full and half occupancy) for
+/* Autotuner: times every tile shape x schedule (persistent at full and half occupancy, two-step
+ * launches for the 64x8 and 64x16 tiles) for
  * `steps` steps on this ensemble in the given workspace and returns the fastest tune and its
  * time in milliseconds. */
 int lbm_autotune(const lbm_params *p, int32_t count, const double *const *gw_host,

@@ -32,6 +32,7 @@ struct lbm_ctx {
     int64_t step;
     int schedule;
     int tile;
+    int tile2;  // output tile of the two-step kernel
     // last lbm_forward_ckpt: where it started, its length and checkpoint interval
     int64_t adj_start, adj_nsteps;
     int32_t adj_K;
@@ -343,8 +344,9 @@ int lbm_create(const lbm_params* p, const double* gw_host, const double* rho0_ho
     c->fin = (double*)(c->ws + L.off_fin);
     c->cur = 0;
     c->step = 0;
-    c->schedule = 0;
+    c->schedule = 2;  // two steps per launch (bit-identical to single steps, fastest)
     c->tile = 1;
+    c->tile2 = 0;
     c->adj_start = -1;
     c->adj_nsteps = 0;
     c->adj_K = 0;
@@ -370,11 +372,17 @@ int lbm_create(const lbm_params* p, const double* gw_host, const double* rho0_ho
 
 int lbm_set_schedule(lbm_ctx* c, int32_t schedule) {
     if (!c) return LBM_E_INVAL;
-    // schedule: 0 fused (tile = default), 1 two-pass; 16 + t: fused with tile shape t
-    if (schedule == 0 || schedule == 1) { c->schedule = schedule; return LBM_OK; }
+    // 0 fused, 1 two-pass, 2 two steps per launch; 16 + t: fused with tile shape t;
+    // 32 + t: two steps per launch with output tile t
+    if (schedule >= 0 && schedule <= 2) { c->schedule = schedule; return LBM_OK; }
     if (schedule >= 16 && schedule < 16 + lbm::n_tiles()) {
         c->schedule = 0;
         c->tile = schedule - 16;
+        return LBM_OK;
+    }
+    if (schedule >= 32 && schedule < 36) {
+        c->schedule = 2;
+        c->tile2 = schedule - 32;
         return LBM_OK;
     }
     return fail(c, LBM_E_INVAL, "unknown schedule");
@@ -383,8 +391,17 @@ int lbm_set_schedule(lbm_ctx* c, int32_t schedule) {
 int lbm_step(lbm_ctx* c, int64_t n) {
     if (!c || n < 0) return LBM_E_INVAL;
     (void)hipGetLastError();  // report only errors of this call
+    if (c->schedule == 2) {
+        for (; n >= 2; n -= 2) {
+            hipError_t e = lbm::launch_step2(c->kp, c->tile2, c->g[c->cur], c->g[c->cur ^ 1],
+                                             c->gw, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "lbm_step");
+            c->cur ^= 1;
+            c->step += 2;
+        }
+    }
     for (int64_t i = 0; i < n; ++i) {
-        hipError_t e = lbm::launch_step(c->kp, c->schedule, c->tile, c->g[c->cur],
+        hipError_t e = lbm::launch_step(c->kp, c->schedule == 1 ? 1 : 0, c->tile, c->g[c->cur],
                                         c->g[c->cur ^ 1], c->psi, c->gw, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "lbm_step");
         c->cur ^= 1;
@@ -750,8 +767,10 @@ int batch_fail(lbm_batch* b, int code, const std::string& m) {
 
 int validate_tune(const lbm_tune* t) {
     if (!t) return LBM_OK;
-    if (t->tile < 0 || t->tile > 3 || t->schedule < 0 || t->schedule > 1 || t->waves_per_cu < 0)
+    if (t->tile < 0 || t->tile > 3 || t->schedule < 0 || t->schedule > 2 || t->waves_per_cu < 0 ||
+        t->reserved != 0)
         return LBM_E_INVAL;
+    if (t->schedule == 2 && t->tile != 1 && t->tile != 2) return LBM_E_INVAL;  // 64x8, 64x16
     return LBM_OK;
 }
 
@@ -866,6 +885,15 @@ int lbm_batch_create(const lbm_params* p, int32_t count, const double* const* gw
 }
 
 static int batch_direct(lbm_batch* b, int64_t n) {
+    if (b->tune.schedule == 2) {
+        for (; n >= 2; n -= 2) {
+            hipError_t e = lbm::launch_batch_step2(b->tune.tile, b->d_inst, b->d_tile_inst,
+                                                   b->ntiles, b->cur, b->stream);
+            if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, std::string("batch step: ") + hipGetErrorString(e));
+            b->cur ^= 1;
+            b->step += 2;
+        }
+    }
     for (int64_t i = 0; i < n; ++i) {
         hipError_t e = lbm::launch_batch_step(b->tune.tile, b->d_inst, b->d_tile_inst, b->ntiles,
                                               b->cur, b->stream);
@@ -934,10 +962,14 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
         const int cur = b->cur;
         if (!b->graph[cur]) {
             int rc = capture(b, &b->graph[cur], [&]() {
-                for (int i = 0; i < kGraphChunk; ++i) {
-                    hipError_t e = lbm::launch_batch_step(b->tune.tile, b->d_inst,
-                                                          b->d_tile_inst, b->ntiles,
-                                                          (cur + i) & 1, b->stream);
+                const bool two = b->tune.schedule == 2;  // two steps per launch
+                for (int i = 0; i < (two ? kGraphChunk / 2 : kGraphChunk); ++i) {
+                    hipError_t e = two ? lbm::launch_batch_step2(b->tune.tile, b->d_inst,
+                                                                 b->d_tile_inst, b->ntiles,
+                                                                 (cur + i) & 1, b->stream)
+                                       : lbm::launch_batch_step(b->tune.tile, b->d_inst,
+                                                                b->d_tile_inst, b->ntiles,
+                                                                (cur + i) & 1, b->stream);
                     if (e != hipSuccess) return e;
                 }
                 return hipSuccess;
@@ -946,7 +978,7 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
         }
         hipError_t e = hipGraphLaunch(b->graph[cur], b->stream);
         if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "graph launch");
-        b->step += kGraphChunk;  // kGraphChunk is even: parity unchanged
+        b->step += kGraphChunk;  // an even number of buffer swaps: parity unchanged
     }
     return batch_direct(b, n - chunks * kGraphChunk);
 }
@@ -1015,6 +1047,28 @@ int lbm_batch_read_f(lbm_batch* b, int32_t index, double* host, size_t count) {
     return LBM_OK;
 }
 
+
+int lbm_batch_save_state(lbm_batch* b, int32_t index, void* host, size_t bytes) {
+    if (!b || !host || index < 0 || index >= b->count) return LBM_E_INVAL;
+    int rc = batch_check_abort(b);
+    if (rc) return rc;
+    const KParams& P = b->kp[index];
+    const size_t need = sizeof(StateHeader) + (size_t)9 * P.nx * P.ny * sizeof(double);
+    if (bytes < need) return LBM_E_SIZE;
+    StateHeader h{kMagic, b->step, P.nx, P.ny, P.walls, 0};
+    std::memcpy(host, &h, sizeof h);
+    double* dst = (double*)((char*)host + sizeof h);
+    const lbm::InstDesc& d = b->desc[index];
+    hipError_t e = hipSuccess;
+    for (int a = 0; a < 9 && e == hipSuccess; ++a)
+        e = hipMemcpy2DAsync(dst + (size_t)a * P.nx * P.ny, P.nx * sizeof(double),
+                             d.g[b->cur] + a * P.plane, P.pitch * sizeof(double),
+                             P.nx * sizeof(double), P.ny, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "batch save state");
+    return LBM_OK;
+}
+
 int64_t lbm_batch_current_step(const lbm_batch* b) { return b ? b->step : -1; }
 
 int lbm_batch_get_tune(const lbm_batch* b, lbm_tune* t, int32_t* grid) {
@@ -1048,7 +1102,8 @@ int lbm_autotune(const lbm_params* p, int32_t count, const double* const* gw_hos
     double best_t = INFINITY;
     int rc_all = LBM_E_INVAL;
     for (int tile = 0; tile < 4; ++tile) {
-        for (int sched = 0; sched < 2; ++sched) {
+        for (int sched = 0; sched < 3; ++sched) {
+            if (sched == 2 && tile != 1 && tile != 2) continue;
             for (int half = 0; half < (sched == 1 ? 2 : 1); ++half) {
                 lbm_tune t{tile, 0, 0, sched};
                 size_t need;

@@ -32,6 +32,19 @@ __global__ __launch_bounds__(TX* TY) void k_batch_step(const InstDesc* __restric
     step_tile<TX, TY, true>(D->P, D->g[cur], D->g[cur ^ 1], nullptr, D->gw, x0, y0, sp);
 }
 
+// Two steps per launch over the work-list (the tiles are the output tiles of step2_tile).
+template <int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_batch_step2(const InstDesc* __restrict__ inst,
+                                                        const int* __restrict__ tile_inst,
+                                                        int ntiles, int cur) {
+    __shared__ Step2Lds<TX, TY> lds;
+    const int t = xcd_tile(blockIdx.x, ntiles);
+    const InstDesc* D = inst + tile_inst[t];
+    int x0, y0;
+    batch_tile_origin(D, t, TX, TY, x0, y0);
+    step2_tile<TX, TY>(D->P, D->g[cur], D->g[cur ^ 1], D->gw, x0, y0, lds);
+}
+
 // Grid-wide barrier number `target / gridDim.x`. Returns false when the run was aborted.
 __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, int* flag,
                                              int spin_limit, int* verdict) {
@@ -126,6 +139,20 @@ static int occupancy_t() {
 }
 
 int batch_tiles(int tile) { return tile >= 0 && tile < 4; }
+
+// Two steps per launch (schedule 2): tile 0 -> 64x8 output tiles, tile 3 -> 64x16; the work-list
+// must have been built for that tile shape.
+hipError_t launch_batch_step2(int tile, const InstDesc* inst, const int* tile_inst, int ntiles,
+                              int cur, hipStream_t s) {
+    if (tile == 2) {
+        hipLaunchKernelGGL((k_batch_step2<64, 16>), dim3(ntiles), dim3(64 * 16), 0, s, inst,
+                           tile_inst, ntiles, cur);
+    } else {
+        hipLaunchKernelGGL((k_batch_step2<64, 8>), dim3(ntiles), dim3(64 * 8), 0, s, inst,
+                           tile_inst, ntiles, cur);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_batch_step(int tile, const InstDesc* inst, const int* tile_inst, int ntiles,
                              int cur, hipStream_t s) {

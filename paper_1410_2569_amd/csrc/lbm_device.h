@@ -30,9 +30,15 @@ struct KParams {
     double s_nu_c, nu_v, dnu, rho_v, inv_drho;  // shear rate: constant, or interpolated
 };
 
+// x mod nx in [0, nx). Tile halos reach at most a few nodes past either end, so one add or
+// subtract suffices except on lattices narrower than a tile.
 __device__ __forceinline__ int wrapx(int x, int nx) {
-    int r = x % nx;
-    return r < 0 ? r + nx : r;
+    int r = x < 0 ? x + nx : (x >= nx ? x - nx : x);
+    if ((unsigned)r >= (unsigned)nx) {
+        r = x % nx;
+        r = r < 0 ? r + nx : r;
+    }
+    return r;
 }
 
 // Floating-point contraction is switched off inside the per-node arithmetic and the multiply-adds
@@ -324,6 +330,151 @@ __device__ __forceinline__ void step_tile(const KParams& P, const double* __rest
         for (int a = 0; a < 9; ++a) (gout + a * P.plane)[i] = f[a];
     }
 }
+
+}  // namespace lbm
+
+namespace lbm {
+
+// Two time steps per launch (temporal blocking). The workgroup owns a TX x TY tile of the second
+// step's output. With Rk the tile grown by k rings:
+//   A  psi of step n+1 on R3, from the pulled populations of gin          -> LDS ps1
+//   B  step n+1 (forces, collision) on the fluid nodes of R2              -> LDS g1 (9 planes)
+//   C  psi of step n+2 on R1, pulling from g1 (bounce-back, ghost rows)   -> LDS ps2
+//   D  step n+2 on the tile, pulling from g1                              -> gout
+// HBM sees one read and one write of the populations per two steps. Every node's arithmetic is
+// that of step_tile, so two launches of k_step and one of k_step2 give identical bits.
+__device__ __forceinline__ void pull9_lds(const KParams& P, const double* g1, int plane, int W,
+                                          int l, int gy, double f[9]) {
+    // l: local index of the node in the LDS grid (row stride W); gy: its global row
+    const bool bot = P.walls && gy == 1, top = P.walls && gy == P.ny - 2;
+    f[0] = g1[l];
+    f[1] = g1[1 * plane + l - 1];
+    f[3] = g1[3 * plane + l + 1];
+    f[2] = bot ? g1[4 * plane + l] : g1[2 * plane + l - W];
+    f[5] = bot ? g1[7 * plane + l] : g1[5 * plane + l - W - 1];
+    f[6] = bot ? g1[8 * plane + l] : g1[6 * plane + l - W + 1];
+    f[4] = top ? g1[2 * plane + l] : g1[4 * plane + l + W];
+    f[7] = top ? g1[5 * plane + l] : g1[7 * plane + l + W + 1];
+    f[8] = top ? g1[6 * plane + l] : g1[8 * plane + l + W - 1];
+}
+
+template <int TX, int TY>
+struct Step2Lds {
+    static constexpr int W3 = TX + 6, H3 = TY + 6, W2 = TX + 4, H2 = TY + 4, W1 = TX + 2,
+                         H1 = TY + 2, PL = W2 * H2;
+    double g1[9 * PL];
+    double ps1[W3 * H3];
+    double ps2[W1 * H1];
+};
+
+template <int TX, int TY>
+__device__ __forceinline__ void step2_tile(const KParams& P, const double* __restrict__ gin,
+                                           double* __restrict__ gout,
+                                           const double* __restrict__ gw, int x0, int y0,
+                                           Step2Lds<TX, TY>& L) {
+    constexpr int NT = TX * TY;
+    constexpr int W3 = TX + 6, H3 = TY + 6, W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
+    constexpr int PL = W2 * H2;
+    double* g1 = L.g1;
+    double* ps1 = L.ps1;
+    double* ps2 = L.ps2;
+
+    // A: psi of step n+1 on R3. The R2 slots (up to three per thread) keep their pulled
+    // populations and density in registers for B; the outer ring of R3 only needs psi.
+    constexpr int NR = (PL + NT - 1) / NT;
+    static_assert(NR <= 3, "at most three R2 slots per thread");
+    double fk[NR][9], rk[NR];
+    bool ok[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int s = threadIdx.x + r * NT;
+        ok[r] = false;
+        rk[r] = 1.0;
+        if (s >= PL) continue;
+        const int lx = s % W2, ly = s / W2;
+        double ps = 0.0;
+        int gy = y0 - 2 + ly;
+        bool fluid;
+        if (P.walls) fluid = gy >= 1 && gy <= P.ny - 2;
+        else { gy = wrapx(gy, P.ny); fluid = true; }
+        if (fluid) {
+            pull9(P, gin, wrapx(x0 - 2 + lx, P.nx), gy, fk[r]);
+            rk[r] = sum9(fk[r]);
+            ps = psi_of_rho(P, rk[r]);
+            ok[r] = true;
+        } else {
+            ps = psi_at(P, gin, x0 - 2 + lx, y0 - 2 + ly);  // solid row: ghost value or 0
+        }
+        ps1[(ly + 1) * W3 + lx + 1] = ps;
+    }
+    constexpr int NRING = 2 * W3 + 2 * H2;  // the ring of R3 outside R2
+    for (int h = threadIdx.x; h < NRING; h += NT) {
+        int lx, ly;  // R3-local coordinates
+        if (h < W3) { lx = h; ly = 0; }
+        else if (h < 2 * W3) { lx = h - W3; ly = H3 - 1; }
+        else if (h < 2 * W3 + H2) { lx = 0; ly = h - 2 * W3 + 1; }
+        else { lx = W3 - 1; ly = h - 2 * W3 - H2 + 1; }
+        ps1[ly * W3 + lx] = psi_at(P, gin, x0 - 3 + lx, y0 - 3 + ly);
+    }
+    __syncthreads();
+
+    // B: step n+1 on the fluid nodes of R2
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        if (!ok[r]) continue;
+        const int s = threadIdx.x + r * NT;
+        const int lx = s % W2, ly = s / W2;
+        const int gx = wrapx(x0 - 2 + lx, P.nx);
+        const int gy = P.walls ? y0 - 2 + ly : wrapx(y0 - 2 + ly, P.ny);
+        const double* c = ps1 + (ly + 1) * W3 + lx + 1;
+        double sx, sy;
+        cohesion_sum(c[-W3 - 1], c[-W3], c[-W3 + 1], c[-1], c[1], c[W3 - 1], c[W3], c[W3 + 1],
+                     sx, sy);
+        double Ax = 0.0, Ay = 0.0;
+        if (P.walls && (gy == 1 || gy == P.ny - 2)) adhesion_sum(P, gw, gx, gy, Ax, Ay);
+        collide(P, fk[r], rk[r], c[0], sx, sy, Ax, Ay);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) g1[a * PL + s] = fk[r][a];
+    }
+    __syncthreads();
+
+    // C: psi of step n+2 on R1 (solid rows take the mirrored fluid row, or 0)
+    for (int s = threadIdx.x; s < W1 * H1; s += NT) {
+        const int lx = s % W1, ly = s / W1;
+        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+        int sx, sy;
+        double v = 0.0;
+        if (slot_source(P, gx, gy, sx, sy)) {
+            // the source node in the R2 grid: same column, row sy (mirrored rows stay adjacent)
+            const int ly2 = P.walls ? sy - (y0 - 2) : ly + 1;
+            double f[9];
+            pull9_lds(P, g1, PL, W2, ly2 * W2 + lx + 1, sy, f);
+            v = psi_of_rho(P, sum9(f));
+        }
+        ps2[s] = v;
+    }
+    __syncthreads();
+
+    // D: step n+2 on the tile
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int x = x0 + tx, y = y0 + ty;
+    if (x < P.nx && y <= P.y_hi) {
+        double f[9];
+        pull9_lds(P, g1, PL, W2, (ty + 2) * W2 + tx + 2, y, f);
+        const double rho = sum9(f);
+        const double* c = ps2 + (ty + 1) * W1 + tx + 1;
+        double sx, sy;
+        cohesion_sum(c[-W1 - 1], c[-W1], c[-W1 + 1], c[-1], c[1], c[W1 - 1], c[W1], c[W1 + 1],
+                     sx, sy);
+        double Ax = 0.0, Ay = 0.0;
+        if (P.walls && (y == 1 || y == P.ny - 2)) adhesion_sum(P, gw, x, y, Ax, Ay);
+        collide(P, f, rho, c[0], sx, sy, Ax, Ay);
+        const unsigned i = (unsigned)y * P.pitch + x;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) (gout + a * P.plane)[i] = f[a];
+    }
+}
+
 
 }  // namespace lbm
 

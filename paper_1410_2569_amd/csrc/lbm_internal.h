@@ -30,6 +30,8 @@ int n_tiles();
 void tile_shape(int tile, int* tx, int* ty);
 hipError_t launch_step(const KParams& P, int schedule, int tile, const double* gin, double* gout,
                        double* psi, const double* gw, hipStream_t s);
+hipError_t launch_step2(const KParams& P, int tile2, const double* gin, double* gout,
+                        const double* gw, hipStream_t s);
 hipError_t launch_init(const KParams& P, const double* rho0, double* g, hipStream_t s);
 hipError_t launch_pull(const KParams& P, const double* gin, double* fout, hipStream_t s);
 hipError_t launch_rho_psi(const KParams& P, const double* gin, double* psi, double* rho,
@@ -54,6 +56,8 @@ hipError_t launch_loss_seed(const KParams& P, double w_c, double w_w, double yc,
 int batch_tiles(int tile);
 hipError_t launch_batch_step(int tile, const InstDesc* inst, const int* tile_inst, int ntiles,
                              int cur, hipStream_t s);
+hipError_t launch_batch_step2(int tile, const InstDesc* inst, const int* tile_inst, int ntiles,
+                              int cur, hipStream_t s);
 hipError_t launch_batch_persistent(int tile, int grid, const InstDesc* inst,
                                    const int* tile_inst, int ntiles, int nsteps, int cur,
                                    unsigned* bar, int* flag, int spin_limit, hipStream_t s);

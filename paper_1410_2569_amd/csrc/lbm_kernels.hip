@@ -74,6 +74,18 @@ __global__ __launch_bounds__(64 * (TYI + 2)) void k_step_ov(KParams P,
     for (int a = 0; a < 9; ++a) (gout + a * P.plane)[i] = f[a];
 }
 
+// Two steps per launch over TX x TY output tiles (step2_tile).
+template <int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_step2(KParams P, const double* __restrict__ gin,
+                                                  double* __restrict__ gout,
+                                                  const double* __restrict__ gw) {
+    __shared__ Step2Lds<TX, TY> lds;
+    const int ntx = (P.nx + TX - 1) / TX;
+    const int nty = (P.y_hi - P.y_lo + TY) / TY;
+    const int tile = xcd_tile(blockIdx.x, ntx * nty);
+    step2_tile<TX, TY>(P, gin, gout, gw, (tile % ntx) * TX, P.y_lo + (tile / ntx) * TY, lds);
+}
+
 // psi pass of the two-pass schedule; also writes the mirrored ghost rows.
 __global__ __launch_bounds__(256) void k_psi(KParams P, const double* __restrict__ gin,
                                              double* __restrict__ psi_g,
@@ -269,6 +281,26 @@ static hipError_t launch_step_ov(const KParams& P, const double* gin, double* go
     hipLaunchKernelGGL((k_step_ov<TYI>), dim3(ntx * nty), dim3(64 * (TYI + 2)), 0, s, P, gin,
                        gout, gw);
     return hipGetLastError();
+}
+
+template <int TX, int TY>
+static hipError_t launch_step2_t(const KParams& P, const double* gin, double* gout,
+                                 const double* gw, hipStream_t s) {
+    const int ntx = (P.nx + TX - 1) / TX;
+    const int nty = (P.y_hi - P.y_lo + TY) / TY;
+    hipLaunchKernelGGL((k_step2<TX, TY>), dim3(ntx * nty), dim3(TX * TY), 0, s, P, gin, gout, gw);
+    return hipGetLastError();
+}
+
+// Two steps in one launch; tile2 selects the output tile: 0 64x8, 1 64x4, 2 128x4, 3 64x16.
+hipError_t launch_step2(const KParams& P, int tile2, const double* gin, double* gout,
+                        const double* gw, hipStream_t s) {
+    switch (tile2) {
+        case 1: return launch_step2_t<64, 4>(P, gin, gout, gw, s);
+        case 2: return launch_step2_t<128, 4>(P, gin, gout, gw, s);
+        case 3: return launch_step2_t<64, 16>(P, gin, gout, gw, s);
+        default: return launch_step2_t<64, 8>(P, gin, gout, gw, s);
+    }
 }
 
 // Fused tile shapes: 0-3 halo-recompute tiles TX x TY; 4-7 overlapped tiles 62 x TYI.

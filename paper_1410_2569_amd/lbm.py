@@ -19,7 +19,7 @@ ABI_VERSION = 1
 OK, E_INVAL, E_SIZE, E_HIP, E_NONFINITE, E_ABI, E_STATE = 0, -1, -2, -3, -4, -5, -6
 WALL = {"rho": 0, "psi": 1, "modpsi": 2}
 EOS = {"cs": 0, "piecewise": 1}
-SCHEDULE = {"fused": 0, "two_pass": 1}
+SCHEDULE = {"fused": 0, "two_pass": 1, "two_step": 2}
 
 
 class LBMError(RuntimeError):
@@ -91,6 +91,7 @@ SIGNATURES = {
     "lbm_batch_step": (C.c_int, [C.c_void_p, C.c_int64]),
     "lbm_batch_observables": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbm_batch_read_f": (C.c_int, [C.c_void_p, C.c_int32, _dp, C.c_size_t]),
+    "lbm_batch_save_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]),
     "lbm_batch_current_step": (C.c_int64, [C.c_void_p]),
     "lbm_batch_get_tune": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
     "lbm_batch_destroy": (C.c_int, [C.c_void_p]),
@@ -348,6 +349,14 @@ class Batch:
         if not (rc == E_NONFINITE and allow_nonfinite):
             self._chk(rc)
         return [o.as_dict() for o in out]
+
+    def save_state(self, index: int) -> bytes:
+        """Checkpoint blob of one instance, loadable by Sim.load_state."""
+        q = self.params[index]
+        n = 32 + 9 * q.nx * q.ny * 8
+        buf = C.create_string_buffer(n)
+        self._chk(lib().lbm_batch_save_state(self.h, int(index), buf, n))
+        return buf.raw
 
     def f(self, index: int) -> np.ndarray:
         q = self.params[index]

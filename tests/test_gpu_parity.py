@@ -141,6 +141,17 @@ def test_tile_shapes_and_schedules_bitwise(orc, gpu):
             ref = f
         else:
             assert np.array_equal(f, ref), f"tile shape {t} differs from tile shape 0"
+    # two steps per launch, every output tile, odd step count (one single-step remainder)
+    for t in range(4):
+        sim = gpu.Sim(pg, gw, rho0)
+        sim.set_schedule(32 + t)
+        sim.step(steps)
+        assert np.array_equal(sim.f(), ref), f"two-step tile {t} differs from the single step"
+    # the two-pass schedule stages the same psi values through memory: also bit-identical
+    sim = gpu.Sim(pg, gw, rho0)
+    sim.set_schedule(1)
+    sim.step(steps)
+    assert np.array_equal(sim.f(), ref), "two-pass schedule differs"
     # rerun determinism
     sim = gpu.Sim(pg, gw, rho0)
     sim.set_schedule(16)
@@ -163,7 +174,7 @@ def test_tiny_and_ragged_lattices_all_tiles(orc, gpu, nx, ny, walls):
     pg = dict(p, rho_l=q.rho_l, rho_v=q.rho_v)
     gw = rng.uniform(-0.1, 0.1, (2, nx))
     f = orc.run(q, gw, orc.init_rest(q, rho0), steps)
-    for sched in [0, 1] + [16 + t for t in range(8)]:
+    for sched in [0, 1, 2] + [16 + t for t in range(8)] + [32 + t for t in range(4)]:
         sim = gpu.Sim(pg, gw, rho0)
         sim.set_schedule(sched)
         sim.step(steps)
