@@ -29,7 +29,7 @@ METRIC = "MLUPS & %HBM peak per LB step; batched-sweep and adjoint speedup vs pl
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LU = 144  # algorithmic: read and write the 9 FP64 populations once
 KERNEL_SOURCES = ["paper_1410_2569_amd/csrc/lbm_device.h", "paper_1410_2569_amd/csrc/lbm_kernels.hip"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused_step_1024x512.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step2_1024x512.json")
 
 
 def kernel_hash() -> str:
