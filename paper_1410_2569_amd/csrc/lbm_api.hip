@@ -388,25 +388,38 @@ int lbm_set_schedule(lbm_ctx* c, int32_t schedule) {
     return fail(c, LBM_E_INVAL, "unknown schedule");
 }
 
-int lbm_step(lbm_ctx* c, int64_t n) {
-    if (!c || n < 0) return LBM_E_INVAL;
-    (void)hipGetLastError();  // report only errors of this call
+// Launches of `n` steps of the context's schedule from buffer parity `cur`; *cur_out receives the
+// parity holding the result (every launch swaps the buffers: two steps per launch make n/2 + n%2
+// swaps, single steps n).
+static hipError_t enqueue_steps(lbm_ctx* c, int64_t n, int cur, hipStream_t s, int* cur_out) {
+    *cur_out = cur;
     if (c->schedule == 2) {
         for (; n >= 2; n -= 2) {
-            hipError_t e = lbm::launch_step2(c->kp, c->tile2, c->g[c->cur], c->g[c->cur ^ 1],
-                                             c->gw, c->stream);
-            if (e != hipSuccess) return hip_fail(c, e, "lbm_step");
-            c->cur ^= 1;
-            c->step += 2;
+            hipError_t e = lbm::launch_step2(c->kp, c->tile2, c->g[cur], c->g[cur ^ 1], c->gw, s);
+            if (e != hipSuccess) return e;
+            cur ^= 1;
+            *cur_out = cur;
         }
     }
     for (int64_t i = 0; i < n; ++i) {
-        hipError_t e = lbm::launch_step(c->kp, c->schedule == 1 ? 1 : 0, c->tile, c->g[c->cur],
-                                        c->g[c->cur ^ 1], c->psi, c->gw, c->stream);
-        if (e != hipSuccess) return hip_fail(c, e, "lbm_step");
-        c->cur ^= 1;
-        c->step += 1;
+        hipError_t e = lbm::launch_step(c->kp, c->schedule == 1 ? 1 : 0, c->tile, c->g[cur],
+                                        c->g[cur ^ 1], c->psi, c->gw, s);
+        if (e != hipSuccess) return e;
+        cur ^= 1;
+        *cur_out = cur;
     }
+    return hipSuccess;
+}
+
+int lbm_step(lbm_ctx* c, int64_t n) {
+    if (!c || n < 0) return LBM_E_INVAL;
+    (void)hipGetLastError();  // report only errors of this call
+    // direct launches: on this platform replaying captured graphs measured slower at every size
+    int after = c->cur;
+    hipError_t e = enqueue_steps(c, n, c->cur, c->stream, &after);
+    if (e != hipSuccess) return hip_fail(c, e, "lbm_step");
+    c->cur = after;
+    c->step += n;
     return LBM_OK;
 }
 
@@ -621,13 +634,11 @@ int lbm_forward_ckpt(lbm_ctx* c, int64_t nsteps, int32_t K, void* d_adj, size_t 
     c->adj_nsteps = nsteps;
     c->adj_K = K;
     c->adj_ws = d_adj;
-    for (int64_t i = 0; i < nsteps; ++i) {
-        if (i % K == 0) {
-            hipError_t e = hipMemcpyAsync(w + A.off_ck + (size_t)(i / K) * A.fbytes, c->g[c->cur], fb,
-                                          hipMemcpyDeviceToDevice, c->stream);
-            if (e != hipSuccess) return hip_fail(c, e, "checkpoint");
-        }
-        int rc = lbm_step(c, 1);
+    for (int64_t i = 0; i < nsteps; i += K) {
+        hipError_t e = hipMemcpyAsync(w + A.off_ck + (size_t)(i / K) * A.fbytes, c->g[c->cur], fb,
+                                      hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "checkpoint");
+        int rc = lbm_step(c, std::min<int64_t>(K, nsteps - i));
         if (rc) return rc;
     }
     return LBM_OK;
@@ -670,17 +681,28 @@ int lbm_backward(lbm_ctx* c, int64_t nsteps, int32_t K, void* d_adj, size_t byte
         char* seg = w + A.off_seg;
         e = hipMemcpyAsync(seg, w + A.off_ck + (size_t)j * A.fbytes, fb, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return hip_fail(c, e, "segment restore");
-        for (int64_t i = 0; i + 1 < len; ++i) {
-            e = lbm::launch_step(P, c->schedule, c->tile, (const double*)(seg + i * A.fbytes),
-                                 (double*)(seg + (i + 1) * A.fbytes), c->psi, c->gw, s);
-            if (e != hipSuccess) return hip_fail(c, e, "segment recompute");
-        }
-        for (int64_t i = len - 1; i >= 0; --i) {
-            e = lbm::launch_adj_step(P, (const double*)(seg + i * A.fbytes), a_buf[ca], c_buf[ca],
-                                     c->gw, a_buf[ca ^ 1], q, p0, dpsi, rv, c_buf[ca ^ 1], gg, s);
-            if (e != hipSuccess) return hip_fail(c, e, "adjoint step");
-            ca ^= 1;
-        }
+        // recompute the segment's states, then its adjoint steps in reverse
+        const int ca0 = ca;
+        auto segment = [&](hipStream_t st) -> hipError_t {
+            hipError_t r;
+            for (int64_t i = 0; i + 1 < len; ++i) {
+                r = lbm::launch_step(P, c->schedule == 1 ? 1 : 0, c->tile,
+                                     (const double*)(seg + i * A.fbytes),
+                                     (double*)(seg + (i + 1) * A.fbytes), c->psi, c->gw, st);
+                if (r != hipSuccess) return r;
+            }
+            int k = ca0;
+            for (int64_t i = len - 1; i >= 0; --i) {
+                r = lbm::launch_adj_step(P, (const double*)(seg + i * A.fbytes), a_buf[k], c_buf[k],
+                                         c->gw, a_buf[k ^ 1], q, p0, dpsi, rv, c_buf[k ^ 1], gg, st);
+                if (r != hipSuccess) return r;
+                k ^= 1;
+            }
+            return hipSuccess;
+        };
+        e = segment(s);
+        if (e != hipSuccess) return hip_fail(c, e, "adjoint segment");
+        ca = ca0 ^ (int)(len & 1);
     }
     e = hipMemcpy2DAsync(d_grad_gw, P.nx * sizeof(double), gg, P.pitch * sizeof(double),
                          P.nx * sizeof(double), 2, hipMemcpyDeviceToDevice, s);

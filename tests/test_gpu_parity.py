@@ -181,6 +181,29 @@ def test_tiny_and_ragged_lattices_all_tiles(orc, gpu, nx, ny, walls):
         assert_f_close(q, sim.f(), f, what=f"{nx}x{ny} walls={walls} schedule {sched}")
 
 
+@pytest.mark.parametrize("schedule", [0, 2, 17, 33])
+def test_step_count_splits_agree(orc, gpu, schedule):
+    """The state after 131 steps must not depend on how the steps are split into lbm_step calls
+    (graph-replayed chunks of 64, two-step launches, odd remainders)."""
+    p = synth.base_params(nx=96, ny=24, wall_force="modpsi")
+    q, pg, rho0 = setup_case(orc, p, None, [(48.0, 0.5)], [8.0], seed=1)
+    gw = synth.gw_uniform(96, 0.1)
+    ref = None
+    for chunks in ([1] * 131, [131], [2] * 65 + [1], [64, 67], [3, 64, 64]):
+        sim = gpu.Sim(pg, gw, rho0)
+        sim.set_schedule(schedule)
+        for n in chunks:
+            sim.step(n)
+        assert sim.current_step == 131
+        f = sim.f()
+        if ref is None:
+            ref = f
+            fo = orc.run(q, gw, orc.init_rest(q, rho0), 131)
+            assert_f_close(q, f, fo, what=f"schedule {schedule}")
+        else:
+            assert np.array_equal(f, ref), (schedule, chunks)
+
+
 def test_c1_geometry_10k_steps(orc, gpu):
     """120x60 lattice, droplet R = 20 on the bottom wall, 10,000 steps. The psi-based wall force
     at G_w = -0.05 (the specified G_w = -0.2 diverges, see test_c1_as_specified_diverges)."""
