@@ -10,9 +10,11 @@
  *   abort or exit. lbm_strerror() names a code; lbm_last_error() gives the message of the last
  *   failure on a context.
  * - Arithmetic is IEEE binary64 throughout.
- * - Lattice: nx columns (x, periodic) by ny rows (y). With walls = 1, rows y = 0 and y = ny-1
- *   are solid nodes (flat walls; the wall planes of halfway bounce-back sit at y = 0.5 and
- *   y = ny - 1.5) and the fluid occupies rows 1 .. ny-2. With walls = 0, y is periodic too.
+ * - Lattice: nx columns (x, periodic) by ny rows (y). With walls = 1 or 2, rows y = 0 and
+ *   y = ny-1 are solid nodes (flat walls) and the fluid occupies rows 1 .. ny-2. walls = 1:
+ *   halfway bounce-back, wall planes at y = 0.5 and y = ny - 1.5. walls = 2: the non-slip
+ *   wet-node scheme of Sec. III.A, wall planes on the boundary nodes y = 1 and y = ny - 2. With
+ *   walls = 0, y is periodic too.
  * - Host arrays are row-major with x fastest: a field is [ny][nx]; populations are [9][ny][nx]
  *   in the velocity order 0 rest; 1..4 = E, N, W, S; 5..8 = NE, NW, SW, SE.
  * - Wall wettability G_w is given per solid node: gw[2][nx], row 0 for the bottom wall (y = 0),
@@ -56,13 +58,23 @@ enum lbm_wall { LBM_WALL_RHO = 0, LBM_WALL_PSI = 1, LBM_WALL_MODPSI = 2 };
  * or the piecewise-linear Eq. (15) of Sec. III. */
 enum lbm_eos { LBM_EOS_CS = 0, LBM_EOS_PIECEWISE = 1 };
 
+/* Geometry in y (lbm_params.walls).
+ * LBM_WALLS_BOUNCE_BACK: a population that would stream in from a solid node is the one the node
+ *   itself sent towards the wall (halfway bounce-back).
+ * LBM_WALLS_WET_NODE: the non-slip boundary of Sec. III.A. The boundary nodes (rows 1 and ny-2)
+ *   reconstruct the populations arriving from the solid from the streamed ones and their force
+ *   F of the previous step so that sum_a e_a f_a + F/2 = 0 (bottom wall: f2 = f4,
+ *   f5 = f7 - (f1 - f3)/2 - (Fx + Fy)/4, f6 = f8 + (f1 - f3)/2 + (Fx - Fy)/4; the top wall is the
+ *   same rule rotated by 180 degrees). That force is part of the state (saved with it). */
+enum lbm_geometry { LBM_PERIODIC = 0, LBM_WALLS_BOUNCE_BACK = 1, LBM_WALLS_WET_NODE = 2 };
+
 typedef struct {
     int32_t abi_version; /* must be LBM_ABI_VERSION */
     int32_t nx, ny;      /* nx >= 3; ny >= 4 with walls, >= 3 without */
-    int32_t walls;       /* 1: solid rows 0 and ny-1 (halfway bounce-back); 0: periodic in y */
+    int32_t walls;       /* enum lbm_geometry: 0 periodic in y; 1, 2 solid rows 0 and ny-1 */
     int32_t ghost_psi;   /* 1: Eq. (7) also acts across the wall: a solid row carries the psi of
-                            the adjacent fluid row (mirror about the wall plane), so G_w = 0 is
-                            neutral wetting (Sec. III.A); 0: psi = 0 on solid nodes */
+                            the adjacent fluid row, so G_w = 0 is neutral wetting (Sec. III.A);
+                            0: psi = 0 on solid nodes */
     int32_t eos;         /* enum lbm_eos */
     int32_t wall_force;  /* enum lbm_wall */
     int32_t reserved;    /* must be 0 */
@@ -100,6 +112,12 @@ int lbm_maxwell_cs(double a, double b, double R, double T, double *rho_v, double
                    double *p0);
 /* Temperature at which the Carnahan-Starling Maxwell densities have ratio rho_l/rho_v = ratio. */
 int lbm_cs_temperature(double a, double b, double R, double ratio, double *T);
+/* Spinodal densities rho1 < rho2 of the piecewise-linear EOS, Eq. (15), whose Maxwell
+ * coexistence densities are (rho_v, rho_l): mechanical and chemical equilibrium as in Sec. III
+ * (for (1, 500) and slopes (0.64, -0.04, 1) c_s^2 the paper gives 1.36 and 481.04).
+ * LBM_E_INVAL if no such pair exists (needs th_m < th_l and rho_v < rho1 < rho2 < rho_l). */
+int lbm_piecewise_spinodals(double rho_v, double rho_l, double th_v, double th_m, double th_l,
+                            double *rho1, double *rho2);
 
 /* ---- Single instance ---------------------------------------------------------------------- */
 

@@ -189,13 +189,19 @@ def kasa_fit(pts: np.ndarray) -> tuple[float, float, float]:
     return xc, yc, float(np.sqrt(xc * xc + yc * yc - F))
 
 
+def wall_plane(q: Params) -> float:
+    """Height of the bottom wall plane: halfway between the solid row 0 and fluid row 1 with
+    bounce-back, on the boundary nodes of row 1 with the wet-node scheme (Sec. III.A)."""
+    return 1.0 if q.walls == 2 else 0.5
+
+
 def contact_angle(q: Params, rho: np.ndarray, x_lo=-np.inf, x_hi=np.inf):
-    """Static contact angle of a droplet on the bottom wall (wall plane y_b = 0.5):
+    """Static contact angle of a droplet on the bottom wall (wall plane y_b, see wall_plane):
     theta = acos((y_b - yc) / r) from the Kasa fit of the interface points with y >= y_b + 3.
     Returns (theta_deg, xc, yc, r, n_points); theta is NaN when fewer than 6 points remain or
     the fitted circle does not cut the wall plane."""
     rho_mid = 0.5 * (q.rho_l + q.rho_v)
-    yb = 0.5
+    yb = wall_plane(q)
     pts = interface_points(q, rho, rho_mid, yb + 3.0, x_lo, x_hi)
     if len(pts) < 6:
         return float("nan"), float("nan"), float("nan"), float("nan"), len(pts)

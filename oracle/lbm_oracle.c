@@ -10,6 +10,10 @@
  * Layout: populations f[a][y][x] (a = 0..8, x fastest), pre-collision (post-streaming) values,
  * i.e. the f_alpha(x, t) of Eq. (1). With walls, rows y = 0 and y = ny-1 are solid nodes and the
  * fluid occupies 1 <= y <= ny-2; x is periodic. Without walls both directions are periodic.
+ * Two wall schemes: halfway bounce-back (walls = 1; the wall plane lies halfway between the solid
+ * row and the first fluid row) and the non-slip wet-node scheme of Sec. III.A (walls = 2; rows 1
+ * and ny-2 are boundary nodes on the wall plane whose populations arriving from the solid are
+ * reconstructed so that the node's velocity, Eq. (6), is zero).
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off [-fopenmp] -shared -fPIC. Every per-node loop writes
  * only its own node, so the result does not depend on the thread count.
@@ -25,7 +29,8 @@ enum { ORC_WALL_RHO = 0, ORC_WALL_PSI = 1, ORC_WALL_MODPSI = 2 };
 
 typedef struct {
     int32_t nx, ny;
-    int32_t walls;       /* 1: solid rows y = 0 and y = ny-1; 0: periodic in y as well */
+    int32_t walls;       /* 1, 2: solid rows y = 0 and y = ny-1 (1 bounce-back, 2 wet-node);
+                            0: periodic in y as well */
     int32_t ghost;       /* 1: Eq. (7) also acts across the wall through mirrored psi rows */
     int32_t eos;         /* ORC_EOS_CS or ORC_EOS_PIECEWISE (Eq. 15) */
     int32_t wall_force;  /* ORC_WALL_RHO (Eq. 10), ORC_WALL_PSI (Eq. 11), ORC_WALL_MODPSI (Eq. 14) */
@@ -123,8 +128,9 @@ static int density_and_psi(const orc_params *p, const double *f, double *rho, do
     }
     if (bad) return ORC_E_PSI;
     if (p->walls) {
-        /* Eq. (7) applied at the wall: the solid row takes the psi of the fluid row next to it,
-         * the mirror image about the wall plane halfway between them. */
+        /* Eq. (7) applied at the wall: the solid row takes the psi of the fluid row next to it
+         * (with bounce-back, the mirror image about the wall plane halfway between them; with
+         * the wet-node scheme, the psi of the boundary node on the wall plane). */
         for (int x = 0; x < nx; ++x) {
             psi[x] = p->ghost ? psi[(size_t)nx + x] : 0.0;
             psi[(size_t)(ny - 1) * nx + x] = p->ghost ? psi[(size_t)(ny - 2) * nx + x] : 0.0;
@@ -255,12 +261,30 @@ static void collide_at(const orc_params *p, const double fin[9], double rho, dou
     }
 }
 
-/* One full time step, f^n -> f^{n+1}, in place. work: 11 * nx * ny doubles (rho, psi, f*). */
+/* Non-slip wet-node boundary of Sec. III.A at a node of the bottom wall plane (unknowns f2, f5,
+ * f6 arrive from the solid) or, rotated by 180 degrees, of the top wall plane (unknowns f4, f7,
+ * f8). fn: the node's post-streaming populations with the known ones filled in; F: the total
+ * force of the step just taken at this node. The reconstruction makes sum_a e_a f_a + F/2 = 0. */
+static void wet_node(int bottom, const double F[2], double fn[9])
+{
+    const double d13 = fn[1] - fn[3];
+    if (bottom) {
+        fn[2] = fn[4];
+        fn[5] = fn[7] - 0.5 * d13 - 0.25 * (F[0] + F[1]);
+        fn[6] = fn[8] + 0.5 * d13 + 0.25 * (F[0] - F[1]);
+    } else {
+        fn[4] = fn[2];
+        fn[7] = fn[5] + 0.5 * d13 + 0.25 * (F[0] + F[1]);
+        fn[8] = fn[6] - 0.5 * d13 - 0.25 * (F[0] - F[1]);
+    }
+}
+
+/* One full time step, f^n -> f^{n+1}, in place. work: 13 * nx * ny doubles (rho, psi, f*, F). */
 static int one_step(const orc_params *p, const double *gw, double *f, double *work)
 {
     const int nx = p->nx, ny = p->ny;
     const size_t N = (size_t)nx * ny;
-    double *rho = work, *psi = work + N, *fs = work + 2 * N;
+    double *rho = work, *psi = work + N, *fs = work + 2 * N, *Ft = work + 11 * N;
     int rc = density_and_psi(p, f, rho, psi);
     if (rc) return rc;
 
@@ -277,11 +301,14 @@ static int one_step(const orc_params *p, const double *gw, double *f, double *wo
             for (int a = 0; a < 9; ++a) fin[a] = f[a * N + i];
             collide_at(p, fin, rho[i], psi[i], Fm, F, v, fo);
             for (int a = 0; a < 9; ++a) fs[a * N + i] = fo[a];
+            Ft[i] = F[0];
+            Ft[N + i] = F[1];
         }
     }
 
-    /* S8, Eq. (5) with halfway bounce-back: f_a(x, t+1) = f*_a(x - e_a) when x - e_a is fluid,
-     * otherwise the population reflected at the wall, f*_opp(a)(x). */
+    /* S8, Eq. (5): f_a(x, t+1) = f*_a(x - e_a) when x - e_a is fluid. Otherwise, with halfway
+     * bounce-back, the population reflected at the wall, f*_opp(a)(x); with the wet-node scheme
+     * the populations from the solid are reconstructed from the streamed ones (wet_node). */
 #pragma omp parallel for
     for (int y = 0; y < ny; ++y) {
         for (int x = 0; x < nx; ++x) {
@@ -290,12 +317,19 @@ static int one_step(const orc_params *p, const double *gw, double *f, double *wo
                 for (int a = 0; a < 9; ++a) f[a * N + i] = 0.0;
                 continue;
             }
+            double fn[9];
             for (int a = 0; a < 9; ++a) {
                 int xs = wrap(x - EX[a], nx);
                 int ys = p->walls ? y - EY[a] : wrap(y - EY[a], ny);
-                if (is_solid(p, ys)) f[a * N + i] = fs[OPP[a] * N + i];
-                else f[a * N + i] = fs[a * N + (size_t)ys * nx + xs];
+                if (is_solid(p, ys)) fn[a] = p->walls == 2 ? 0.0 : fs[OPP[a] * N + i];
+                else fn[a] = fs[a * N + (size_t)ys * nx + xs];
             }
+            if (p->walls == 2 && (y == 1 || y == ny - 2)) {
+                const double F[2] = {Ft[i], Ft[N + i]};
+                if (y == 1) wet_node(1, F, fn);
+                if (y == ny - 2) wet_node(0, F, fn);
+            }
+            for (int a = 0; a < 9; ++a) f[a * N + i] = fn[a];
         }
     }
     return ORC_OK;
@@ -303,7 +337,8 @@ static int one_step(const orc_params *p, const double *gw, double *f, double *wo
 
 static int check(const orc_params *p)
 {
-    if (!p || p->nx < 3 || p->ny < (p->walls ? 4 : 3)) return ORC_E_INVAL;
+    if (!p || p->nx < 3 || p->ny < (p->walls ? 4 : 3) || p->walls < 0 || p->walls > 2)
+        return ORC_E_INVAL;
     return ORC_OK;
 }
 
@@ -313,7 +348,7 @@ int orc_run(const orc_params *p, const double *gw, double *f, int64_t nsteps)
     int rc = check(p);
     if (rc) return rc;
     const size_t N = (size_t)p->nx * p->ny;
-    double *work = (double *)malloc(11 * N * sizeof(double));
+    double *work = (double *)malloc(13 * N * sizeof(double));
     if (!work) return ORC_E_NOMEM;
     for (int64_t n = 0; n < nsteps && rc == ORC_OK; ++n) rc = one_step(p, gw, f, work);
     free(work);

@@ -3,8 +3,10 @@
 The hot path lives in liblbm.so (HIP kernels behind the C ABI of include/lbm.h); this package is
 its thin Python binding.
 """
-from .lbm import (ABI_VERSION, EOS, SCHEDULE, WALL, Batch, LBMError, Obs, Params, Sim,  # noqa: F401
-                  Tune, autotune, cs_temperature, lib, make_params, maxwell_cs, workspace_size)
+from .lbm import (ABI_VERSION, EOS, SCHEDULE, WALL, WALLS, Batch, LBMError, Obs, Params,  # noqa: F401
+                  Sim, Tune, autotune, cs_temperature, lib, make_params, maxwell_cs,
+                  piecewise_spinodals, workspace_size)
 
-__all__ = ["Sim", "Batch", "Tune", "autotune", "Params", "Obs", "LBMError", "make_params", "maxwell_cs", "cs_temperature",
-           "workspace_size", "lib", "WALL", "EOS", "SCHEDULE", "ABI_VERSION"]
+__all__ = ["Sim", "Batch", "Tune", "autotune", "Params", "Obs", "LBMError", "make_params",
+           "maxwell_cs", "cs_temperature", "piecewise_spinodals", "workspace_size", "lib", "WALL",
+           "WALLS", "EOS", "SCHEDULE", "ABI_VERSION"]

@@ -81,7 +81,7 @@ int validate(const lbm_params* p, std::string* msg) {
         if (msg) *msg = "abi_version mismatch";
         return LBM_E_ABI;
     }
-    if (p->walls != 0 && p->walls != 1) return bad("walls must be 0 or 1");
+    if (p->walls < LBM_PERIODIC || p->walls > LBM_WALLS_WET_NODE) return bad("walls must be 0, 1 or 2");
     if (p->ghost_psi != 0 && p->ghost_psi != 1) return bad("ghost_psi must be 0 or 1");
     if (p->nx < 3) return bad("nx must be >= 3");
     if (p->ny < (p->walls ? 4 : 3)) return bad("ny must be >= 4 with walls (>= 3 without)");
@@ -113,6 +113,7 @@ KParams kparams_of(const lbm_params* p, const Layout& L) {
     KParams k{};
     k.nx = p->nx; k.ny = p->ny; k.pitch = L.pitch; k.plane = L.plane;
     k.walls = p->walls; k.ghost = p->ghost_psi; k.eos = p->eos; k.wall_force = p->wall_force;
+    k.wet = p->walls == LBM_WALLS_WET_NODE ? 1 : 0;
     k.y_lo = p->walls ? 1 : 0;
     k.y_hi = p->walls ? p->ny - 2 : p->ny - 1;
     k.RT = p->R * p->T; k.a = p->a; k.b4 = p->b / 4.0;
@@ -300,6 +301,48 @@ int lbm_cs_temperature(double a, double b, double R, double ratio, double* T) {
     return LBM_OK;
 }
 
+// Spinodal densities of the piecewise-linear EOS, Eq. (15), for given coexistence densities
+// (Sec. III). With p0 = rho_v th_v, mechanical equilibrium p(rho_l) = p0 is linear in (rho1, rho2)
+// and fixes rho2(rho1); chemical equilibrium is the equal-area rule
+//   sum over the three linear pieces p = A + th rho of  (A - p0)(1/lo - 1/hi) + th ln(hi/lo) = 0,
+// the closed-form integral of (p - p0)/rho^2 on [lo, hi]. The root in rho1 is bracketed on a
+// logarithmic scan of (rho_v, rho_l) and bisected.
+int lbm_piecewise_spinodals(double rho_v, double rho_l, double th_v, double th_m, double th_l,
+                            double* rho1, double* rho2) {
+    if (!rho1 || !rho2 || !(finite_pos(rho_v) && std::isfinite(rho_l) && rho_l > rho_v) ||
+        !(std::isfinite(th_v) && std::isfinite(th_m) && std::isfinite(th_l)) || !(th_m < th_l))
+        return LBM_E_INVAL;
+    const double p0 = rho_v * th_v;
+    auto r2_of = [&](double r1) { return (p0 - r1 * (th_v - th_m) - th_l * rho_l) / (th_m - th_l); };
+    auto piece = [&](double A, double th, double lo, double hi) {
+        return (A - p0) * (1.0 / lo - 1.0 / hi) + th * std::log(hi / lo);
+    };
+    auto chem = [&](double r1) {
+        const double r2 = r2_of(r1);
+        const double A2 = r1 * (th_v - th_m);
+        const double A3 = A2 + r2 * (th_m - th_l);
+        return piece(0.0, th_v, rho_v, r1) + piece(A2, th_m, r1, r2) + piece(A3, th_l, r2, rho_l);
+    };
+    auto valid = [&](double r1) { const double r2 = r2_of(r1); return r1 < r2 && r2 < rho_l; };
+    const int n = 4000;
+    const double lr = std::log(rho_l / rho_v);
+    double prev = rho_v * (1.0 + 1e-12), fprev = NAN;
+    for (int k = 1; k <= n; ++k) {
+        const double r1 = rho_v * std::exp(lr * k / n);
+        if (!valid(r1)) { fprev = NAN; prev = r1; continue; }
+        const double fc = chem(r1);
+        if (std::isfinite(fprev) && (fc > 0) != (fprev > 0)) {
+            const double r = bisect(chem, prev, r1);
+            *rho1 = r;
+            *rho2 = r2_of(r);
+            return LBM_OK;
+        }
+        prev = r1;
+        fprev = fc;
+    }
+    return LBM_E_INVAL;
+}
+
 int lbm_workspace_size(const lbm_params* p, size_t* bytes) {
     if (!bytes) return LBM_E_INVAL;
     int rc = validate(p, nullptr);
@@ -427,6 +470,10 @@ int64_t lbm_current_step(const lbm_ctx* c) { return c ? c->step : -1; }
 
 // Observables record from the reduced sums of the observables kernel: density extremes,
 // velocity maxima, mass, and the Kasa circle fit solved from its 3x3 normal equations.
+// Height of the bottom wall plane: halfway between solid row 0 and fluid row 1 with bounce-back,
+// on the boundary nodes of row 1 with the wet-node scheme (Sec. III.A).
+static double wall_plane(int32_t walls) { return walls == LBM_WALLS_WET_NODE ? 1.0 : 0.5; }
+
 static void obs_from_sums(const double* q, const lbm::ObsArgs& A, int64_t step, lbm_obs* out) {
     enum { O_MIN = 0, O_MAX, O_U, O_UL, O_MASS, O_BAD, O_N, O_SX, O_SY, O_SXX, O_SYY, O_SXY,
            O_SXR, O_SYR, O_SR };
@@ -462,7 +509,7 @@ static void obs_from_sums(const double* q, const lbm::ObsArgs& A, int64_t step, 
         o.xc = X + A.cx;
         o.yc = Y + A.cy;
         o.r = r;
-        const double cth = (0.5 - o.yc) / r;
+        const double cth = (A.cy - o.yc) / r;  // the shift origin is the wall plane
         if (std::isfinite(cth) && std::fabs(cth) <= 1.0) o.theta_deg = std::acos(cth) * 180.0 / M_PI;
     }
     *out = o;
@@ -474,11 +521,11 @@ int lbm_observables_window(lbm_ctx* c, double x_lo, double x_hi, lbm_obs* out) {
     const KParams& P = c->kp;
     lbm::ObsArgs A;
     A.rho_mid = 0.5 * (c->p.rho_l + c->p.rho_v);
-    A.y_min = 0.5 + 3.0;
+    A.y_min = wall_plane(c->p.walls) + 3.0;
     A.x_lo = x_lo;
     A.x_hi = x_hi;
     A.cx = std::isfinite(x_lo) && std::isfinite(x_hi) ? 0.5 * (x_lo + x_hi) : 0.5 * P.nx;
-    A.cy = 0.5;
+    A.cy = wall_plane(c->p.walls);
     double* rho = c->g[c->cur ^ 1];  // the idle population buffer serves as scratch
     hipError_t e = lbm::launch_rho_psi(P, c->g[c->cur], c->psi, rho, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "observables psi");
@@ -600,7 +647,7 @@ int lbm_adjoint_workspace_size(const lbm_params* p, int64_t nsteps, int32_t K, s
     if (!bytes || nsteps < 1 || K < 1) return LBM_E_INVAL;
     int rc = validate(p, nullptr);
     if (rc) return rc;
-    if (!p->walls) return LBM_E_INVAL;
+    if (p->walls != LBM_WALLS_BOUNCE_BACK) return LBM_E_INVAL;  // objective and adjoint: bounce-back walls
     *bytes = adj_layout_of(p, nsteps, K).total;
     return LBM_OK;
 }
@@ -615,7 +662,7 @@ static int run_loss(lbm_ctx* c, double* sums) {
 }
 
 int lbm_loss(lbm_ctx* c, double w_centroid, double w_wet, double* L) {
-    if (!c || !L || !c->p.walls) return LBM_E_INVAL;
+    if (!c || !L || c->p.walls != LBM_WALLS_BOUNCE_BACK) return LBM_E_INVAL;
     double s[3];
     int rc = run_loss(c, s);
     if (rc) return rc;
@@ -624,7 +671,8 @@ int lbm_loss(lbm_ctx* c, double w_centroid, double w_wet, double* L) {
 }
 
 int lbm_forward_ckpt(lbm_ctx* c, int64_t nsteps, int32_t K, void* d_adj, size_t bytes) {
-    if (!c || !d_adj || nsteps < 1 || K < 1 || !c->p.walls) return LBM_E_INVAL;
+    if (!c || !d_adj || nsteps < 1 || K < 1 || c->p.walls != LBM_WALLS_BOUNCE_BACK)
+        return LBM_E_INVAL;
     AdjLayout A = adj_layout_of(&c->p, nsteps, K);
     if (bytes < A.total) return fail(c, LBM_E_SIZE, "adjoint workspace too small");
     if (((uintptr_t)d_adj) % kAlign) return fail(c, LBM_E_INVAL, "adjoint workspace misaligned");
@@ -646,7 +694,8 @@ int lbm_forward_ckpt(lbm_ctx* c, int64_t nsteps, int32_t K, void* d_adj, size_t 
 
 int lbm_backward(lbm_ctx* c, int64_t nsteps, int32_t K, void* d_adj, size_t bytes,
                  double w_centroid, double w_wet, double* d_grad_gw) {
-    if (!c || !d_adj || !d_grad_gw || nsteps < 1 || K < 1 || !c->p.walls) return LBM_E_INVAL;
+    if (!c || !d_adj || !d_grad_gw || nsteps < 1 || K < 1 || c->p.walls != LBM_WALLS_BOUNCE_BACK)
+        return LBM_E_INVAL;
     AdjLayout A = adj_layout_of(&c->p, nsteps, K);
     if (bytes < A.total) return fail(c, LBM_E_SIZE, "adjoint workspace too small");
     if (c->adj_ws != d_adj || c->adj_nsteps != nsteps || c->adj_K != K ||
@@ -1025,11 +1074,11 @@ int lbm_batch_observables(lbm_batch* b, lbm_obs* out) {
         const lbm::InstDesc& d = b->desc[i];
         lbm::ObsArgs& A = args[i];
         A.rho_mid = 0.5 * (b->p[i].rho_l + b->p[i].rho_v);
-        A.y_min = 3.5;
+        A.y_min = wall_plane(b->p[i].walls) + 3.0;
         A.x_lo = -INFINITY;
         A.x_hi = INFINITY;
         A.cx = 0.5 * P.nx;
-        A.cy = 0.5;
+        A.cy = wall_plane(b->p[i].walls);
         double* rho = d.g[b->cur ^ 1];
         hipError_t e = lbm::launch_rho_psi(P, d.g[b->cur], b->psi[i], rho, b->stream);
         if (e == hipSuccess)

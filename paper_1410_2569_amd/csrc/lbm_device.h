@@ -3,8 +3,13 @@
 // State layout in HBM: two ping-pong buffers g[2], each 9 population planes of ny rows x pitch
 // doubles (x fastest, pitch a multiple of 32 doubles so every row starts on a 256-byte boundary).
 // A buffer holds POST-collision populations f*; the pre-collision f^n of a node is pulled from its
-// neighbours (streaming, Eq. 5), with halfway bounce-back f_a(x) = f*_opp(a)(x) where x - e_a is
-// a solid node. Rows 0 and ny-1 are solid when walls = 1.
+// neighbours (streaming, Eq. 5). Rows 0 and ny-1 are solid when walls != 0. Where x - e_a is a
+// solid node the population is, with walls = 1, the halfway bounce-back f_a(x) = f*_opp(a)(x);
+// with walls = 2 (the non-slip wet-node scheme of Sec. III.A) rows 1 and ny-2 are boundary nodes
+// on the wall planes and the populations arriving from the solid are reconstructed from the
+// streamed ones and the node's force of the step that wrote the buffer. That force (Fx, Fy) is
+// part of the state: planes 0 and 1 of the adjacent solid row hold it, slots no pull reads
+// otherwise.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -14,7 +19,8 @@ namespace lbm {
 // Kernel-side parameters, computed once on the host (lbm_api.cpp) from lbm_params.
 struct KParams {
     int nx, ny, pitch;      // lattice and row pitch (doubles)
-    int walls, ghost;       // solid rows 0 and ny-1; mirrored psi on them
+    int walls, ghost;       // solid rows 0 and ny-1 (1 bounce-back, 2 wet-node); mirrored psi
+    int wet;                // walls == 2
     int eos, wall_force;    // 0 CS / 1 piecewise; 0 rho / 1 psi / 2 psi^2 pre-sum factor
     int y_lo, y_hi;         // fluid rows [y_lo, y_hi]
     int visc_const;         // 1: tau_l == tau_v, use s_nu_c
@@ -62,6 +68,26 @@ __device__ __forceinline__ double psi_of_rho(const KParams& P, double rho) {
     return sqrt(P.two_over_G * (p - rho * (1.0 / 3.0)));
 }
 
+// Non-slip wet-node boundary (Sec. III.A) at a boundary node of the bottom wall plane: the
+// populations arriving from the solid (2, 5, 6) follow from the streamed ones and the node's
+// force (Fx, Fy) so that sum_a e_a f_a + F/2 = 0. The top wall plane is the same rule rotated by
+// 180 degrees (unknowns 4, 7, 8).
+__device__ __forceinline__ void wet_node_bottom(double f[9], double Fx, double Fy) {
+#pragma clang fp contract(off)
+    const double d13 = f[1] - f[3];
+    f[2] = f[4];
+    f[5] = f[7] - 0.5 * d13 - 0.25 * (Fx + Fy);
+    f[6] = f[8] + 0.5 * d13 + 0.25 * (Fx - Fy);
+}
+
+__device__ __forceinline__ void wet_node_top(double f[9], double Fx, double Fy) {
+#pragma clang fp contract(off)
+    const double d13 = f[1] - f[3];
+    f[4] = f[2];
+    f[7] = f[5] + 0.5 * d13 + 0.25 * (Fx + Fy);
+    f[8] = f[6] - 0.5 * d13 - 0.25 * (Fx - Fy);
+}
+
 // Pull the 9 pre-collision populations of fluid node (x, y) from post-collision buffer g.
 // Plane bases are uniform (scalar registers) and in-plane offsets 32-bit unsigned, so loads use
 // scalar-base + 32-bit vector-offset addressing.
@@ -94,6 +120,11 @@ __device__ __forceinline__ void pull9(const KParams& P, const double* __restrict
     f[4] = top ? (g + 2 * pl)[r0 + ux] : (g + 4 * pl)[rp + ux];
     f[7] = top ? (g + 5 * pl)[r0 + ux] : (g + 7 * pl)[rp + xp];
     f[8] = top ? (g + 6 * pl)[r0 + ux] : (g + 8 * pl)[rp + xm];
+    if (P.wet && (bot || top)) {
+        // the slots read above for the unknown populations are overwritten by the reconstruction
+        if (bot) wet_node_bottom(f, g[rm + ux], (g + pl)[rm + ux]);
+        if (top) wet_node_top(f, g[rp + ux], (g + pl)[rp + ux]);
+    }
 }
 
 // The fluid node whose psi a lattice slot (gx, gy) holds: gx wraps (periodic x); a solid row
@@ -162,16 +193,39 @@ __device__ __forceinline__ void cohesion_sum(double pmm, double p0m, double ppm,
     sy = fma(p0p - p0m, 1.0 / 3.0, (dpx - dmx) * (1.0 / 12.0));
 }
 
+// Total force F = F_m + F_ads of one node (Eqs. 7, 10, 11, 14).
+__device__ __forceinline__ void total_force(const KParams& P, double rho, double psi_c, double sx,
+                                            double sy, double Ax, double Ay, double& Fx,
+                                            double& Fy) {
+#pragma clang fp contract(off)
+    const double pre = P.wall_force == 0 ? rho : (P.wall_force == 1 ? psi_c : psi_c * psi_c);
+    Fx = fma(-pre, Ax, P.negG * psi_c * sx);
+    Fy = fma(-pre, Ay, P.negG * psi_c * sy);
+}
+
+// With the wet-node scheme, a boundary node stores its force of this step in planes 0 and 1 of
+// the adjacent solid row of the output buffer (o: the output slot of the node, plane stride pl,
+// row stride W). Other nodes store nothing.
+__device__ __forceinline__ void store_wall_force(const KParams& P, double* out, long long o,
+                                                 long long pl, long long W, int y, double rho,
+                                                 double psi_c, double sx, double sy, double Ax,
+                                                 double Ay) {
+    if (!P.wet || (y != 1 && y != P.ny - 2)) return;
+    double Fx, Fy;
+    total_force(P, rho, psi_c, sx, sy, Ax, Ay, Fx, Fy);
+    if (y == 1) { out[o - W] = Fx; out[pl + o - W] = Fy; }
+    if (y == P.ny - 2) { out[o + W] = Fx; out[pl + o + W] = Fy; }
+}
+
 // Forces, velocity and MRT collision of one node (Eqs. 2-4, 6, 7, 9 and 10/11/14):
 // in f[9] (pre-collision), rho, psi_c, cohesion sum (sx, sy), adhesion sum (Ax, Ay);
 // out f[9] overwritten with f* = M^-1 m*.
 __device__ __forceinline__ void collide(const KParams& P, double f[9], double rho, double psi_c,
                                         double sx, double sy, double Ax, double Ay) {
 #pragma clang fp contract(off)
-    // Eq. (7): F_m = -G psi(x) s;  adhesion pre-sum factor
-    const double fmx = P.negG * psi_c * sx, fmy = P.negG * psi_c * sy;
-    const double pre = P.wall_force == 0 ? rho : (P.wall_force == 1 ? psi_c : psi_c * psi_c);
-    const double Fx = fma(-pre, Ax, fmx), Fy = fma(-pre, Ay, fmy);
+    // Eq. (7) cohesion plus the adhesion of Eq. (10)/(11)/(14)
+    double Fx, Fy;
+    total_force(P, rho, psi_c, sx, sy, Ax, Ay, Fx, Fy);
 
     // moments m = M f (rows rho, e, epsilon, jx, qx, jy, qy, pxx, pxy)
     const double ax = f[1] + f[3], ay = f[2] + f[4];
@@ -244,8 +298,8 @@ __device__ __forceinline__ void velocity(const KParams& P, const double f[9], do
                                          double psi_c, double sx, double sy, double Ax,
                                          double Ay, double& vx, double& vy) {
 #pragma clang fp contract(off)
-    const double pre = P.wall_force == 0 ? rho : (P.wall_force == 1 ? psi_c : psi_c * psi_c);
-    const double Fx = fma(-pre, Ax, P.negG * psi_c * sx), Fy = fma(-pre, Ay, P.negG * psi_c * sy);
+    double Fx, Fy;
+    total_force(P, rho, psi_c, sx, sy, Ax, Ay, Fx, Fy);
     const double d58 = f[5] - f[7], d68 = f[6] - f[8];
     const double jx = (f[1] - f[3]) + d58 - d68;
     const double jy = (f[2] - f[4]) + d58 + d68;
@@ -324,6 +378,8 @@ __device__ __forceinline__ void step_tile(const KParams& P, const double* __rest
                      sx, sy);
         double Ax = 0.0, Ay = 0.0;
         if (P.walls && (y == 1 || y == P.ny - 2)) adhesion_sum(P, gw, x, y, Ax, Ay);
+        store_wall_force(P, gout, (long long)y * P.pitch + x, P.plane, P.pitch, y, rho, psi_c, sx,
+                         sy, Ax, Ay);
         collide(P, f, rho, psi_c, sx, sy, Ax, Ay);
         const unsigned i = (unsigned)y * P.pitch + x;
 #pragma unroll
@@ -356,6 +412,11 @@ __device__ __forceinline__ void pull9_lds(const KParams& P, const double* g1, in
     f[4] = top ? g1[2 * plane + l] : g1[4 * plane + l + W];
     f[7] = top ? g1[5 * plane + l] : g1[7 * plane + l + W + 1];
     f[8] = top ? g1[6 * plane + l] : g1[8 * plane + l + W - 1];
+    if (P.wet && (bot || top)) {
+        // the force of the boundary node sits in the solid-row slot below (bottom) or above (top)
+        if (bot) wet_node_bottom(f, g1[l - W], g1[plane + l - W]);
+        if (top) wet_node_top(f, g1[l + W], g1[plane + l + W]);
+    }
 }
 
 template <int TX, int TY>
@@ -432,6 +493,10 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
                      sx, sy);
         double Ax = 0.0, Ay = 0.0;
         if (P.walls && (gy == 1 || gy == P.ny - 2)) adhesion_sum(P, gw, gx, gy, Ax, Ay);
+        // a boundary node's force feeds the reconstruction of step n+2, which only nodes of R1
+        // perform; those have their solid-row slot inside R2
+        if (P.wet && ly >= 1 && ly <= H2 - 2)
+            store_wall_force(P, g1, s, PL, W2, gy, rk[r], c[0], sx, sy, Ax, Ay);
         collide(P, fk[r], rk[r], c[0], sx, sy, Ax, Ay);
 #pragma unroll
         for (int a = 0; a < 9; ++a) g1[a * PL + s] = fk[r][a];
@@ -468,6 +533,8 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
                      sx, sy);
         double Ax = 0.0, Ay = 0.0;
         if (P.walls && (y == 1 || y == P.ny - 2)) adhesion_sum(P, gw, x, y, Ax, Ay);
+        store_wall_force(P, gout, (long long)y * P.pitch + x, P.plane, P.pitch, y, rho, c[0], sx,
+                         sy, Ax, Ay);
         collide(P, f, rho, c[0], sx, sy, Ax, Ay);
         const unsigned i = (unsigned)y * P.pitch + x;
 #pragma unroll

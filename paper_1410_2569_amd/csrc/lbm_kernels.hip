@@ -8,6 +8,9 @@
 //             written per lattice update.
 //   two-pass  psi pass (pull, rho, psi -> psi array with mirrored ghost rows), then the step
 //             kernel stages the psi tile plus halo in LDS: 72 + 8 B and 72 + 8 + 72 B per update.
+//   two-step  two time steps per launch with the intermediate state in LDS (step2_tile).
+// With the wet-node wall scheme the boundary nodes also write their force (16 B) to the solid row,
+// which the next pull reads back; that traffic is confined to two rows of the lattice.
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
@@ -68,6 +71,8 @@ __global__ __launch_bounds__(64 * (TYI + 2)) void k_step_ov(KParams P,
                  syy);
     double Ax = 0.0, Ay = 0.0;
     if (P.walls && (gy == 1 || gy == P.ny - 2)) adhesion_sum(P, gw, gx, gy, Ax, Ay);
+    store_wall_force(P, gout, (long long)gy * P.pitch + gx, P.plane, P.pitch, gy, rho, psi_c, sxx,
+                     syy, Ax, Ay);
     collide(P, f, rho, psi_c, sxx, syy, Ax, Ay);
     const unsigned i = (unsigned)gy * P.pitch + gx;
 #pragma unroll

@@ -19,6 +19,7 @@ ABI_VERSION = 1
 OK, E_INVAL, E_SIZE, E_HIP, E_NONFINITE, E_ABI, E_STATE = 0, -1, -2, -3, -4, -5, -6
 WALL = {"rho": 0, "psi": 1, "modpsi": 2}
 EOS = {"cs": 0, "piecewise": 1}
+WALLS = {"periodic": 0, "bounce_back": 1, "wet_node": 2}
 SCHEDULE = {"fused": 0, "two_pass": 1, "two_step": 2}
 
 
@@ -66,6 +67,7 @@ _P = C.POINTER(Params)
 SIGNATURES = {
     "lbm_maxwell_cs": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double, _dp, _dp, _dp]),
     "lbm_cs_temperature": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double, _dp]),
+    "lbm_piecewise_spinodals": (C.c_int, [C.c_double] * 5 + [_dp, _dp]),
     "lbm_workspace_size": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
     "lbm_create": (C.c_int, [_P, _dp, _dp, C.c_void_p, C.c_size_t, C.c_void_p,
                              C.POINTER(C.c_void_p)]),
@@ -150,18 +152,32 @@ def cs_temperature(a: float, b: float, R: float, ratio: float) -> float:
     return T.value
 
 
+def piecewise_spinodals(rho_v: float, rho_l: float, th_v: float, th_m: float, th_l: float):
+    """(rho1, rho2) of Eq. (15) for coexistence densities (rho_v, rho_l) (library's solver)."""
+    r1, r2 = C.c_double(), C.c_double()
+    check(lib().lbm_piecewise_spinodals(rho_v, rho_l, th_v, th_m, th_l, C.byref(r1),
+                                        C.byref(r2)))
+    return r1.value, r2.value
+
+
 def make_params(p: dict) -> Params:
     """C parameter block from a parameter dict (keys as in synth.base_params). rho_l/rho_v
-    default to the library's own Maxwell construction for the Carnahan-Starling EOS."""
+    default to the library's own Maxwell construction for the Carnahan-Starling EOS; rho1/rho2
+    of Eq. (15) to the library's spinodal solver. walls: 0 periodic, 1 bounce-back, 2 wet-node
+    (or the names in WALLS)."""
     q = Params()
     q.abi_version = ABI_VERSION
     q.nx, q.ny = int(p["nx"]), int(p["ny"])
-    q.walls = int(p.get("walls", 1))
+    w = p.get("walls", 1)
+    q.walls = WALLS[w] if isinstance(w, str) else int(w)
     q.ghost_psi = int(p.get("ghost", 1))
     q.eos = EOS[p.get("eos", "cs")]
     q.wall_force = WALL[p.get("wall_force", "psi")]
     for k in ("a", "b", "R", "T", "rho1", "rho2", "th_v", "th_m", "th_l"):
         setattr(q, k, float(p.get(k, 0.0)))
+    if q.eos == EOS["piecewise"] and "rho1" not in p:
+        q.rho1, q.rho2 = piecewise_spinodals(float(p["rho_v"]), float(p["rho_l"]), q.th_v,
+                                             q.th_m, q.th_l)
     q.G = float(p.get("G", -1.0))
     q.sigma = float(p["sigma"])
     for k in ("s_rho", "s_e", "s_zeta", "s_j", "s_q", "tau_l", "tau_v"):

@@ -61,7 +61,7 @@ def test_workspace_size_scales(L):
 
 
 @pytest.mark.parametrize("field,value,code", [
-    ("abi_version", 99, -5), ("nx", 2, -1), ("ny", 3, -1), ("walls", 2, -1),
+    ("abi_version", 99, -5), ("nx", 2, -1), ("ny", 3, -1), ("walls", 3, -1), ("walls", -1, -1),
     ("ghost_psi", 7, -1), ("eos", 5, -1), ("wall_force", 3, -1), ("reserved", 1, -1),
     ("G", 1.0, -1), ("G", float("nan"), -1), ("sigma", float("inf"), -1),
     ("s_e", 0.0, -1), ("s_q", 2.0, -1), ("tau_l", 0.5, -1), ("tau_v", 0.4, -1),
@@ -78,6 +78,17 @@ def test_invalid_parameters_rejected_without_gpu(L, field, value, code):
     rc = L.lib().lbm_create(C.byref(q), gw.ctypes.data_as(dp), rho0.ctypes.data_as(dp),
                             C.c_void_p(256), 1 << 40, None, C.byref(h))
     assert rc == code and not h.value
+
+
+def test_wet_node_accepted_but_not_for_the_adjoint(L):
+    """walls = 2 (wet-node scheme) is a valid geometry; the objective and adjoint support
+    bounce-back walls only and say so before any GPU call."""
+    q = good_params(L, walls=2)
+    n = C.c_size_t()
+    assert L.lib().lbm_workspace_size(C.byref(q), C.byref(n)) == 0
+    assert L.lib().lbm_adjoint_workspace_size(C.byref(q), 100, 10, C.byref(n)) == -1
+    q = good_params(L, walls=1)
+    assert L.lib().lbm_adjoint_workspace_size(C.byref(q), 100, 10, C.byref(n)) == 0
 
 
 def test_create_rejects_bad_buffers_without_gpu(L):
