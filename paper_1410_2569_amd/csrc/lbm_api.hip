@@ -780,6 +780,7 @@ struct lbm_batch {
     int64_t step;
     lbm_tune tune;
     int grid;  // persistent grid size
+    bool wet;  // some instance uses the wet-node wall
     hipGraphExec_t graph[2];  // per-step schedule: kGraphChunk launches starting at parity 0 / 1
     hipGraphExec_t pgraph;    // persistent schedule: reset + persistent kernel for pgraph_n steps
     int64_t pgraph_n;
@@ -891,6 +892,8 @@ int lbm_batch_create(const lbm_params* p, int32_t count, const double* const* gw
     b->d_bar = (unsigned*)(b->ws + B.off_bar);
     b->d_flag = (int*)(b->ws + B.off_bar + 64);
     b->ntiles = B.ntiles;
+    b->wet = false;
+    for (int i = 0; i < count; ++i) b->wet = b->wet || p[i].walls == LBM_WALLS_WET_NODE;
     b->cur = 0;
     b->step = 0;
     b->tune = tn;
@@ -958,16 +961,16 @@ int lbm_batch_create(const lbm_params* p, int32_t count, const double* const* gw
 static int batch_direct(lbm_batch* b, int64_t n) {
     if (b->tune.schedule == 2) {
         for (; n >= 2; n -= 2) {
-            hipError_t e = lbm::launch_batch_step2(b->tune.tile, b->d_inst, b->d_tile_inst,
-                                                   b->ntiles, b->cur, b->stream);
+            hipError_t e = lbm::launch_batch_step2(b->tune.tile, b->wet, b->d_inst,
+                                                   b->d_tile_inst, b->ntiles, b->cur, b->stream);
             if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, std::string("batch step: ") + hipGetErrorString(e));
             b->cur ^= 1;
             b->step += 2;
         }
     }
     for (int64_t i = 0; i < n; ++i) {
-        hipError_t e = lbm::launch_batch_step(b->tune.tile, b->d_inst, b->d_tile_inst, b->ntiles,
-                                              b->cur, b->stream);
+        hipError_t e = lbm::launch_batch_step(b->tune.tile, b->wet, b->d_inst, b->d_tile_inst,
+                                              b->ntiles, b->cur, b->stream);
         if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, std::string("batch step: ") + hipGetErrorString(e));
         b->cur ^= 1;
         b->step += 1;
@@ -1010,9 +1013,9 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
         if (n > (int64_t)1 << 30) return batch_fail(b, LBM_E_INVAL, "too many steps in one call");
         const int cur = b->cur;
         auto persistent = [&]() {
-            return lbm::launch_batch_persistent(b->tune.tile, b->grid, b->d_inst, b->d_tile_inst,
-                                                b->ntiles, (int)n, cur, b->d_bar, b->d_flag,
-                                                kSpinLimit, b->stream);
+            return lbm::launch_batch_persistent(b->tune.tile, b->wet, b->grid, b->d_inst,
+                                                b->d_tile_inst, b->ntiles, (int)n, cur, b->d_bar,
+                                                b->d_flag, kSpinLimit, b->stream);
         };
         if (!b->pgraph || b->pgraph_n != n || b->pgraph_cur != cur) {
             if (b->pgraph) { (void)hipGraphExecDestroy(b->pgraph); b->pgraph = nullptr; }
@@ -1035,10 +1038,10 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
             int rc = capture(b, &b->graph[cur], [&]() {
                 const bool two = b->tune.schedule == 2;  // two steps per launch
                 for (int i = 0; i < (two ? kGraphChunk / 2 : kGraphChunk); ++i) {
-                    hipError_t e = two ? lbm::launch_batch_step2(b->tune.tile, b->d_inst,
+                    hipError_t e = two ? lbm::launch_batch_step2(b->tune.tile, b->wet, b->d_inst,
                                                                  b->d_tile_inst, b->ntiles,
                                                                  (cur + i) & 1, b->stream)
-                                       : lbm::launch_batch_step(b->tune.tile, b->d_inst,
+                                       : lbm::launch_batch_step(b->tune.tile, b->wet, b->d_inst,
                                                                 b->d_tile_inst, b->ntiles,
                                                                 (cur + i) & 1, b->stream);
                     if (e != hipSuccess) return e;

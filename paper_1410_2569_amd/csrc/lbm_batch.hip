@@ -20,7 +20,8 @@ __device__ __forceinline__ void batch_tile_origin(const InstDesc* D, int t, int 
     y0 = D->P.y_lo + (lt / D->ntx) * TY;
 }
 
-template <int TX, int TY>
+// WET: compiled with the wet-node wall rule (launched when some instance uses wall mode 2).
+template <int TX, int TY, bool WET>
 __global__ __launch_bounds__(TX* TY) void k_batch_step(const InstDesc* __restrict__ inst,
                                                        const int* __restrict__ tile_inst,
                                                        int ntiles, int cur) {
@@ -29,11 +30,11 @@ __global__ __launch_bounds__(TX* TY) void k_batch_step(const InstDesc* __restric
     const InstDesc* D = inst + tile_inst[t];
     int x0, y0;
     batch_tile_origin(D, t, TX, TY, x0, y0);
-    step_tile<TX, TY, true>(D->P, D->g[cur], D->g[cur ^ 1], nullptr, D->gw, x0, y0, sp);
+    step_tile<TX, TY, true, WET>(D->P, D->g[cur], D->g[cur ^ 1], nullptr, D->gw, x0, y0, sp);
 }
 
 // Two steps per launch over the work-list (the tiles are the output tiles of step2_tile).
-template <int TX, int TY>
+template <int TX, int TY, bool WET>
 __global__ __launch_bounds__(TX* TY) void k_batch_step2(const InstDesc* __restrict__ inst,
                                                         const int* __restrict__ tile_inst,
                                                         int ntiles, int cur) {
@@ -42,7 +43,7 @@ __global__ __launch_bounds__(TX* TY) void k_batch_step2(const InstDesc* __restri
     const InstDesc* D = inst + tile_inst[t];
     int x0, y0;
     batch_tile_origin(D, t, TX, TY, x0, y0);
-    step2_tile<TX, TY>(D->P, D->g[cur], D->g[cur ^ 1], D->gw, x0, y0, lds);
+    step2_tile<TX, TY, WET>(D->P, D->g[cur], D->g[cur ^ 1], D->gw, x0, y0, lds);
 }
 
 // Grid-wide barrier number `target / gridDim.x`. Returns false when the run was aborted.
@@ -74,7 +75,7 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, int
     return *verdict != 0;
 }
 
-template <int TX, int TY>
+template <int TX, int TY, bool WET>
 __global__ __launch_bounds__(TX* TY) void k_batch_persistent(const InstDesc* __restrict__ inst,
                                                              const int* __restrict__ tile_inst,
                                                              int ntiles, int nsteps, int cur0,
@@ -92,7 +93,8 @@ __global__ __launch_bounds__(TX* TY) void k_batch_persistent(const InstDesc* __r
             const InstDesc* D = inst + tile_inst[t];
             int x0, y0;
             batch_tile_origin(D, t, TX, TY, x0, y0);
-            step_tile<TX, TY, true>(D->P, D->g[cur], D->g[cur ^ 1], nullptr, D->gw, x0, y0, sp);
+            step_tile<TX, TY, true, WET>(D->P, D->g[cur], D->g[cur ^ 1], nullptr, D->gw, x0, y0,
+                                         sp);
             __syncthreads();  // the LDS tile is reused by the next tile
         }
         if (!grid_barrier(bar, (unsigned)(s + 1) * (unsigned)G, flag, spin_limit, &verdict)) return;
@@ -110,72 +112,90 @@ __global__ void k_batch_reset(unsigned* bar, int* flag) {
 
 // ------------------------------------------------------------------------------------------------
 template <int TX, int TY>
-static hipError_t launch_batch_t(const InstDesc* inst, const int* tile_inst, int ntiles, int cur,
-                                 hipStream_t s) {
-    hipLaunchKernelGGL((k_batch_step<TX, TY>), dim3(ntiles), dim3(TX * TY), 0, s, inst, tile_inst,
-                       ntiles, cur);
+static hipError_t launch_batch_t(bool wet, const InstDesc* inst, const int* tile_inst, int ntiles,
+                                 int cur, hipStream_t s) {
+    if (wet)
+        hipLaunchKernelGGL((k_batch_step<TX, TY, true>), dim3(ntiles), dim3(TX * TY), 0, s, inst,
+                           tile_inst, ntiles, cur);
+    else
+        hipLaunchKernelGGL((k_batch_step<TX, TY, false>), dim3(ntiles), dim3(TX * TY), 0, s, inst,
+                           tile_inst, ntiles, cur);
     return hipGetLastError();
 }
 
 template <int TX, int TY>
-static hipError_t launch_persist_t(int grid, const InstDesc* inst, const int* tile_inst,
+static hipError_t launch_persist_t(bool wet, int grid, const InstDesc* inst, const int* tile_inst,
                                    int ntiles, int nsteps, int cur, unsigned* bar, int* flag,
                                    int spin_limit, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, bar, flag);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_batch_persistent<TX, TY>), dim3(grid), dim3(TX * TY), 0, s, inst,
-                       tile_inst, ntiles, nsteps, cur, bar, flag, spin_limit);
+    if (wet)
+        hipLaunchKernelGGL((k_batch_persistent<TX, TY, true>), dim3(grid), dim3(TX * TY), 0, s,
+                           inst, tile_inst, ntiles, nsteps, cur, bar, flag, spin_limit);
+    else
+        hipLaunchKernelGGL((k_batch_persistent<TX, TY, false>), dim3(grid), dim3(TX * TY), 0, s,
+                           inst, tile_inst, ntiles, nsteps, cur, bar, flag, spin_limit);
     return hipGetLastError();
 }
 
+// Resident workgroups per CU of the persistent kernel (the smaller of its two variants, so a
+// grid sized by it fits whichever is launched).
 template <int TX, int TY>
 static int occupancy_t() {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_persistent<TX, TY>, TX * TY, 0) !=
-        hipSuccess)
+    int a = 0, b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_batch_persistent<TX, TY, false>,
+                                                     TX * TY, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_batch_persistent<TX, TY, true>,
+                                                     TX * TY, 0) != hipSuccess)
         return 0;
-    return n;
+    return a < b ? a : b;
 }
 
 int batch_tiles(int tile) { return tile >= 0 && tile < 4; }
 
 // Two steps per launch (schedule 2): tile 0 -> 64x8 output tiles, tile 3 -> 64x16; the work-list
 // must have been built for that tile shape.
-hipError_t launch_batch_step2(int tile, const InstDesc* inst, const int* tile_inst, int ntiles,
-                              int cur, hipStream_t s) {
-    if (tile == 2) {
-        hipLaunchKernelGGL((k_batch_step2<64, 16>), dim3(ntiles), dim3(64 * 16), 0, s, inst,
+template <int TX, int TY>
+static hipError_t launch_batch2_t(bool wet, const InstDesc* inst, const int* tile_inst, int ntiles,
+                                  int cur, hipStream_t s) {
+    if (wet)
+        hipLaunchKernelGGL((k_batch_step2<TX, TY, true>), dim3(ntiles), dim3(TX * TY), 0, s, inst,
                            tile_inst, ntiles, cur);
-    } else {
-        hipLaunchKernelGGL((k_batch_step2<64, 8>), dim3(ntiles), dim3(64 * 8), 0, s, inst,
+    else
+        hipLaunchKernelGGL((k_batch_step2<TX, TY, false>), dim3(ntiles), dim3(TX * TY), 0, s, inst,
                            tile_inst, ntiles, cur);
-    }
     return hipGetLastError();
 }
 
-hipError_t launch_batch_step(int tile, const InstDesc* inst, const int* tile_inst, int ntiles,
-                             int cur, hipStream_t s) {
+hipError_t launch_batch_step2(int tile, bool wet, const InstDesc* inst, const int* tile_inst,
+                              int ntiles, int cur, hipStream_t s) {
+    if (tile == 2) return launch_batch2_t<64, 16>(wet, inst, tile_inst, ntiles, cur, s);
+    return launch_batch2_t<64, 8>(wet, inst, tile_inst, ntiles, cur, s);
+}
+
+hipError_t launch_batch_step(int tile, bool wet, const InstDesc* inst, const int* tile_inst,
+                             int ntiles, int cur, hipStream_t s) {
     switch (tile) {
-        case 1: return launch_batch_t<64, 8>(inst, tile_inst, ntiles, cur, s);
-        case 2: return launch_batch_t<64, 16>(inst, tile_inst, ntiles, cur, s);
-        case 3: return launch_batch_t<128, 4>(inst, tile_inst, ntiles, cur, s);
-        default: return launch_batch_t<64, 4>(inst, tile_inst, ntiles, cur, s);
+        case 1: return launch_batch_t<64, 8>(wet, inst, tile_inst, ntiles, cur, s);
+        case 2: return launch_batch_t<64, 16>(wet, inst, tile_inst, ntiles, cur, s);
+        case 3: return launch_batch_t<128, 4>(wet, inst, tile_inst, ntiles, cur, s);
+        default: return launch_batch_t<64, 4>(wet, inst, tile_inst, ntiles, cur, s);
     }
 }
 
-hipError_t launch_batch_persistent(int tile, int grid, const InstDesc* inst,
+hipError_t launch_batch_persistent(int tile, bool wet, int grid, const InstDesc* inst,
                                    const int* tile_inst, int ntiles, int nsteps, int cur,
                                    unsigned* bar, int* flag, int spin_limit, hipStream_t s) {
     switch (tile) {
-        case 1: return launch_persist_t<64, 8>(grid, inst, tile_inst, ntiles, nsteps, cur, bar,
-                                               flag, spin_limit, s);
-        case 2: return launch_persist_t<64, 16>(grid, inst, tile_inst, ntiles, nsteps, cur, bar,
-                                                flag, spin_limit, s);
-        case 3: return launch_persist_t<128, 4>(grid, inst, tile_inst, ntiles, nsteps, cur, bar,
-                                                flag, spin_limit, s);
-        default: return launch_persist_t<64, 4>(grid, inst, tile_inst, ntiles, nsteps, cur, bar,
-                                                flag, spin_limit, s);
+        case 1: return launch_persist_t<64, 8>(wet, grid, inst, tile_inst, ntiles, nsteps, cur,
+                                               bar, flag, spin_limit, s);
+        case 2: return launch_persist_t<64, 16>(wet, grid, inst, tile_inst, ntiles, nsteps, cur,
+                                                bar, flag, spin_limit, s);
+        case 3: return launch_persist_t<128, 4>(wet, grid, inst, tile_inst, ntiles, nsteps, cur,
+                                                bar, flag, spin_limit, s);
+        default: return launch_persist_t<64, 4>(wet, grid, inst, tile_inst, ntiles, nsteps, cur,
+                                                bar, flag, spin_limit, s);
     }
 }
 

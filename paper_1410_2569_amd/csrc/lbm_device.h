@@ -90,7 +90,9 @@ __device__ __forceinline__ void wet_node_top(double f[9], double Fx, double Fy) 
 
 // Pull the 9 pre-collision populations of fluid node (x, y) from post-collision buffer g.
 // Plane bases are uniform (scalar registers) and in-plane offsets 32-bit unsigned, so loads use
-// scalar-base + 32-bit vector-offset addressing.
+// scalar-base + 32-bit vector-offset addressing. WET = false compiles the wet-node rule out (for
+// launches known to use another wall mode); WET = true applies it where P.wet says so.
+template <bool WET = true>
 __device__ __forceinline__ void pull9(const KParams& P, const double* __restrict__ g, int x,
                                       int y, double f[9]) {
     const unsigned nx = P.nx, pitch = P.pitch;
@@ -120,7 +122,7 @@ __device__ __forceinline__ void pull9(const KParams& P, const double* __restrict
     f[4] = top ? (g + 2 * pl)[r0 + ux] : (g + 4 * pl)[rp + ux];
     f[7] = top ? (g + 5 * pl)[r0 + ux] : (g + 7 * pl)[rp + xp];
     f[8] = top ? (g + 6 * pl)[r0 + ux] : (g + 8 * pl)[rp + xm];
-    if (P.wet && (bot || top)) {
+    if (WET && P.wet && (bot || top)) {
         // the slots read above for the unknown populations are overwritten by the reconstruction
         if (bot) wet_node_bottom(f, g[rm + ux], (g + pl)[rm + ux]);
         if (top) wet_node_top(f, g[rp + ux], (g + pl)[rp + ux]);
@@ -144,13 +146,14 @@ __device__ __forceinline__ bool slot_source(const KParams& P, int gx, int gy, in
 }
 
 // psi at lattice position (gx, gy) (see slot_source), evaluated from the pulled populations.
+template <bool WET = true>
 __device__ __forceinline__ double psi_at(const KParams& P, const double* __restrict__ g, int gx,
                                          int gy) {
 #pragma clang fp contract(off)
     int sx, sy;
     if (!slot_source(P, gx, gy, sx, sy)) return 0.0;
     double f[9];
-    pull9(P, g, sx, sy, f);
+    pull9<WET>(P, g, sx, sy, f);
     return psi_of_rho(P, ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8]);
 }
 
@@ -206,11 +209,12 @@ __device__ __forceinline__ void total_force(const KParams& P, double rho, double
 // With the wet-node scheme, a boundary node stores its force of this step in planes 0 and 1 of
 // the adjacent solid row of the output buffer (o: the output slot of the node, plane stride pl,
 // row stride W). Other nodes store nothing.
+template <bool WET = true>
 __device__ __forceinline__ void store_wall_force(const KParams& P, double* out, long long o,
                                                  long long pl, long long W, int y, double rho,
                                                  double psi_c, double sx, double sy, double Ax,
                                                  double Ay) {
-    if (!P.wet || (y != 1 && y != P.ny - 2)) return;
+    if (!WET || !P.wet || (y != 1 && y != P.ny - 2)) return;
     double Fx, Fy;
     total_force(P, rho, psi_c, sx, sy, Ax, Ay, Fx, Fy);
     if (y == 1) { out[o - W] = Fx; out[pl + o - W] = Fy; }
@@ -324,7 +328,7 @@ namespace lbm {
 // threads with the LDS array sp of (TY + 2) * (TX + 2) doubles. FUSED: psi of the tile and its
 // halo is evaluated from the pulled populations; otherwise it is staged from psi_g. Contains
 // __syncthreads() and no early return, so it can run inside loops over tiles.
-template <int TX, int TY, bool FUSED>
+template <int TX, int TY, bool FUSED, bool WET>
 __device__ __forceinline__ void step_tile(const KParams& P, const double* __restrict__ gin,
                                           double* __restrict__ gout,
                                           const double* __restrict__ psi_g,
@@ -340,20 +344,20 @@ __device__ __forceinline__ void step_tile(const KParams& P, const double* __rest
     double f[9];
     double rho = 1.0, psi_c = 0.0;
     if (active) {
-        pull9(P, gin, x, y, f);
+        pull9<WET>(P, gin, x, y, f);
         rho = sum9(f);
         if (FUSED) psi_c = psi_of_rho(P, rho);
     }
     if (FUSED) {
         // own slot: computed above, or (outside the fluid) the value at that lattice position
-        sp[(ty + 1) * LW + tx + 1] = active ? psi_c : psi_at(P, gin, x, y);
+        sp[(ty + 1) * LW + tx + 1] = active ? psi_c : psi_at<WET>(P, gin, x, y);
         for (int h = threadIdx.x; h < NH; h += NT) {
             int hx, hy;  // tile-local coordinates in [-1, TX] x [-1, TY]
             if (h < LW) { hx = h - 1; hy = -1; }
             else if (h < 2 * LW) { hx = h - LW - 1; hy = TY; }
             else if (h < 2 * LW + TY) { hx = -1; hy = h - 2 * LW; }
             else { hx = TX; hy = h - 2 * LW - TY; }
-            sp[(hy + 1) * LW + hx + 1] = psi_at(P, gin, x0 + hx, y0 + hy);
+            sp[(hy + 1) * LW + hx + 1] = psi_at<WET>(P, gin, x0 + hx, y0 + hy);
         }
     } else {
         // stage psi (ghost rows already mirrored by the psi pass) with its halo
@@ -378,8 +382,8 @@ __device__ __forceinline__ void step_tile(const KParams& P, const double* __rest
                      sx, sy);
         double Ax = 0.0, Ay = 0.0;
         if (P.walls && (y == 1 || y == P.ny - 2)) adhesion_sum(P, gw, x, y, Ax, Ay);
-        store_wall_force(P, gout, (long long)y * P.pitch + x, P.plane, P.pitch, y, rho, psi_c, sx,
-                         sy, Ax, Ay);
+        store_wall_force<WET>(P, gout, (long long)y * P.pitch + x, P.plane, P.pitch, y, rho,
+                              psi_c, sx, sy, Ax, Ay);
         collide(P, f, rho, psi_c, sx, sy, Ax, Ay);
         const unsigned i = (unsigned)y * P.pitch + x;
 #pragma unroll
@@ -399,6 +403,7 @@ namespace lbm {
 //   D  step n+2 on the tile, pulling from g1                              -> gout
 // HBM sees one read and one write of the populations per two steps. Every node's arithmetic is
 // that of step_tile, so two launches of k_step and one of k_step2 give identical bits.
+template <bool WET>
 __device__ __forceinline__ void pull9_lds(const KParams& P, const double* g1, int plane, int W,
                                           int l, int gy, double f[9]) {
     // l: local index of the node in the LDS grid (row stride W); gy: its global row
@@ -412,7 +417,7 @@ __device__ __forceinline__ void pull9_lds(const KParams& P, const double* g1, in
     f[4] = top ? g1[2 * plane + l] : g1[4 * plane + l + W];
     f[7] = top ? g1[5 * plane + l] : g1[7 * plane + l + W + 1];
     f[8] = top ? g1[6 * plane + l] : g1[8 * plane + l + W - 1];
-    if (P.wet && (bot || top)) {
+    if (WET && P.wet && (bot || top)) {
         // the force of the boundary node sits in the solid-row slot below (bottom) or above (top)
         if (bot) wet_node_bottom(f, g1[l - W], g1[plane + l - W]);
         if (top) wet_node_top(f, g1[l + W], g1[plane + l + W]);
@@ -428,7 +433,7 @@ struct Step2Lds {
     double ps2[W1 * H1];
 };
 
-template <int TX, int TY>
+template <int TX, int TY, bool WET>
 __device__ __forceinline__ void step2_tile(const KParams& P, const double* __restrict__ gin,
                                            double* __restrict__ gout,
                                            const double* __restrict__ gw, int x0, int y0,
@@ -459,12 +464,12 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
         if (P.walls) fluid = gy >= 1 && gy <= P.ny - 2;
         else { gy = wrapx(gy, P.ny); fluid = true; }
         if (fluid) {
-            pull9(P, gin, wrapx(x0 - 2 + lx, P.nx), gy, fk[r]);
+            pull9<WET>(P, gin, wrapx(x0 - 2 + lx, P.nx), gy, fk[r]);
             rk[r] = sum9(fk[r]);
             ps = psi_of_rho(P, rk[r]);
             ok[r] = true;
         } else {
-            ps = psi_at(P, gin, x0 - 2 + lx, y0 - 2 + ly);  // solid row: ghost value or 0
+            ps = psi_at<WET>(P, gin, x0 - 2 + lx, y0 - 2 + ly);  // solid row: ghost value or 0
         }
         ps1[(ly + 1) * W3 + lx + 1] = ps;
     }
@@ -475,7 +480,7 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
         else if (h < 2 * W3) { lx = h - W3; ly = H3 - 1; }
         else if (h < 2 * W3 + H2) { lx = 0; ly = h - 2 * W3 + 1; }
         else { lx = W3 - 1; ly = h - 2 * W3 - H2 + 1; }
-        ps1[ly * W3 + lx] = psi_at(P, gin, x0 - 3 + lx, y0 - 3 + ly);
+        ps1[ly * W3 + lx] = psi_at<WET>(P, gin, x0 - 3 + lx, y0 - 3 + ly);
     }
     __syncthreads();
 
@@ -495,8 +500,8 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
         if (P.walls && (gy == 1 || gy == P.ny - 2)) adhesion_sum(P, gw, gx, gy, Ax, Ay);
         // a boundary node's force feeds the reconstruction of step n+2, which only nodes of R1
         // perform; those have their solid-row slot inside R2
-        if (P.wet && ly >= 1 && ly <= H2 - 2)
-            store_wall_force(P, g1, s, PL, W2, gy, rk[r], c[0], sx, sy, Ax, Ay);
+        if (WET && P.wet && ly >= 1 && ly <= H2 - 2)
+            store_wall_force<WET>(P, g1, s, PL, W2, gy, rk[r], c[0], sx, sy, Ax, Ay);
         collide(P, fk[r], rk[r], c[0], sx, sy, Ax, Ay);
 #pragma unroll
         for (int a = 0; a < 9; ++a) g1[a * PL + s] = fk[r][a];
@@ -513,7 +518,7 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
             // the source node in the R2 grid: same column, row sy (mirrored rows stay adjacent)
             const int ly2 = P.walls ? sy - (y0 - 2) : ly + 1;
             double f[9];
-            pull9_lds(P, g1, PL, W2, ly2 * W2 + lx + 1, sy, f);
+            pull9_lds<WET>(P, g1, PL, W2, ly2 * W2 + lx + 1, sy, f);
             v = psi_of_rho(P, sum9(f));
         }
         ps2[s] = v;
@@ -525,7 +530,7 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
     const int x = x0 + tx, y = y0 + ty;
     if (x < P.nx && y <= P.y_hi) {
         double f[9];
-        pull9_lds(P, g1, PL, W2, (ty + 2) * W2 + tx + 2, y, f);
+        pull9_lds<WET>(P, g1, PL, W2, (ty + 2) * W2 + tx + 2, y, f);
         const double rho = sum9(f);
         const double* c = ps2 + (ty + 1) * W1 + tx + 1;
         double sx, sy;
@@ -533,8 +538,8 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
                      sx, sy);
         double Ax = 0.0, Ay = 0.0;
         if (P.walls && (y == 1 || y == P.ny - 2)) adhesion_sum(P, gw, x, y, Ax, Ay);
-        store_wall_force(P, gout, (long long)y * P.pitch + x, P.plane, P.pitch, y, rho, c[0], sx,
-                         sy, Ax, Ay);
+        store_wall_force<WET>(P, gout, (long long)y * P.pitch + x, P.plane, P.pitch, y, rho, c[0],
+                              sx, sy, Ax, Ay);
         collide(P, f, rho, c[0], sx, sy, Ax, Ay);
         const unsigned i = (unsigned)y * P.pitch + x;
 #pragma unroll

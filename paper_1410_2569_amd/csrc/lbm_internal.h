@@ -54,11 +54,12 @@ hipError_t launch_loss_seed(const KParams& P, double w_c, double w_w, double yc,
 
 // batch
 int batch_tiles(int tile);
-hipError_t launch_batch_step(int tile, const InstDesc* inst, const int* tile_inst, int ntiles,
-                             int cur, hipStream_t s);
-hipError_t launch_batch_step2(int tile, const InstDesc* inst, const int* tile_inst, int ntiles,
-                              int cur, hipStream_t s);
-hipError_t launch_batch_persistent(int tile, int grid, const InstDesc* inst,
+// wet: some instance uses the wet-node wall (selects the kernels compiled with that rule)
+hipError_t launch_batch_step(int tile, bool wet, const InstDesc* inst, const int* tile_inst,
+                             int ntiles, int cur, hipStream_t s);
+hipError_t launch_batch_step2(int tile, bool wet, const InstDesc* inst, const int* tile_inst,
+                              int ntiles, int cur, hipStream_t s);
+hipError_t launch_batch_persistent(int tile, bool wet, int grid, const InstDesc* inst,
                                    const int* tile_inst, int ntiles, int nsteps, int cur,
                                    unsigned* bar, int* flag, int spin_limit, hipStream_t s);
 int batch_persistent_occupancy(int tile);

@@ -19,7 +19,8 @@ namespace lbm {
 // ------------------------------------------------------------------------------------------------
 // Time step
 // ------------------------------------------------------------------------------------------------
-template <int TX, int TY, bool FUSED>
+// WET: compiled with the wet-node wall rule (launched for wall mode 2 only).
+template <int TX, int TY, bool FUSED, bool WET>
 __global__ __launch_bounds__(TX* TY) void k_step(KParams P, const double* __restrict__ gin,
                                                  double* __restrict__ gout,
                                                  const double* __restrict__ psi_g,
@@ -28,15 +29,15 @@ __global__ __launch_bounds__(TX* TY) void k_step(KParams P, const double* __rest
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
     const int tile = xcd_tile(blockIdx.x, ntx * nty);
-    step_tile<TX, TY, FUSED>(P, gin, gout, psi_g, gw, (tile % ntx) * TX,
-                             P.y_lo + (tile / ntx) * TY, sp);
+    step_tile<TX, TY, FUSED, WET>(P, gin, gout, psi_g, gw, (tile % ntx) * TX,
+                                  P.y_lo + (tile / ntx) * TY, sp);
 }
 
 // Overlapped tiles: one 64-lane wave spans TXI = 62 interior columns plus the halo column on each
 // side, and the workgroup has TYI interior rows plus a halo row above and below. Every thread
 // pulls exactly one node and evaluates its psi (one memory round trip per tile, all loads
 // coalesced rows); the interior threads then collide and store.
-template <int TYI>
+template <int TYI, bool WET>
 __global__ __launch_bounds__(64 * (TYI + 2)) void k_step_ov(KParams P,
                                                             const double* __restrict__ gin,
                                                             double* __restrict__ gout,
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(64 * (TYI + 2)) void k_step_ov(KParams P,
     double f[9];
     double rho = 1.0, psi_c = 0.0;
     if (has) {
-        pull9(P, gin, sx, sy, f);
+        pull9<WET>(P, gin, sx, sy, f);
         rho = sum9(f);
         psi_c = psi_of_rho(P, rho);
     }
@@ -71,8 +72,8 @@ __global__ __launch_bounds__(64 * (TYI + 2)) void k_step_ov(KParams P,
                  syy);
     double Ax = 0.0, Ay = 0.0;
     if (P.walls && (gy == 1 || gy == P.ny - 2)) adhesion_sum(P, gw, gx, gy, Ax, Ay);
-    store_wall_force(P, gout, (long long)gy * P.pitch + gx, P.plane, P.pitch, gy, rho, psi_c, sxx,
-                     syy, Ax, Ay);
+    store_wall_force<WET>(P, gout, (long long)gy * P.pitch + gx, P.plane, P.pitch, gy, rho, psi_c,
+                          sxx, syy, Ax, Ay);
     collide(P, f, rho, psi_c, sxx, syy, Ax, Ay);
     const unsigned i = (unsigned)gy * P.pitch + gx;
 #pragma unroll
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(64 * (TYI + 2)) void k_step_ov(KParams P,
 }
 
 // Two steps per launch over TX x TY output tiles (step2_tile).
-template <int TX, int TY>
+template <int TX, int TY, bool WET>
 __global__ __launch_bounds__(TX* TY) void k_step2(KParams P, const double* __restrict__ gin,
                                                   double* __restrict__ gout,
                                                   const double* __restrict__ gw) {
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(TX* TY) void k_step2(KParams P, const double* __res
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
     const int tile = xcd_tile(blockIdx.x, ntx * nty);
-    step2_tile<TX, TY>(P, gin, gout, gw, (tile % ntx) * TX, P.y_lo + (tile / ntx) * TY, lds);
+    step2_tile<TX, TY, WET>(P, gin, gout, gw, (tile % ntx) * TX, P.y_lo + (tile / ntx) * TY, lds);
 }
 
 // psi pass of the two-pass schedule; also writes the mirrored ghost rows.
@@ -273,8 +274,12 @@ static hipError_t launch_step_t(const KParams& P, const double* gin, double* gou
                                 const double* psi, const double* gw, hipStream_t s) {
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
-    hipLaunchKernelGGL((k_step<TX, TY, FUSED>), dim3(ntx * nty), dim3(TX * TY), 0, s, P, gin,
-                       gout, psi, gw);
+    if (P.wet)
+        hipLaunchKernelGGL((k_step<TX, TY, FUSED, true>), dim3(ntx * nty), dim3(TX * TY), 0, s, P,
+                           gin, gout, psi, gw);
+    else
+        hipLaunchKernelGGL((k_step<TX, TY, FUSED, false>), dim3(ntx * nty), dim3(TX * TY), 0, s,
+                           P, gin, gout, psi, gw);
     return hipGetLastError();
 }
 
@@ -283,8 +288,12 @@ static hipError_t launch_step_ov(const KParams& P, const double* gin, double* go
                                  const double* gw, hipStream_t s) {
     const int ntx = (P.nx + 61) / 62;
     const int nty = (P.y_hi - P.y_lo + TYI) / TYI;
-    hipLaunchKernelGGL((k_step_ov<TYI>), dim3(ntx * nty), dim3(64 * (TYI + 2)), 0, s, P, gin,
-                       gout, gw);
+    if (P.wet)
+        hipLaunchKernelGGL((k_step_ov<TYI, true>), dim3(ntx * nty), dim3(64 * (TYI + 2)), 0, s, P,
+                           gin, gout, gw);
+    else
+        hipLaunchKernelGGL((k_step_ov<TYI, false>), dim3(ntx * nty), dim3(64 * (TYI + 2)), 0, s,
+                           P, gin, gout, gw);
     return hipGetLastError();
 }
 
@@ -293,7 +302,12 @@ static hipError_t launch_step2_t(const KParams& P, const double* gin, double* go
                                  const double* gw, hipStream_t s) {
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
-    hipLaunchKernelGGL((k_step2<TX, TY>), dim3(ntx * nty), dim3(TX * TY), 0, s, P, gin, gout, gw);
+    if (P.wet)
+        hipLaunchKernelGGL((k_step2<TX, TY, true>), dim3(ntx * nty), dim3(TX * TY), 0, s, P, gin,
+                           gout, gw);
+    else
+        hipLaunchKernelGGL((k_step2<TX, TY, false>), dim3(ntx * nty), dim3(TX * TY), 0, s, P, gin,
+                           gout, gw);
     return hipGetLastError();
 }
 
