@@ -65,8 +65,13 @@ enum lbm_eos { LBM_EOS_CS = 0, LBM_EOS_PIECEWISE = 1 };
  *   reconstruct the populations arriving from the solid from the streamed ones and their force
  *   F of the previous step so that sum_a e_a f_a + F/2 = 0 (bottom wall: f2 = f4,
  *   f5 = f7 - (f1 - f3)/2 - (Fx + Fy)/4, f6 = f8 + (f1 - f3)/2 + (Fx - Fy)/4; the top wall is the
- *   same rule rotated by 180 degrees). That force is part of the state (saved with it). */
-enum lbm_geometry { LBM_PERIODIC = 0, LBM_WALLS_BOUNCE_BACK = 1, LBM_WALLS_WET_NODE = 2 };
+ *   same rule rotated by 180 degrees). That force is part of the state (saved with it).
+ * LBM_WALLS_MASK: periodic in x and y with an arbitrary solid mask (rough surfaces, Sec. III.B),
+ *   given to lbm_create_masked: halfway bounce-back on every link from a solid node, psi = 0 on
+ *   solid nodes (Eq. 7 is not applied across the solid, so ghost_psi must be 0) and G_w per
+ *   solid node. */
+enum lbm_geometry { LBM_PERIODIC = 0, LBM_WALLS_BOUNCE_BACK = 1, LBM_WALLS_WET_NODE = 2,
+                    LBM_WALLS_MASK = 3 };
 
 typedef struct {
     int32_t abi_version; /* must be LBM_ABI_VERSION */
@@ -128,11 +133,23 @@ int lbm_workspace_size(const lbm_params *p, size_t *bytes);
  * gw_host: [2][nx] host array of G_w per solid node (may be NULL with walls = 0; copied).
  * rho0_host: [ny][nx] host array of the initial density (solid rows ignored; copied). The
  * initial populations are the rest equilibrium f_a = t_a rho0 with t = 4/9, 1/9, 1/36.
- * stream: hipStream_t (NULL = default). On success *out owns host memory only. */
+ * stream: hipStream_t (NULL = default). On success *out owns host memory only.
+ * walls = LBM_WALLS_MASK is rejected here (LBM_E_INVAL): use lbm_create_masked. */
 int lbm_create(const lbm_params *p, const double *gw_host, const double *rho0_host, void *d_ws,
                size_t ws_bytes, void *stream, lbm_ctx **out);
 
-/* Advance n >= 0 time steps (Eqs. 1-9 with the adhesion force and halfway bounce-back).
+/* Create a context on an arbitrary solid geometry (p->walls = LBM_WALLS_MASK, ghost_psi = 0;
+ * rough surfaces of Sec. III.B). solid_host: [ny][nx] bytes, nonzero = solid node; gw_host:
+ * [ny][nx] G_w of every solid node (values on fluid nodes are ignored); rho0_host: [ny][nx]
+ * initial density (solid nodes ignored, fluid nodes > 0). All copied. x and y are periodic: a
+ * closed channel lists its wall rows in the mask. Such a context runs the fused schedule (tile
+ * shapes 0-3) or the two-pass schedule; the ensemble and adjoint entry points reject it.
+ * LBM_E_INVAL for any other walls value, a null array or a mask without fluid nodes. */
+int lbm_create_masked(const lbm_params *p, const uint8_t *solid_host, const double *gw_host,
+                      const double *rho0_host, void *d_ws, size_t ws_bytes, void *stream,
+                      lbm_ctx **out);
+
+/* Advance n >= 0 time steps (Eqs. 1-9 with the adhesion force and the context's wall scheme).
  * Asynchronous on the context stream. */
 int lbm_step(lbm_ctx *c, int64_t n);
 
@@ -147,6 +164,11 @@ int lbm_observables(lbm_ctx *c, lbm_obs *out);
  * several). */
 int lbm_observables_window(lbm_ctx *c, double x_lo, double x_hi, lbm_obs *out);
 
+/* Same, with the contact plane at height y_wall (points with y >= y_wall + 3 are fitted and
+ * theta = acos((y_wall - yc)/r)): the apparent angle on pillars whose tops end at y_wall. The
+ * default plane is y = 0.5 (bounce-back and masked geometries) or 1 (wet-node walls). */
+int lbm_observables_plane(lbm_ctx *c, double x_lo, double x_hi, double y_wall, lbm_obs *out);
+
 /* Copy rho^n ([ny][nx], count >= nx*ny) or the pre-collision populations f^n ([9][ny][nx]) to
  * host memory. Synchronises the stream. Solid rows read 0. */
 int lbm_read_rho(lbm_ctx *c, double *host, size_t count);
@@ -158,7 +180,8 @@ int lbm_state_size(const lbm_ctx *c, size_t *bytes);
 int lbm_save_state(lbm_ctx *c, void *host, size_t bytes);
 int lbm_load_state(lbm_ctx *c, const void *host, size_t bytes);
 
-/* Replace the wall wettability pattern ([2][nx] host array, copied). */
+/* Replace the wall wettability pattern ([2][nx] host array, or [ny][nx] per node for a solid
+ * mask; copied). */
 int lbm_set_gw(lbm_ctx *c, const double *gw_host);
 
 /* Kernel schedule of lbm_step:
@@ -170,12 +193,14 @@ int lbm_set_gw(lbm_ctx *c, const double *gw_host);
  *   16+t   fused with tile shape t (0..7: 64x4, 64x8, 64x16, 128x4, and the overlapped
  *          62-column tiles with 4, 6, 8, 14 rows);
  *   32+t   two steps per launch with output tile t (0..3: 64x8, 64x4, 128x4, 64x16).
- * All schedules give bit-identical populations. */
+ * All schedules give bit-identical populations. A solid mask accepts 0, 1 and 16..19 (it
+ * defaults to 16+1). */
 int lbm_set_schedule(lbm_ctx *c, int32_t schedule);
 
 /* ---- Gradients of a wetting objective with respect to the wall wettability G_w ------------- */
 /*
- * Objective on the state f^N after N steps (walls = 1 only): with the phase fraction
+ * Objective on the state f^N after N steps (walls = 1 only; other geometries get LBM_E_INVAL):
+ * with the phase fraction
  * phi = (rho - rho_v)/(rho_l - rho_v) over fluid nodes, the centroid height
  * y_c = sum phi (y - 1/2) / sum phi and the wetted length l_w = sum_x phi(x, 1),
  *     L = w_centroid * y_c + w_wet * l_w.

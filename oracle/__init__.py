@@ -36,7 +36,7 @@ class Params(C.Structure):
                 ("s_rho", C.c_double), ("s_e", C.c_double), ("s_zeta", C.c_double),
                 ("s_j", C.c_double), ("s_q", C.c_double),
                 ("tau_l", C.c_double), ("tau_v", C.c_double),
-                ("rho_l", C.c_double), ("rho_v", C.c_double)]
+                ("rho_l", C.c_double), ("rho_v", C.c_double), ("solid", C.c_void_p)]
 
 
 def build(force: bool = False) -> str:
@@ -86,10 +86,16 @@ def coexistence(p: dict) -> tuple[float, float]:
 
 
 def make_params(p: dict) -> Params:
-    """ctypes parameter block from a parameter dict (see synth.base_params)."""
+    """ctypes parameter block from a parameter dict (see synth.base_params). With walls = 3 the
+    dict carries the solid mask under "solid" ((ny, nx), nonzero = solid)."""
     q = Params()
     q.nx, q.ny = int(p["nx"]), int(p["ny"])
     q.walls, q.ghost = int(p.get("walls", 1)), int(p.get("ghost", 1))
+    if q.walls == 3:
+        m = np.ascontiguousarray(np.asarray(p["solid"]) != 0, dtype=np.uint8)
+        assert m.shape == (q.ny, q.nx)
+        q._solid = m  # keeps the array alive as long as the parameter block
+        q.solid = m.ctypes.data
     q.eos = EOS[p.get("eos", "cs")]
     q.wall_force = WALL[p.get("wall_force", "psi")]
     for k in ("a", "b", "R", "T"):
@@ -129,16 +135,24 @@ def init_rest(q: Params, rho0: np.ndarray) -> np.ndarray:
     return f
 
 
+def _gw(q: Params, gw) -> np.ndarray:
+    shape = (q.ny, q.nx) if q.walls == 3 else (2, q.nx)
+    g = np.zeros(shape) if gw is None else np.ascontiguousarray(gw, dtype=np.float64)
+    assert g.shape == shape, (g.shape, shape)
+    return g
+
+
 def run(q: Params, gw: np.ndarray | None, f: np.ndarray, nsteps: int) -> np.ndarray:
-    """Advance f (9, ny, nx) by nsteps steps, in place; returns f."""
-    g = np.zeros((2, q.nx)) if gw is None else np.ascontiguousarray(gw, dtype=np.float64)
+    """Advance f (9, ny, nx) by nsteps steps, in place; returns f. gw: [2][nx] wall rows, or
+    [ny][nx] per node for a masked geometry."""
+    g = _gw(q, gw)
     _rc(lib().orc_run(C.byref(q), _ptr(g), _ptr(f), int(nsteps)))
     return f
 
 
 def fields(q: Params, gw: np.ndarray | None, f: np.ndarray) -> dict:
     """rho, psi (ny, nx); Fm, Fads, v (2, ny, nx) of state f."""
-    g = np.zeros((2, q.nx)) if gw is None else np.ascontiguousarray(gw, dtype=np.float64)
+    g = _gw(q, gw)
     rho = np.zeros((q.ny, q.nx)); psi = np.zeros_like(rho)
     Fm = np.zeros((2, q.ny, q.nx)); Fads = np.zeros_like(Fm); v = np.zeros_like(Fm)
     _rc(lib().orc_fields(C.byref(q), _ptr(g), _ptr(f), _ptr(rho), _ptr(psi), _ptr(Fm),
@@ -147,6 +161,8 @@ def fields(q: Params, gw: np.ndarray | None, f: np.ndarray) -> dict:
 
 
 def fluid_mask(q: Params) -> np.ndarray:
+    if q.walls == 3:
+        return q._solid == 0
     m = np.ones((q.ny, q.nx), dtype=bool)
     if q.walls:
         m[0, :] = m[-1, :] = False
@@ -191,17 +207,20 @@ def kasa_fit(pts: np.ndarray) -> tuple[float, float, float]:
 
 def wall_plane(q: Params) -> float:
     """Height of the bottom wall plane: halfway between the solid row 0 and fluid row 1 with
-    bounce-back, on the boundary nodes of row 1 with the wet-node scheme (Sec. III.A)."""
+    bounce-back, on the boundary nodes of row 1 with the wet-node scheme (Sec. III.A). A masked
+    geometry has no implied wall plane: the caller gives it."""
+    if q.walls == 3:
+        raise ValueError("give the contact plane of a masked geometry explicitly")
     return 1.0 if q.walls == 2 else 0.5
 
 
-def contact_angle(q: Params, rho: np.ndarray, x_lo=-np.inf, x_hi=np.inf):
-    """Static contact angle of a droplet on the bottom wall (wall plane y_b, see wall_plane):
-    theta = acos((y_b - yc) / r) from the Kasa fit of the interface points with y >= y_b + 3.
-    Returns (theta_deg, xc, yc, r, n_points); theta is NaN when fewer than 6 points remain or
-    the fitted circle does not cut the wall plane."""
+def contact_angle(q: Params, rho: np.ndarray, x_lo=-np.inf, x_hi=np.inf, y_wall=None):
+    """Static contact angle of a droplet on the bottom wall (wall plane y_b = y_wall, by default
+    wall_plane(q)): theta = acos((y_b - yc) / r) from the Kasa fit of the interface points with
+    y >= y_b + 3. Returns (theta_deg, xc, yc, r, n_points); theta is NaN when fewer than 6 points
+    remain or the fitted circle does not cut the wall plane."""
     rho_mid = 0.5 * (q.rho_l + q.rho_v)
-    yb = wall_plane(q)
+    yb = wall_plane(q) if y_wall is None else float(y_wall)
     pts = interface_points(q, rho, rho_mid, yb + 3.0, x_lo, x_hi)
     if len(pts) < 6:
         return float("nan"), float("nan"), float("nan"), float("nan"), len(pts)
@@ -211,7 +230,7 @@ def contact_angle(q: Params, rho: np.ndarray, x_lo=-np.inf, x_hi=np.inf):
     return th, xc, yc, r, len(pts)
 
 
-def observables(q: Params, gw, f) -> dict:
+def observables(q: Params, gw, f, y_wall=None) -> dict:
     """Density extremes, spurious-current maxima, mass and contact angle of state f."""
     fd = fields(q, gw, f)
     fl = fluid_mask(q)
@@ -219,7 +238,7 @@ def observables(q: Params, gw, f) -> dict:
     u = np.sqrt(fd["v"][0] ** 2 + fd["v"][1] ** 2)
     rho_mid = 0.5 * (q.rho_l + q.rho_v)
     liq = fl & (rho >= rho_mid)
-    th, xc, yc, r, n = contact_angle(q, rho)
+    th, xc, yc, r, n = contact_angle(q, rho, y_wall=y_wall)
     return dict(rho_min=float(rho[fl].min()), rho_max=float(rho[fl].max()),
                 umax=float(u[fl].max()), umax_liquid=float(u[liq].max()) if liq.any() else 0.0,
                 mass=float(rho[fl].sum()), theta=th, xc=xc, yc=yc, r=r, n_fit=n)

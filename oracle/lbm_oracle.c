@@ -13,7 +13,10 @@
  * Two wall schemes: halfway bounce-back (walls = 1; the wall plane lies halfway between the solid
  * row and the first fluid row) and the non-slip wet-node scheme of Sec. III.A (walls = 2; rows 1
  * and ny-2 are boundary nodes on the wall plane whose populations arriving from the solid are
- * reconstructed so that the node's velocity, Eq. (6), is zero).
+ * reconstructed so that the node's velocity, Eq. (6), is zero). With walls = 3 the lattice is
+ * periodic in both directions and an arbitrary solid mask (rough surfaces, Sec. III.B) defines the
+ * solid nodes: halfway bounce-back on every link from a solid node, psi = 0 on solid nodes (no
+ * ghost layer) and G_w given per solid node.
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off [-fopenmp] -shared -fPIC. Every per-node loop writes
  * only its own node, so the result does not depend on the thread count.
@@ -40,6 +43,7 @@ typedef struct {
     double s_rho, s_e, s_zeta, s_j, s_q; /* diagonal of Lambda, Eq. (2) */
     double tau_l, tau_v; /* tau_nu in the liquid and in the vapour */
     double rho_l, rho_v; /* coexistence densities (viscosity interpolation) */
+    const uint8_t *solid; /* walls = 3: [ny][nx], 1 = solid node; otherwise unused */
 } orc_params;
 
 /* D2Q9 velocities: 0 rest; 1..4 = E, N, W, S; 5..8 = NE, NW, SW, SE (numbering that the paper's
@@ -101,12 +105,21 @@ double orc_psi(const orc_params *p, double rho)
     return sqrt(rad);
 }
 
-static int is_solid(const orc_params *p, int y)
+static int wrap(int v, int n) { return ((v % n) + n) % n; }
+
+/* Geometry: solid rows 0 and ny-1 (walls = 1, 2), the mask (walls = 3, coordinates wrapped), or
+ * no solid at all (walls = 0). Rows outside the lattice only arise with walls = 1, 2. */
+static int is_solid(const orc_params *p, int x, int y)
 {
-    return p->walls && (y == 0 || y == p->ny - 1);
+    if (p->walls == 3) return p->solid[(size_t)wrap(y, p->ny) * p->nx + wrap(x, p->nx)] != 0;
+    return (p->walls == 1 || p->walls == 2) && (y == 0 || y == p->ny - 1);
 }
 
-static int wrap(int v, int n) { return ((v % n) + n) % n; }
+/* Row of a neighbour: wrapped where y is periodic (walls = 0, 3). */
+static int nb_row(const orc_params *p, int y)
+{
+    return (p->walls == 0 || p->walls == 3) ? wrap(y, p->ny) : y;
+}
 
 /* S1, S2: density and pseudopotential of every fluid node; ghost psi on the solid rows. */
 static int density_and_psi(const orc_params *p, const double *f, double *rho, double *psi)
@@ -118,7 +131,7 @@ static int density_and_psi(const orc_params *p, const double *f, double *rho, do
     for (int y = 0; y < ny; ++y) {
         for (int x = 0; x < nx; ++x) {
             size_t i = (size_t)y * nx + x;
-            if (is_solid(p, y)) { rho[i] = 0.0; psi[i] = 0.0; continue; }
+            if (is_solid(p, x, y)) { rho[i] = 0.0; psi[i] = 0.0; continue; }
             double s = 0.0;
             for (int a = 0; a < 9; ++a) s += f[a * N + i];        /* Eq. (6) */
             rho[i] = s;
@@ -127,7 +140,7 @@ static int density_and_psi(const orc_params *p, const double *f, double *rho, do
         }
     }
     if (bad) return ORC_E_PSI;
-    if (p->walls) {
+    if (p->walls == 1 || p->walls == 2) {
         /* Eq. (7) applied at the wall: the solid row takes the psi of the fluid row next to it
          * (with bounce-back, the mirror image about the wall plane halfway between them; with
          * the wet-node scheme, the psi of the boundary node on the wall plane). */
@@ -140,7 +153,8 @@ static int density_and_psi(const orc_params *p, const double *f, double *rho, do
 }
 
 /* S3-S5 at one fluid node: cohesive force Eq. (7), adhesive force Eq. (10)/(11)/(14), total
- * force and velocity Eq. (6). gw[2][nx]: G_w of the bottom (row 0) and top (row 1) solid nodes. */
+ * force and velocity Eq. (6). gw: G_w of the solid nodes, [2][nx] for the bottom (row 0) and top
+ * (row 1) walls, or [ny][nx] per node with walls = 3. */
 static void forces_at(const orc_params *p, const double *gw, const double *f, const double *rho,
                       const double *psi, int x, int y, double Fm[2], double Fads[2], double F[2],
                       double v[2])
@@ -154,7 +168,7 @@ static void forces_at(const orc_params *p, const double *gw, const double *f, co
     double sx = 0.0, sy = 0.0;
     for (int a = 1; a < 9; ++a) {
         int xn = wrap(x + EX[a], nx);
-        int yn = p->walls ? y + EY[a] : wrap(y + EY[a], ny);
+        int yn = nb_row(p, y + EY[a]);
         double pn = psi[(size_t)yn * nx + xn];
         sx += w_alpha(a) * pn * EX[a];
         sy += w_alpha(a) * pn * EY[a];
@@ -173,10 +187,11 @@ static void forces_at(const orc_params *p, const double *gw, const double *f, co
         else pre = psi[i] * psi[i];
         double ax = 0.0, ay = 0.0;
         for (int a = 1; a < 9; ++a) {
-            int yn = y + EY[a];
-            if (!is_solid(p, yn)) continue;
+            int yn = nb_row(p, y + EY[a]);
             int xn = wrap(x + EX[a], nx);
-            double g = gw[(yn == 0 ? 0 : 1) * (size_t)nx + xn];
+            if (!is_solid(p, xn, yn)) continue;
+            double g = p->walls == 3 ? gw[(size_t)yn * nx + xn]
+                                     : gw[(yn == 0 ? 0 : 1) * (size_t)nx + xn];
             double om = w_alpha(a) / 3.0;
             ax += om * g * EX[a];
             ay += om * g * EY[a];
@@ -292,7 +307,7 @@ static int one_step(const orc_params *p, const double *gw, double *f, double *wo
     for (int y = 0; y < ny; ++y) {
         for (int x = 0; x < nx; ++x) {
             size_t i = (size_t)y * nx + x;
-            if (is_solid(p, y)) {
+            if (is_solid(p, x, y)) {
                 for (int a = 0; a < 9; ++a) fs[a * N + i] = 0.0;
                 continue;
             }
@@ -313,15 +328,15 @@ static int one_step(const orc_params *p, const double *gw, double *f, double *wo
     for (int y = 0; y < ny; ++y) {
         for (int x = 0; x < nx; ++x) {
             size_t i = (size_t)y * nx + x;
-            if (is_solid(p, y)) {
+            if (is_solid(p, x, y)) {
                 for (int a = 0; a < 9; ++a) f[a * N + i] = 0.0;
                 continue;
             }
             double fn[9];
             for (int a = 0; a < 9; ++a) {
                 int xs = wrap(x - EX[a], nx);
-                int ys = p->walls ? y - EY[a] : wrap(y - EY[a], ny);
-                if (is_solid(p, ys)) fn[a] = p->walls == 2 ? 0.0 : fs[OPP[a] * N + i];
+                int ys = nb_row(p, y - EY[a]);
+                if (is_solid(p, xs, ys)) fn[a] = p->walls == 2 ? 0.0 : fs[OPP[a] * N + i];
                 else fn[a] = fs[a * N + (size_t)ys * nx + xs];
             }
             if (p->walls == 2 && (y == 1 || y == ny - 2)) {
@@ -337,8 +352,9 @@ static int one_step(const orc_params *p, const double *gw, double *f, double *wo
 
 static int check(const orc_params *p)
 {
-    if (!p || p->nx < 3 || p->ny < (p->walls ? 4 : 3) || p->walls < 0 || p->walls > 2)
-        return ORC_E_INVAL;
+    if (!p || p->nx < 3 || p->walls < 0 || p->walls > 3) return ORC_E_INVAL;
+    if (p->ny < ((p->walls == 1 || p->walls == 2) ? 4 : 3)) return ORC_E_INVAL;
+    if (p->walls == 3 && (!p->solid || p->ghost)) return ORC_E_INVAL;
     return ORC_OK;
 }
 
@@ -367,7 +383,7 @@ int orc_init_rest(const orc_params *p, const double *rho0, double *f)
             for (int a = 0; a < 9; ++a) {
                 int e2 = EX[a] * EX[a] + EY[a] * EY[a];
                 double t = e2 == 0 ? 4.0 / 9.0 : (e2 == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
-                f[a * N + i] = is_solid(p, y) ? 0.0 : t * rho0[i];
+                f[a * N + i] = is_solid(p, x, y) ? 0.0 : t * rho0[i];
             }
         }
     return ORC_OK;
@@ -388,7 +404,7 @@ int orc_fields(const orc_params *p, const double *gw, const double *f, double *r
         for (int x = 0; x < nx; ++x) {
             size_t i = (size_t)y * nx + x;
             double Fm[2] = {0, 0}, Fads[2] = {0, 0}, F[2], v[2] = {0, 0};
-            if (!is_solid(p, y)) forces_at(p, gw, f, rho, psi, x, y, Fm, Fads, F, v);
+            if (!is_solid(p, x, y)) forces_at(p, gw, f, rho, psi, x, y, Fm, Fads, F, v);
             Fm_out[i] = Fm[0]; Fm_out[N + i] = Fm[1];
             Fads_out[i] = Fads[0]; Fads_out[N + i] = Fads[1];
             v_out[i] = v[0]; v_out[N + i] = v[1];

@@ -44,18 +44,18 @@ __global__ __launch_bounds__(TX* TY) void k_adj_local(KParams P, const double* _
     double f[9];
     double rho = 1.0, psi_c = 0.0;
     if (active) {
-        pull9<false>(P, gprev, x, y, f);
+        pull9<GEO_ROWS>(P, gprev, x, y, f);
         rho = sum9(f);
         psi_c = psi_of_rho(P, rho);
     }
-    sp[(ty + 1) * LW + tx + 1] = active ? psi_c : psi_at<false>(P, gprev, x, y);
+    sp[(ty + 1) * LW + tx + 1] = active ? psi_c : psi_at<GEO_ROWS>(P, gprev, x, y);
     for (int h = threadIdx.x; h < NH; h += NT) {
         int hx, hy;
         if (h < LW) { hx = h - 1; hy = -1; }
         else if (h < 2 * LW) { hx = h - LW - 1; hy = TY; }
         else if (h < 2 * LW + TY) { hx = -1; hy = h - 2 * LW; }
         else { hx = TX; hy = h - 2 * LW - TY; }
-        sp[(hy + 1) * LW + hx + 1] = psi_at<false>(P, gprev, x0 + hx, y0 + hy);
+        sp[(hy + 1) * LW + hx + 1] = psi_at<GEO_ROWS>(P, gprev, x0 + hx, y0 + hy);
     }
     __syncthreads();
     if (!active) return;
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void k_loss_partial(KParams P, const double* _
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     if (x < P.nx && y <= P.y_hi) {
         double f[9];
-        pull9<false>(P, g, x, y, f);
+        pull9<GEO_ROWS>(P, g, x, y, f);
         const double phi = (sum9(f) - P.rho_v) * P.inv_drho;
         s0 = phi;
         s1 = phi * (y - 0.5);

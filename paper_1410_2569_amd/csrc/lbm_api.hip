@@ -49,8 +49,12 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
     int pitch;
     long long plane;  // doubles
-    size_t off_g0, off_g1, off_psi, off_gw, off_part, off_fin, total;
+    size_t off_g0, off_g1, off_psi, off_gw, off_links, off_part, off_fin, total;
 };
+
+bool is_mask(const lbm_params* p) { return p->walls == LBM_WALLS_MASK; }
+int y_lo_of(const lbm_params* p) { return (p->walls == 1 || p->walls == 2) ? 1 : 0; }
+int y_hi_of(const lbm_params* p) { return (p->walls == 1 || p->walls == 2) ? p->ny - 2 : p->ny - 1; }
 
 Layout layout_of(const lbm_params* p) {
     Layout L;
@@ -61,10 +65,13 @@ Layout layout_of(const lbm_params* p) {
     L.off_g0 = o; o += fbytes;
     L.off_g1 = o; o += fbytes;
     L.off_psi = o; o += align_up((size_t)L.plane * sizeof(double), kAlign);
-    L.off_gw = o; o += align_up((size_t)2 * L.pitch * sizeof(double), kAlign);
+    // G_w: two wall rows, or one value per node with a solid mask (plus its link words)
+    L.off_gw = o; o += align_up((size_t)(is_mask(p) ? p->ny : 2) * L.pitch * sizeof(double), kAlign);
+    L.off_links = o;
+    if (is_mask(p)) o += align_up((size_t)L.plane * sizeof(unsigned short), kAlign);
     KParams tmp{};
     tmp.nx = p->nx; tmp.ny = p->ny;
-    tmp.y_lo = p->walls ? 1 : 0; tmp.y_hi = p->walls ? p->ny - 2 : p->ny - 1;
+    tmp.y_lo = y_lo_of(p); tmp.y_hi = y_hi_of(p);
     L.off_part = o; o += align_up((size_t)lbm::obs_blocks(tmp) * lbm::OBS_NQ * sizeof(double), kAlign);
     L.off_fin = o; o += align_up(32 * sizeof(double), kAlign);
     L.total = o;
@@ -81,10 +88,12 @@ int validate(const lbm_params* p, std::string* msg) {
         if (msg) *msg = "abi_version mismatch";
         return LBM_E_ABI;
     }
-    if (p->walls < LBM_PERIODIC || p->walls > LBM_WALLS_WET_NODE) return bad("walls must be 0, 1 or 2");
+    if (p->walls < LBM_PERIODIC || p->walls > LBM_WALLS_MASK) return bad("walls must be 0, 1, 2 or 3");
+    if (p->walls == LBM_WALLS_MASK && p->ghost_psi != 0)
+        return bad("a solid mask has no ghost layer: ghost_psi must be 0");
     if (p->ghost_psi != 0 && p->ghost_psi != 1) return bad("ghost_psi must be 0 or 1");
     if (p->nx < 3) return bad("nx must be >= 3");
-    if (p->ny < (p->walls ? 4 : 3)) return bad("ny must be >= 4 with walls (>= 3 without)");
+    if (p->ny < (y_lo_of(p) ? 4 : 3)) return bad("ny must be >= 4 with walls (>= 3 without)");
     if ((long long)p->nx * p->ny > (1LL << 31)) return bad("lattice too large");
     if (p->eos != LBM_EOS_CS && p->eos != LBM_EOS_PIECEWISE) return bad("unknown eos");
     if (p->wall_force < LBM_WALL_RHO || p->wall_force > LBM_WALL_MODPSI) return bad("unknown wall_force");
@@ -114,8 +123,9 @@ KParams kparams_of(const lbm_params* p, const Layout& L) {
     k.nx = p->nx; k.ny = p->ny; k.pitch = L.pitch; k.plane = L.plane;
     k.walls = p->walls; k.ghost = p->ghost_psi; k.eos = p->eos; k.wall_force = p->wall_force;
     k.wet = p->walls == LBM_WALLS_WET_NODE ? 1 : 0;
-    k.y_lo = p->walls ? 1 : 0;
-    k.y_hi = p->walls ? p->ny - 2 : p->ny - 1;
+    k.mask = is_mask(p) ? 1 : 0;
+    k.y_lo = y_lo_of(p);
+    k.y_hi = y_hi_of(p);
     k.RT = p->R * p->T; k.a = p->a; k.b4 = p->b / 4.0;
     k.rho1 = p->rho1; k.rho2 = p->rho2; k.th_v = p->th_v; k.th_m = p->th_m; k.th_l = p->th_l;
     k.p1 = p->rho1 * p->th_v;
@@ -351,8 +361,27 @@ int lbm_workspace_size(const lbm_params* p, size_t* bytes) {
     return LBM_OK;
 }
 
-int lbm_create(const lbm_params* p, const double* gw_host, const double* rho0_host, void* d_ws,
-               size_t ws_bytes, void* stream, lbm_ctx** out) {
+// Link words of a solid mask: bit 0 = node solid, bit a = node x - e_a solid (x, y periodic).
+static std::vector<unsigned short> mask_links(const lbm_params* p, const uint8_t* solid, int pitch) {
+    static const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    std::vector<unsigned short> lk((size_t)p->ny * pitch, 1);  // padding columns: solid
+    for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+            unsigned short w = 0;
+            for (int a = 0; a < 9; ++a) {
+                const int xs = ((x - ex[a]) % p->nx + p->nx) % p->nx;
+                const int ys = ((y - ey[a]) % p->ny + p->ny) % p->ny;
+                if (solid[(size_t)ys * p->nx + xs]) w |= (unsigned short)(1u << a);
+            }
+            lk[(size_t)y * pitch + x] = w;
+        }
+    return lk;
+}
+
+static int create_impl(const lbm_params* p, const uint8_t* solid, const double* gw_host,
+                       const double* rho0_host, void* d_ws, size_t ws_bytes, void* stream,
+                       lbm_ctx** out) {
     if (!out) return LBM_E_INVAL;
     *out = nullptr;
     std::string msg;
@@ -360,13 +389,18 @@ int lbm_create(const lbm_params* p, const double* gw_host, const double* rho0_ho
     if (rc) return rc;
     if (!rho0_host || !d_ws) return LBM_E_INVAL;
     if (p->walls && !gw_host) return LBM_E_INVAL;
+    if (is_mask(p) != (solid != nullptr)) return LBM_E_INVAL;
+    long long nfluid = 0;
     for (long long i = 0; i < (long long)p->nx * p->ny; ++i) {
         const int y = (int)(i / p->nx);
-        if (p->walls && (y == 0 || y == p->ny - 1)) continue;
+        if (solid ? solid[i] != 0 : (y < y_lo_of(p) || y > y_hi_of(p))) continue;
         if (!finite_pos(rho0_host[i])) return LBM_E_INVAL;
+        ++nfluid;
     }
+    if (nfluid == 0) return LBM_E_INVAL;
+    const int gw_rows = solid ? p->ny : 2;
     if (gw_host)
-        for (int i = 0; i < 2 * p->nx; ++i)
+        for (long long i = 0; i < (long long)gw_rows * p->nx; ++i)
             if (!std::isfinite(gw_host[i])) return LBM_E_INVAL;
     Layout L = layout_of(p);
     if (ws_bytes < L.total) return LBM_E_SIZE;
@@ -400,8 +434,21 @@ int lbm_create(const lbm_params* p, const double* gw_host, const double* rho0_ho
     if ((e = hipMemsetAsync(c->ws, 0, L.total, s)) != hipSuccess) { delete c; return LBM_E_HIP; }
     if (gw_host) {
         e = hipMemcpy2DAsync(c->gw, L.pitch * sizeof(double), gw_host, p->nx * sizeof(double),
-                             p->nx * sizeof(double), 2, hipMemcpyHostToDevice, s);
+                             p->nx * sizeof(double), gw_rows, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) { delete c; return LBM_E_HIP; }
+    }
+    if (solid) {
+        // the fused single step with the tile shapes that stage the halo is the masked schedule
+        c->schedule = 0;
+        c->tile = 1;
+        std::vector<unsigned short> lk = mask_links(p, solid, L.pitch);
+        unsigned short* d_links = (unsigned short*)(c->ws + L.off_links);
+        e = hipMemcpyAsync(d_links, lk.data(), lk.size() * sizeof(unsigned short),
+                           hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);  // lk is a host temporary
+        if (e != hipSuccess) { delete c; return LBM_E_HIP; }
+        c->kp.links = d_links;
+        c->kp.gwn = c->gw;
     }
     // stage rho0 in the second population buffer, then build the first from it
     e = hipMemcpy2DAsync(c->g[1], L.pitch * sizeof(double), rho0_host, p->nx * sizeof(double),
@@ -413,10 +460,31 @@ int lbm_create(const lbm_params* p, const double* gw_host, const double* rho0_ho
     return LBM_OK;
 }
 
+int lbm_create(const lbm_params* p, const double* gw_host, const double* rho0_host, void* d_ws,
+               size_t ws_bytes, void* stream, lbm_ctx** out) {
+    if (p && is_mask(p)) {
+        if (out) *out = nullptr;
+        return LBM_E_INVAL;  // a solid mask is given through lbm_create_masked
+    }
+    return create_impl(p, nullptr, gw_host, rho0_host, d_ws, ws_bytes, stream, out);
+}
+
+int lbm_create_masked(const lbm_params* p, const uint8_t* solid_host, const double* gw_host,
+                      const double* rho0_host, void* d_ws, size_t ws_bytes, void* stream,
+                      lbm_ctx** out) {
+    if (!p || !is_mask(p) || !solid_host || !gw_host) {
+        if (out) *out = nullptr;
+        return LBM_E_INVAL;
+    }
+    return create_impl(p, solid_host, gw_host, rho0_host, d_ws, ws_bytes, stream, out);
+}
+
 int lbm_set_schedule(lbm_ctx* c, int32_t schedule) {
     if (!c) return LBM_E_INVAL;
     // 0 fused, 1 two-pass, 2 two steps per launch; 16 + t: fused with tile shape t;
-    // 32 + t: two steps per launch with output tile t
+    // 32 + t: two steps per launch with output tile t. A solid mask: 0, 1 and tiles 0-3.
+    if (c->kp.mask && (schedule == 2 || schedule >= 20))
+        return fail(c, LBM_E_INVAL, "a solid mask runs the fused (tiles 0-3) or two-pass schedule");
     if (schedule >= 0 && schedule <= 2) { c->schedule = schedule; return LBM_OK; }
     if (schedule >= 16 && schedule < 16 + lbm::n_tiles()) {
         c->schedule = 0;
@@ -515,17 +583,17 @@ static void obs_from_sums(const double* q, const lbm::ObsArgs& A, int64_t step, 
     *out = o;
 }
 
-int lbm_observables_window(lbm_ctx* c, double x_lo, double x_hi, lbm_obs* out) {
-    if (!c || !out) return LBM_E_INVAL;
+int lbm_observables_plane(lbm_ctx* c, double x_lo, double x_hi, double y_wall, lbm_obs* out) {
+    if (!c || !out || !std::isfinite(y_wall)) return LBM_E_INVAL;
     (void)hipGetLastError();  // report only errors of this call
     const KParams& P = c->kp;
     lbm::ObsArgs A;
     A.rho_mid = 0.5 * (c->p.rho_l + c->p.rho_v);
-    A.y_min = wall_plane(c->p.walls) + 3.0;
+    A.y_min = y_wall + 3.0;
     A.x_lo = x_lo;
     A.x_hi = x_hi;
     A.cx = std::isfinite(x_lo) && std::isfinite(x_hi) ? 0.5 * (x_lo + x_hi) : 0.5 * P.nx;
-    A.cy = wall_plane(c->p.walls);
+    A.cy = y_wall;
     double* rho = c->g[c->cur ^ 1];  // the idle population buffer serves as scratch
     hipError_t e = lbm::launch_rho_psi(P, c->g[c->cur], c->psi, rho, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "observables psi");
@@ -538,6 +606,11 @@ int lbm_observables_window(lbm_ctx* c, double x_lo, double x_hi, lbm_obs* out) {
 
     obs_from_sums(q, A, c->step, out);
     return out->nonfinite ? LBM_E_NONFINITE : LBM_OK;
+}
+
+int lbm_observables_window(lbm_ctx* c, double x_lo, double x_hi, lbm_obs* out) {
+    if (!c) return LBM_E_INVAL;
+    return lbm_observables_plane(c, x_lo, x_hi, wall_plane(c->p.walls), out);
 }
 
 int lbm_observables(lbm_ctx* c, lbm_obs* out) {
@@ -630,10 +703,11 @@ int lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
 
 int lbm_set_gw(lbm_ctx* c, const double* gw_host) {
     if (!c || !gw_host) return LBM_E_INVAL;
-    for (int i = 0; i < 2 * c->p.nx; ++i)
+    const int rows = c->kp.mask ? c->p.ny : 2;
+    for (long long i = 0; i < (long long)rows * c->p.nx; ++i)
         if (!std::isfinite(gw_host[i])) return fail(c, LBM_E_INVAL, "non-finite G_w");
     hipError_t e = hipMemcpy2DAsync(c->gw, c->kp.pitch * sizeof(double), gw_host,
-                                    c->p.nx * sizeof(double), c->p.nx * sizeof(double), 2,
+                                    c->p.nx * sizeof(double), c->p.nx * sizeof(double), rows,
                                     hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "set_gw");
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "set_gw sync");
@@ -855,6 +929,7 @@ int lbm_batch_workspace_size(const lbm_params* p, int32_t count, const lbm_tune*
     for (int i = 0; i < count; ++i) {
         int rc = validate(&p[i], nullptr);
         if (rc) return rc;
+        if (is_mask(&p[i])) return LBM_E_INVAL;
     }
     BatchLayout B;
     if (!batch_layout(p, count, tune ? tune->tile : 0, &B)) return LBM_E_INVAL;
@@ -872,6 +947,7 @@ int lbm_batch_create(const lbm_params* p, int32_t count, const double* const* gw
     for (int i = 0; i < count; ++i) {
         int rc = validate(&p[i], nullptr);
         if (rc) return rc;
+        if (is_mask(&p[i])) return LBM_E_INVAL;  // ensembles: flat walls or periodic lattices
         if (!rho0_host[i] || (p[i].walls && !gw_host[i])) return LBM_E_INVAL;
     }
     lbm_tune tn = tune ? *tune : lbm_tune{1, 0, 0, 0};

@@ -20,8 +20,8 @@ __device__ __forceinline__ void batch_tile_origin(const InstDesc* D, int t, int 
     y0 = D->P.y_lo + (lt / D->ntx) * TY;
 }
 
-// WET: compiled with the wet-node wall rule (launched when some instance uses wall mode 2).
-template <int TX, int TY, bool WET>
+// GEO: GEO_WET when some instance uses the wet-node wall, else GEO_ROWS (chosen at launch).
+template <int TX, int TY, int GEO>
 __global__ __launch_bounds__(TX* TY) void k_batch_step(const InstDesc* __restrict__ inst,
                                                        const int* __restrict__ tile_inst,
                                                        int ntiles, int cur) {
@@ -30,11 +30,11 @@ __global__ __launch_bounds__(TX* TY) void k_batch_step(const InstDesc* __restric
     const InstDesc* D = inst + tile_inst[t];
     int x0, y0;
     batch_tile_origin(D, t, TX, TY, x0, y0);
-    step_tile<TX, TY, true, WET>(D->P, D->g[cur], D->g[cur ^ 1], nullptr, D->gw, x0, y0, sp);
+    step_tile<TX, TY, true, GEO>(D->P, D->g[cur], D->g[cur ^ 1], nullptr, D->gw, x0, y0, sp);
 }
 
 // Two steps per launch over the work-list (the tiles are the output tiles of step2_tile).
-template <int TX, int TY, bool WET>
+template <int TX, int TY, int GEO>
 __global__ __launch_bounds__(TX* TY) void k_batch_step2(const InstDesc* __restrict__ inst,
                                                         const int* __restrict__ tile_inst,
                                                         int ntiles, int cur) {
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(TX* TY) void k_batch_step2(const InstDesc* __restri
     const InstDesc* D = inst + tile_inst[t];
     int x0, y0;
     batch_tile_origin(D, t, TX, TY, x0, y0);
-    step2_tile<TX, TY, WET>(D->P, D->g[cur], D->g[cur ^ 1], D->gw, x0, y0, lds);
+    step2_tile<TX, TY, GEO>(D->P, D->g[cur], D->g[cur ^ 1], D->gw, x0, y0, lds);
 }
 
 // Grid-wide barrier number `target / gridDim.x`. Returns false when the run was aborted.
@@ -75,7 +75,7 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, int
     return *verdict != 0;
 }
 
-template <int TX, int TY, bool WET>
+template <int TX, int TY, int GEO>
 __global__ __launch_bounds__(TX* TY) void k_batch_persistent(const InstDesc* __restrict__ inst,
                                                              const int* __restrict__ tile_inst,
                                                              int ntiles, int nsteps, int cur0,
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(TX* TY) void k_batch_persistent(const InstDesc* __r
             const InstDesc* D = inst + tile_inst[t];
             int x0, y0;
             batch_tile_origin(D, t, TX, TY, x0, y0);
-            step_tile<TX, TY, true, WET>(D->P, D->g[cur], D->g[cur ^ 1], nullptr, D->gw, x0, y0,
+            step_tile<TX, TY, true, GEO>(D->P, D->g[cur], D->g[cur ^ 1], nullptr, D->gw, x0, y0,
                                          sp);
             __syncthreads();  // the LDS tile is reused by the next tile
         }
@@ -115,10 +115,10 @@ template <int TX, int TY>
 static hipError_t launch_batch_t(bool wet, const InstDesc* inst, const int* tile_inst, int ntiles,
                                  int cur, hipStream_t s) {
     if (wet)
-        hipLaunchKernelGGL((k_batch_step<TX, TY, true>), dim3(ntiles), dim3(TX * TY), 0, s, inst,
+        hipLaunchKernelGGL((k_batch_step<TX, TY, GEO_WET>), dim3(ntiles), dim3(TX * TY), 0, s, inst,
                            tile_inst, ntiles, cur);
     else
-        hipLaunchKernelGGL((k_batch_step<TX, TY, false>), dim3(ntiles), dim3(TX * TY), 0, s, inst,
+        hipLaunchKernelGGL((k_batch_step<TX, TY, GEO_ROWS>), dim3(ntiles), dim3(TX * TY), 0, s, inst,
                            tile_inst, ntiles, cur);
     return hipGetLastError();
 }
@@ -131,10 +131,10 @@ static hipError_t launch_persist_t(bool wet, int grid, const InstDesc* inst, con
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (wet)
-        hipLaunchKernelGGL((k_batch_persistent<TX, TY, true>), dim3(grid), dim3(TX * TY), 0, s,
+        hipLaunchKernelGGL((k_batch_persistent<TX, TY, GEO_WET>), dim3(grid), dim3(TX * TY), 0, s,
                            inst, tile_inst, ntiles, nsteps, cur, bar, flag, spin_limit);
     else
-        hipLaunchKernelGGL((k_batch_persistent<TX, TY, false>), dim3(grid), dim3(TX * TY), 0, s,
+        hipLaunchKernelGGL((k_batch_persistent<TX, TY, GEO_ROWS>), dim3(grid), dim3(TX * TY), 0, s,
                            inst, tile_inst, ntiles, nsteps, cur, bar, flag, spin_limit);
     return hipGetLastError();
 }
@@ -144,9 +144,9 @@ static hipError_t launch_persist_t(bool wet, int grid, const InstDesc* inst, con
 template <int TX, int TY>
 static int occupancy_t() {
     int a = 0, b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_batch_persistent<TX, TY, false>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_batch_persistent<TX, TY, GEO_ROWS>,
                                                      TX * TY, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_batch_persistent<TX, TY, true>,
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_batch_persistent<TX, TY, GEO_WET>,
                                                      TX * TY, 0) != hipSuccess)
         return 0;
     return a < b ? a : b;
@@ -160,10 +160,10 @@ template <int TX, int TY>
 static hipError_t launch_batch2_t(bool wet, const InstDesc* inst, const int* tile_inst, int ntiles,
                                   int cur, hipStream_t s) {
     if (wet)
-        hipLaunchKernelGGL((k_batch_step2<TX, TY, true>), dim3(ntiles), dim3(TX * TY), 0, s, inst,
+        hipLaunchKernelGGL((k_batch_step2<TX, TY, GEO_WET>), dim3(ntiles), dim3(TX * TY), 0, s, inst,
                            tile_inst, ntiles, cur);
     else
-        hipLaunchKernelGGL((k_batch_step2<TX, TY, false>), dim3(ntiles), dim3(TX * TY), 0, s, inst,
+        hipLaunchKernelGGL((k_batch_step2<TX, TY, GEO_ROWS>), dim3(ntiles), dim3(TX * TY), 0, s, inst,
                            tile_inst, ntiles, cur);
     return hipGetLastError();
 }

@@ -9,7 +9,9 @@
 // on the wall planes and the populations arriving from the solid are reconstructed from the
 // streamed ones and the node's force of the step that wrote the buffer. That force (Fx, Fy) is
 // part of the state: planes 0 and 1 of the adjacent solid row hold it, slots no pull reads
-// otherwise.
+// otherwise. With walls = 3 the lattice is periodic in x and y and a solid mask defines the solid
+// nodes: links[y][x] bit 0 marks node (x, y) solid and bit a marks x - e_a solid (halfway
+// bounce-back on that link); psi is 0 on solid nodes and G_w is given per solid node (gwn).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -21,6 +23,7 @@ struct KParams {
     int nx, ny, pitch;      // lattice and row pitch (doubles)
     int walls, ghost;       // solid rows 0 and ny-1 (1 bounce-back, 2 wet-node); mirrored psi
     int wet;                // walls == 2
+    int mask;               // walls == 3: solid nodes from links, G_w per node in gwn
     int eos, wall_force;    // 0 CS / 1 piecewise; 0 rho / 1 psi / 2 psi^2 pre-sum factor
     int y_lo, y_hi;         // fluid rows [y_lo, y_hi]
     int visc_const;         // 1: tau_l == tau_v, use s_nu_c
@@ -34,7 +37,15 @@ struct KParams {
     double s_e, s_z, s_j, s_q;            // relaxation rates (s_rho drops out: rho is conserved)
     double h_e, h_z, h_j, h_q;            // 1 - s/2
     double s_nu_c, nu_v, dnu, rho_v, inv_drho;  // shear rate: constant, or interpolated
+    const unsigned short* links;  // walls = 3: [ny][pitch] solid and bounce-back bits
+    const double* gwn;            // walls = 3: [ny][pitch] G_w of solid nodes
 };
+
+// Geometry variants compiled into the step kernels. GEO_ROWS: periodic lattice or bounce-back
+// rows; GEO_WET: also the wet-node rule where P.wet says so; GEO_MASK: solid mask.
+enum { GEO_ROWS = 0, GEO_WET = 1, GEO_MASK = 2 };
+
+__device__ __forceinline__ int wrap_once(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 // x mod nx in [0, nx). Tile halos reach at most a few nodes past either end, so one add or
 // subtract suffices except on lattices narrower than a tile.
@@ -90,11 +101,39 @@ __device__ __forceinline__ void wet_node_top(double f[9], double Fx, double Fy) 
 
 // Pull the 9 pre-collision populations of fluid node (x, y) from post-collision buffer g.
 // Plane bases are uniform (scalar registers) and in-plane offsets 32-bit unsigned, so loads use
-// scalar-base + 32-bit vector-offset addressing. WET = false compiles the wet-node rule out (for
-// launches known to use another wall mode); WET = true applies it where P.wet says so.
-template <bool WET = true>
+// scalar-base + 32-bit vector-offset addressing. GEO selects the geometry code compiled in (see
+// GEO_ROWS, GEO_WET, GEO_MASK).
+template <int GEO>
+__device__ __forceinline__ void pull9(const KParams& P, const double* __restrict__ g, int x,
+                                      int y, double f[9]);
+
+// Solid-mask geometry: lk = links of (x, y); a set bit a pulls the node's own reflected
+// population (halfway bounce-back), otherwise the neighbour's, with x and y periodic.
+__device__ __forceinline__ void pull9_mask(const KParams& P, const double* __restrict__ g, int x,
+                                           int y, unsigned lk, double f[9]) {
+    const unsigned pitch = P.pitch;
+    const unsigned xm = x == 0 ? P.nx - 1 : x - 1, xp = x == P.nx - 1 ? 0 : x + 1;
+    const unsigned ym = y == 0 ? P.ny - 1 : y - 1, yp = y == P.ny - 1 ? 0 : y + 1;
+    const long long pl = P.plane;
+    const unsigned r0 = (unsigned)y * pitch, rm = ym * pitch, rp = yp * pitch, i0 = r0 + x;
+    f[0] = g[i0];
+    f[1] = (lk & 2u) ? (g + 3 * pl)[i0] : (g + 1 * pl)[r0 + xm];
+    f[2] = (lk & 4u) ? (g + 4 * pl)[i0] : (g + 2 * pl)[rm + x];
+    f[3] = (lk & 8u) ? (g + 1 * pl)[i0] : (g + 3 * pl)[r0 + xp];
+    f[4] = (lk & 16u) ? (g + 2 * pl)[i0] : (g + 4 * pl)[rp + x];
+    f[5] = (lk & 32u) ? (g + 7 * pl)[i0] : (g + 5 * pl)[rm + xm];
+    f[6] = (lk & 64u) ? (g + 8 * pl)[i0] : (g + 6 * pl)[rm + xp];
+    f[7] = (lk & 128u) ? (g + 5 * pl)[i0] : (g + 7 * pl)[rp + xp];
+    f[8] = (lk & 256u) ? (g + 6 * pl)[i0] : (g + 8 * pl)[rp + xm];
+}
+
+template <int GEO>
 __device__ __forceinline__ void pull9(const KParams& P, const double* __restrict__ g, int x,
                                       int y, double f[9]) {
+    if constexpr (GEO == GEO_MASK) {
+        pull9_mask(P, g, x, y, P.links[(unsigned)y * P.pitch + x], f);
+        return;
+    }
     const unsigned nx = P.nx, pitch = P.pitch;
     const unsigned ux = x;
     const unsigned xm = ux == 0 ? nx - 1 : ux - 1;
@@ -122,18 +161,34 @@ __device__ __forceinline__ void pull9(const KParams& P, const double* __restrict
     f[4] = top ? (g + 2 * pl)[r0 + ux] : (g + 4 * pl)[rp + ux];
     f[7] = top ? (g + 5 * pl)[r0 + ux] : (g + 7 * pl)[rp + xp];
     f[8] = top ? (g + 6 * pl)[r0 + ux] : (g + 8 * pl)[rp + xm];
-    if (WET && P.wet && (bot || top)) {
+    if (GEO == GEO_WET && P.wet && (bot || top)) {
         // the slots read above for the unknown populations are overwritten by the reconstruction
         if (bot) wet_node_bottom(f, g[rm + ux], (g + pl)[rm + ux]);
         if (top) wet_node_top(f, g[rp + ux], (g + pl)[rp + ux]);
     }
 }
 
+// Any geometry, dispatched at run time (for kernels off the time-step loop).
+__device__ __forceinline__ void pull9_any(const KParams& P, const double* __restrict__ g, int x,
+                                          int y, double f[9]) {
+    if (P.mask) pull9<GEO_MASK>(P, g, x, y, f);
+    else pull9<GEO_WET>(P, g, x, y, f);
+}
+
+__device__ __forceinline__ bool is_solid_node(const KParams& P, int x, int y) {
+    return P.mask && (P.links[(unsigned)y * P.pitch + x] & 1u);
+}
+
 // The fluid node whose psi a lattice slot (gx, gy) holds: gx wraps (periodic x); a solid row
 // takes the adjacent fluid row (mirrored ghost psi) or nothing (psi = 0); rows outside the
-// lattice hold nothing. Returns false when the slot's psi is 0.
+// lattice hold nothing; with a solid mask both coordinates wrap and solid nodes hold nothing.
+// Returns false when the slot's psi is 0.
 __device__ __forceinline__ bool slot_source(const KParams& P, int gx, int gy, int& sx, int& sy) {
     sx = wrapx(gx, P.nx);
+    if (P.mask) {
+        sy = wrapx(gy, P.ny);
+        return (P.links[(unsigned)sy * P.pitch + sx] & 1u) == 0;
+    }
     if (P.walls) {
         if (gy < 0 || gy > P.ny - 1) return false;
         if (gy == 0) { sy = 1; return P.ghost != 0; }
@@ -146,14 +201,14 @@ __device__ __forceinline__ bool slot_source(const KParams& P, int gx, int gy, in
 }
 
 // psi at lattice position (gx, gy) (see slot_source), evaluated from the pulled populations.
-template <bool WET = true>
+template <int GEO>
 __device__ __forceinline__ double psi_at(const KParams& P, const double* __restrict__ g, int gx,
                                          int gy) {
 #pragma clang fp contract(off)
     int sx, sy;
     if (!slot_source(P, gx, gy, sx, sy)) return 0.0;
     double f[9];
-    pull9<WET>(P, g, sx, sy, f);
+    pull9<GEO>(P, g, sx, sy, f);
     return psi_of_rho(P, ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8]);
 }
 
@@ -168,7 +223,7 @@ __device__ __forceinline__ void adhesion_sum(const KParams& P, const double* __r
                                              int x, int y, double& Ax, double& Ay) {
 #pragma clang fp contract(off)
     Ax = 0.0; Ay = 0.0;
-    if (!P.walls) return;
+    if (!P.walls || P.mask) return;
     const int xm = x == 0 ? P.nx - 1 : x - 1;
     const int xp = x == P.nx - 1 ? 0 : x + 1;
     if (y == 1) {  // bottom wall below: e4 (0,-1) w 1/9, e7 (-1,-1) and e8 (1,-1) w 1/36
@@ -181,6 +236,27 @@ __device__ __forceinline__ void adhesion_sum(const KParams& P, const double* __r
         const double gc = gt[x], gm = gt[xm], gp = gt[xp];
         Ax += (gp - gm) * (1.0 / 36.0);
         Ay += fma(gc, 1.0 / 9.0, (gm + gp) * (1.0 / 36.0));
+    }
+}
+
+// Adhesion sum over the solid neighbours of a solid-mask geometry (lk: links of the node; bit
+// opp(a) marks x + e_a solid), in the order a = 1..8.
+__device__ __forceinline__ void adhesion_mask(const KParams& P, int x, int y, unsigned lk,
+                                              double& Ax, double& Ay) {
+#pragma clang fp contract(off)
+    Ax = 0.0; Ay = 0.0;
+    if ((lk & 0x1FEu) == 0) return;
+    const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    const int op[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        if (!((lk >> op[a]) & 1u)) continue;
+        const int xs = wrap_once(x + ex[a], P.nx), ys = wrap_once(y + ey[a], P.ny);
+        const double om = (a < 5 ? 1.0 / 3.0 : 1.0 / 12.0) * (1.0 / 3.0);
+        const double g = P.gwn[(unsigned)ys * P.pitch + xs];
+        Ax = fma(om * g, (double)ex[a], Ax);
+        Ay = fma(om * g, (double)ey[a], Ay);
     }
 }
 
@@ -209,12 +285,12 @@ __device__ __forceinline__ void total_force(const KParams& P, double rho, double
 // With the wet-node scheme, a boundary node stores its force of this step in planes 0 and 1 of
 // the adjacent solid row of the output buffer (o: the output slot of the node, plane stride pl,
 // row stride W). Other nodes store nothing.
-template <bool WET = true>
+template <int GEO>
 __device__ __forceinline__ void store_wall_force(const KParams& P, double* out, long long o,
                                                  long long pl, long long W, int y, double rho,
                                                  double psi_c, double sx, double sy, double Ax,
                                                  double Ay) {
-    if (!WET || !P.wet || (y != 1 && y != P.ny - 2)) return;
+    if (GEO != GEO_WET || !P.wet || (y != 1 && y != P.ny - 2)) return;
     double Fx, Fy;
     total_force(P, rho, psi_c, sx, sy, Ax, Ay, Fx, Fy);
     if (y == 1) { out[o - W] = Fx; out[pl + o - W] = Fy; }
@@ -328,7 +404,7 @@ namespace lbm {
 // threads with the LDS array sp of (TY + 2) * (TX + 2) doubles. FUSED: psi of the tile and its
 // halo is evaluated from the pulled populations; otherwise it is staged from psi_g. Contains
 // __syncthreads() and no early return, so it can run inside loops over tiles.
-template <int TX, int TY, bool FUSED, bool WET>
+template <int TX, int TY, bool FUSED, int GEO>
 __device__ __forceinline__ void step_tile(const KParams& P, const double* __restrict__ gin,
                                           double* __restrict__ gout,
                                           const double* __restrict__ psi_g,
@@ -339,25 +415,28 @@ __device__ __forceinline__ void step_tile(const KParams& P, const double* __rest
     constexpr int NH = 2 * LW + 2 * TY;  // halo slots of a (TX+2) x (TY+2) tile
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int x = x0 + tx, y = y0 + ty;
-    const bool active = x < P.nx && y <= P.y_hi;
+    unsigned lk = 0;  // solid-mask links of the node
+    if (GEO == GEO_MASK && x < P.nx && y <= P.y_hi) lk = P.links[(unsigned)y * P.pitch + x];
+    const bool active = x < P.nx && y <= P.y_hi && !(lk & 1u);
 
     double f[9];
     double rho = 1.0, psi_c = 0.0;
     if (active) {
-        pull9<WET>(P, gin, x, y, f);
+        if constexpr (GEO == GEO_MASK) pull9_mask(P, gin, x, y, lk, f);
+        else pull9<GEO>(P, gin, x, y, f);
         rho = sum9(f);
         if (FUSED) psi_c = psi_of_rho(P, rho);
     }
     if (FUSED) {
         // own slot: computed above, or (outside the fluid) the value at that lattice position
-        sp[(ty + 1) * LW + tx + 1] = active ? psi_c : psi_at<WET>(P, gin, x, y);
+        sp[(ty + 1) * LW + tx + 1] = active ? psi_c : psi_at<GEO>(P, gin, x, y);
         for (int h = threadIdx.x; h < NH; h += NT) {
             int hx, hy;  // tile-local coordinates in [-1, TX] x [-1, TY]
             if (h < LW) { hx = h - 1; hy = -1; }
             else if (h < 2 * LW) { hx = h - LW - 1; hy = TY; }
             else if (h < 2 * LW + TY) { hx = -1; hy = h - 2 * LW; }
             else { hx = TX; hy = h - 2 * LW - TY; }
-            sp[(hy + 1) * LW + hx + 1] = psi_at<WET>(P, gin, x0 + hx, y0 + hy);
+            sp[(hy + 1) * LW + hx + 1] = psi_at<GEO>(P, gin, x0 + hx, y0 + hy);
         }
     } else {
         // stage psi (ghost rows already mirrored by the psi pass) with its halo
@@ -365,7 +444,7 @@ __device__ __forceinline__ void step_tile(const KParams& P, const double* __rest
             const int gy = y0 - 1 + s / LW;
             const int gx = wrapx(x0 - 1 + s % LW, P.nx);
             double v = 0.0;
-            if (P.walls) {
+            if (P.walls && !P.mask) {
                 if (gy >= 0 && gy < P.ny) v = psi_g[(long long)gy * P.pitch + gx];
             } else {
                 v = psi_g[(long long)wrapx(gy, P.ny) * P.pitch + gx];
@@ -381,8 +460,9 @@ __device__ __forceinline__ void step_tile(const KParams& P, const double* __rest
         cohesion_sum(c[-LW - 1], c[-LW], c[-LW + 1], c[-1], c[1], c[LW - 1], c[LW], c[LW + 1],
                      sx, sy);
         double Ax = 0.0, Ay = 0.0;
-        if (P.walls && (y == 1 || y == P.ny - 2)) adhesion_sum(P, gw, x, y, Ax, Ay);
-        store_wall_force<WET>(P, gout, (long long)y * P.pitch + x, P.plane, P.pitch, y, rho,
+        if constexpr (GEO == GEO_MASK) adhesion_mask(P, x, y, lk, Ax, Ay);
+        else if (P.walls && (y == 1 || y == P.ny - 2)) adhesion_sum(P, gw, x, y, Ax, Ay);
+        store_wall_force<GEO>(P, gout, (long long)y * P.pitch + x, P.plane, P.pitch, y, rho,
                               psi_c, sx, sy, Ax, Ay);
         collide(P, f, rho, psi_c, sx, sy, Ax, Ay);
         const unsigned i = (unsigned)y * P.pitch + x;
@@ -403,7 +483,7 @@ namespace lbm {
 //   D  step n+2 on the tile, pulling from g1                              -> gout
 // HBM sees one read and one write of the populations per two steps. Every node's arithmetic is
 // that of step_tile, so two launches of k_step and one of k_step2 give identical bits.
-template <bool WET>
+template <int GEO>
 __device__ __forceinline__ void pull9_lds(const KParams& P, const double* g1, int plane, int W,
                                           int l, int gy, double f[9]) {
     // l: local index of the node in the LDS grid (row stride W); gy: its global row
@@ -417,7 +497,7 @@ __device__ __forceinline__ void pull9_lds(const KParams& P, const double* g1, in
     f[4] = top ? g1[2 * plane + l] : g1[4 * plane + l + W];
     f[7] = top ? g1[5 * plane + l] : g1[7 * plane + l + W + 1];
     f[8] = top ? g1[6 * plane + l] : g1[8 * plane + l + W - 1];
-    if (WET && P.wet && (bot || top)) {
+    if (GEO == GEO_WET && P.wet && (bot || top)) {
         // the force of the boundary node sits in the solid-row slot below (bottom) or above (top)
         if (bot) wet_node_bottom(f, g1[l - W], g1[plane + l - W]);
         if (top) wet_node_top(f, g1[l + W], g1[plane + l + W]);
@@ -433,7 +513,7 @@ struct Step2Lds {
     double ps2[W1 * H1];
 };
 
-template <int TX, int TY, bool WET>
+template <int TX, int TY, int GEO>
 __device__ __forceinline__ void step2_tile(const KParams& P, const double* __restrict__ gin,
                                            double* __restrict__ gout,
                                            const double* __restrict__ gw, int x0, int y0,
@@ -441,6 +521,7 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
     constexpr int NT = TX * TY;
     constexpr int W3 = TX + 6, H3 = TY + 6, W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
     constexpr int PL = W2 * H2;
+    static_assert(GEO != GEO_MASK, "two steps per launch: flat walls only");
     double* g1 = L.g1;
     double* ps1 = L.ps1;
     double* ps2 = L.ps2;
@@ -464,12 +545,12 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
         if (P.walls) fluid = gy >= 1 && gy <= P.ny - 2;
         else { gy = wrapx(gy, P.ny); fluid = true; }
         if (fluid) {
-            pull9<WET>(P, gin, wrapx(x0 - 2 + lx, P.nx), gy, fk[r]);
+            pull9<GEO>(P, gin, wrapx(x0 - 2 + lx, P.nx), gy, fk[r]);
             rk[r] = sum9(fk[r]);
             ps = psi_of_rho(P, rk[r]);
             ok[r] = true;
         } else {
-            ps = psi_at<WET>(P, gin, x0 - 2 + lx, y0 - 2 + ly);  // solid row: ghost value or 0
+            ps = psi_at<GEO>(P, gin, x0 - 2 + lx, y0 - 2 + ly);  // solid row: ghost value or 0
         }
         ps1[(ly + 1) * W3 + lx + 1] = ps;
     }
@@ -480,7 +561,7 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
         else if (h < 2 * W3) { lx = h - W3; ly = H3 - 1; }
         else if (h < 2 * W3 + H2) { lx = 0; ly = h - 2 * W3 + 1; }
         else { lx = W3 - 1; ly = h - 2 * W3 - H2 + 1; }
-        ps1[ly * W3 + lx] = psi_at<WET>(P, gin, x0 - 3 + lx, y0 - 3 + ly);
+        ps1[ly * W3 + lx] = psi_at<GEO>(P, gin, x0 - 3 + lx, y0 - 3 + ly);
     }
     __syncthreads();
 
@@ -500,8 +581,8 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
         if (P.walls && (gy == 1 || gy == P.ny - 2)) adhesion_sum(P, gw, gx, gy, Ax, Ay);
         // a boundary node's force feeds the reconstruction of step n+2, which only nodes of R1
         // perform; those have their solid-row slot inside R2
-        if (WET && P.wet && ly >= 1 && ly <= H2 - 2)
-            store_wall_force<WET>(P, g1, s, PL, W2, gy, rk[r], c[0], sx, sy, Ax, Ay);
+        if (GEO == GEO_WET && P.wet && ly >= 1 && ly <= H2 - 2)
+            store_wall_force<GEO>(P, g1, s, PL, W2, gy, rk[r], c[0], sx, sy, Ax, Ay);
         collide(P, fk[r], rk[r], c[0], sx, sy, Ax, Ay);
 #pragma unroll
         for (int a = 0; a < 9; ++a) g1[a * PL + s] = fk[r][a];
@@ -518,7 +599,7 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
             // the source node in the R2 grid: same column, row sy (mirrored rows stay adjacent)
             const int ly2 = P.walls ? sy - (y0 - 2) : ly + 1;
             double f[9];
-            pull9_lds<WET>(P, g1, PL, W2, ly2 * W2 + lx + 1, sy, f);
+            pull9_lds<GEO>(P, g1, PL, W2, ly2 * W2 + lx + 1, sy, f);
             v = psi_of_rho(P, sum9(f));
         }
         ps2[s] = v;
@@ -530,7 +611,7 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
     const int x = x0 + tx, y = y0 + ty;
     if (x < P.nx && y <= P.y_hi) {
         double f[9];
-        pull9_lds<WET>(P, g1, PL, W2, (ty + 2) * W2 + tx + 2, y, f);
+        pull9_lds<GEO>(P, g1, PL, W2, (ty + 2) * W2 + tx + 2, y, f);
         const double rho = sum9(f);
         const double* c = ps2 + (ty + 1) * W1 + tx + 1;
         double sx, sy;
@@ -538,7 +619,7 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
                      sx, sy);
         double Ax = 0.0, Ay = 0.0;
         if (P.walls && (y == 1 || y == P.ny - 2)) adhesion_sum(P, gw, x, y, Ax, Ay);
-        store_wall_force<WET>(P, gout, (long long)y * P.pitch + x, P.plane, P.pitch, y, rho, c[0],
+        store_wall_force<GEO>(P, gout, (long long)y * P.pitch + x, P.plane, P.pitch, y, rho, c[0],
                               sx, sy, Ax, Ay);
         collide(P, f, rho, c[0], sx, sy, Ax, Ay);
         const unsigned i = (unsigned)y * P.pitch + x;

@@ -19,8 +19,8 @@ namespace lbm {
 // ------------------------------------------------------------------------------------------------
 // Time step
 // ------------------------------------------------------------------------------------------------
-// WET: compiled with the wet-node wall rule (launched for wall mode 2 only).
-template <int TX, int TY, bool FUSED, bool WET>
+// GEO: the geometry variant compiled in (GEO_ROWS, GEO_WET, GEO_MASK), chosen at launch.
+template <int TX, int TY, bool FUSED, int GEO>
 __global__ __launch_bounds__(TX* TY) void k_step(KParams P, const double* __restrict__ gin,
                                                  double* __restrict__ gout,
                                                  const double* __restrict__ psi_g,
@@ -29,7 +29,7 @@ __global__ __launch_bounds__(TX* TY) void k_step(KParams P, const double* __rest
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
     const int tile = xcd_tile(blockIdx.x, ntx * nty);
-    step_tile<TX, TY, FUSED, WET>(P, gin, gout, psi_g, gw, (tile % ntx) * TX,
+    step_tile<TX, TY, FUSED, GEO>(P, gin, gout, psi_g, gw, (tile % ntx) * TX,
                                   P.y_lo + (tile / ntx) * TY, sp);
 }
 
@@ -37,7 +37,7 @@ __global__ __launch_bounds__(TX* TY) void k_step(KParams P, const double* __rest
 // side, and the workgroup has TYI interior rows plus a halo row above and below. Every thread
 // pulls exactly one node and evaluates its psi (one memory round trip per tile, all loads
 // coalesced rows); the interior threads then collide and store.
-template <int TYI, bool WET>
+template <int TYI, int GEO>
 __global__ __launch_bounds__(64 * (TYI + 2)) void k_step_ov(KParams P,
                                                             const double* __restrict__ gin,
                                                             double* __restrict__ gout,
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(64 * (TYI + 2)) void k_step_ov(KParams P,
     double f[9];
     double rho = 1.0, psi_c = 0.0;
     if (has) {
-        pull9<WET>(P, gin, sx, sy, f);
+        pull9<GEO>(P, gin, sx, sy, f);
         rho = sum9(f);
         psi_c = psi_of_rho(P, rho);
     }
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(64 * (TYI + 2)) void k_step_ov(KParams P,
                  syy);
     double Ax = 0.0, Ay = 0.0;
     if (P.walls && (gy == 1 || gy == P.ny - 2)) adhesion_sum(P, gw, gx, gy, Ax, Ay);
-    store_wall_force<WET>(P, gout, (long long)gy * P.pitch + gx, P.plane, P.pitch, gy, rho, psi_c,
+    store_wall_force<GEO>(P, gout, (long long)gy * P.pitch + gx, P.plane, P.pitch, gy, rho, psi_c,
                           sxx, syy, Ax, Ay);
     collide(P, f, rho, psi_c, sxx, syy, Ax, Ay);
     const unsigned i = (unsigned)gy * P.pitch + gx;
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(64 * (TYI + 2)) void k_step_ov(KParams P,
 }
 
 // Two steps per launch over TX x TY output tiles (step2_tile).
-template <int TX, int TY, bool WET>
+template <int TX, int TY, int GEO>
 __global__ __launch_bounds__(TX* TY) void k_step2(KParams P, const double* __restrict__ gin,
                                                   double* __restrict__ gout,
                                                   const double* __restrict__ gw) {
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(TX* TY) void k_step2(KParams P, const double* __res
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
     const int tile = xcd_tile(blockIdx.x, ntx * nty);
-    step2_tile<TX, TY, WET>(P, gin, gout, gw, (tile % ntx) * TX, P.y_lo + (tile / ntx) * TY, lds);
+    step2_tile<TX, TY, GEO>(P, gin, gout, gw, (tile % ntx) * TX, P.y_lo + (tile / ntx) * TY, lds);
 }
 
 // psi pass of the two-pass schedule; also writes the mirrored ghost rows.
@@ -99,13 +99,18 @@ __global__ __launch_bounds__(256) void k_psi(KParams P, const double* __restrict
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = P.y_lo + blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= P.nx || y > P.y_hi) return;
+    if (is_solid_node(P, x, y)) {  // solid mask: psi = 0, density reported as 0
+        psi_g[(long long)y * P.pitch + x] = 0.0;
+        if (rho_out) rho_out[(long long)y * P.pitch + x] = 0.0;
+        return;
+    }
     double f[9];
-    pull9(P, gin, x, y, f);
+    pull9_any(P, gin, x, y, f);
     const double rho = sum9(f);
     const double ps = psi_of_rho(P, rho);
     psi_g[(long long)y * P.pitch + x] = ps;
     if (rho_out) rho_out[(long long)y * P.pitch + x] = rho;
-    if (P.walls && P.ghost) {
+    if (P.walls && !P.mask && P.ghost) {
         if (y == 1) psi_g[x] = ps;
         if (y == P.ny - 2) psi_g[(long long)(P.ny - 1) * P.pitch + x] = ps;
     }
@@ -122,16 +127,19 @@ __global__ __launch_bounds__(256) void k_init(KParams P, const double* __restric
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = P.y_lo + blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= P.nx || y > P.y_hi) return;
+    if (is_solid_node(P, x, y)) return;
     const double r = rho0[(long long)y * P.pitch + x];
     const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
     const int op[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    const unsigned lk = P.mask ? P.links[(unsigned)y * P.pitch + x] : 0u;
     for (int a = 0; a < 9; ++a) {
         const double t = a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
         int sx = wrapx(x - ex[a], P.nx);
         int sy = y - ey[a];
         bool solid = false;
-        if (P.walls) solid = (sy == 0 || sy == P.ny - 1);
+        if (P.mask) { solid = (lk >> a) & 1u; sy = wrapx(sy, P.ny); }
+        else if (P.walls) solid = (sy == 0 || sy == P.ny - 1);
         else sy = wrapx(sy, P.ny);
         if (solid) g[op[a] * P.plane + (long long)y * P.pitch + x] = t * r;
         else g[a * P.plane + (long long)sy * P.pitch + sx] = t * r;
@@ -143,9 +151,9 @@ __global__ __launch_bounds__(256) void k_pull(KParams P, const double* __restric
                                               double* __restrict__ fout) {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = P.y_lo + blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (x >= P.nx || y > P.y_hi) return;
+    if (x >= P.nx || y > P.y_hi || is_solid_node(P, x, y)) return;
     double f[9];
-    pull9(P, gin, x, y, f);
+    pull9_any(P, gin, x, y, f);
     for (int a = 0; a < 9; ++a) fout[a * P.plane + (long long)y * P.pitch + x] = f[a];
 }
 
@@ -186,20 +194,21 @@ __global__ __launch_bounds__(256) void k_obs(KParams P, const double* __restrict
     const int y = P.y_lo + blockIdx.y * 4 + (threadIdx.x >> 6);
     double v[O_NQ];
     for (int q = 0; q < O_NQ; ++q) v[q] = op_identity(q);
-    if (x < P.nx && y <= P.y_hi) {
+    if (x < P.nx && y <= P.y_hi && !is_solid_node(P, x, y)) {
         const long long i = (long long)y * P.pitch + x;
         double f[9];
-        pull9(P, gin, x, y, f);
+        pull9_any(P, gin, x, y, f);
         const double rho = rho_f[i], pc = psi_g[i];
         const int xm = x == 0 ? P.nx - 1 : x - 1, xp = x == P.nx - 1 ? 0 : x + 1;
         int ym = y - 1, yp = y + 1;
-        if (!P.walls) { ym = wrapx(ym, P.ny); yp = wrapx(yp, P.ny); }
+        if (!P.walls || P.mask) { ym = wrapx(ym, P.ny); yp = wrapx(yp, P.ny); }
         const double* rm = psi_g + (long long)ym * P.pitch;
         const double* r0 = psi_g + (long long)y * P.pitch;
         const double* rp = psi_g + (long long)yp * P.pitch;
         double sx, sy, Ax = 0.0, Ay = 0.0, vx, vy;
         cohesion_sum(rm[xm], rm[x], rm[xp], r0[xm], r0[xp], rp[xm], rp[x], rp[xp], sx, sy);
-        adhesion_sum(P, gw, x, y, Ax, Ay);
+        if (P.mask) adhesion_mask(P, x, y, P.links[(unsigned)i], Ax, Ay);
+        else adhesion_sum(P, gw, x, y, Ax, Ay);
         velocity(P, f, rho, pc, sx, sy, Ax, Ay, vx, vy);
         const double u = sqrt(vx * vx + vy * vy);
         const bool ok = isfinite(rho) && isfinite(pc) && isfinite(u);
@@ -210,7 +219,7 @@ __global__ __launch_bounds__(256) void k_obs(KParams P, const double* __restrict
         }
         // interface crossings on the edges to the right and upper neighbours
         const bool la = rho >= A.rho_mid;
-        if (x + 1 < P.nx) {
+        if (x + 1 < P.nx && !is_solid_node(P, x + 1, y)) {
             const double rb = rho_f[i + 1];
             if ((rb >= A.rho_mid) != la) {
                 const double t = (A.rho_mid - rho) / (rb - rho);
@@ -218,7 +227,7 @@ __global__ __launch_bounds__(256) void k_obs(KParams P, const double* __restrict
                 if (py >= A.y_min && px >= A.x_lo && px < A.x_hi) add_point(v, px, py, A.cx, A.cy);
             }
         }
-        if (y + 1 <= P.y_hi) {
+        if (y + 1 <= P.y_hi && !is_solid_node(P, x, y + 1)) {
             const double rb = rho_f[i + P.pitch];
             if ((rb >= A.rho_mid) != la) {
                 const double t = (A.rho_mid - rho) / (rb - rho);
@@ -274,11 +283,14 @@ static hipError_t launch_step_t(const KParams& P, const double* gin, double* gou
                                 const double* psi, const double* gw, hipStream_t s) {
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
-    if (P.wet)
-        hipLaunchKernelGGL((k_step<TX, TY, FUSED, true>), dim3(ntx * nty), dim3(TX * TY), 0, s, P,
-                           gin, gout, psi, gw);
+    if (P.mask)
+        hipLaunchKernelGGL((k_step<TX, TY, FUSED, GEO_MASK>), dim3(ntx * nty), dim3(TX * TY), 0, s,
+                           P, gin, gout, psi, gw);
+    else if (P.wet)
+        hipLaunchKernelGGL((k_step<TX, TY, FUSED, GEO_WET>), dim3(ntx * nty), dim3(TX * TY), 0, s,
+                           P, gin, gout, psi, gw);
     else
-        hipLaunchKernelGGL((k_step<TX, TY, FUSED, false>), dim3(ntx * nty), dim3(TX * TY), 0, s,
+        hipLaunchKernelGGL((k_step<TX, TY, FUSED, GEO_ROWS>), dim3(ntx * nty), dim3(TX * TY), 0, s,
                            P, gin, gout, psi, gw);
     return hipGetLastError();
 }
@@ -289,10 +301,10 @@ static hipError_t launch_step_ov(const KParams& P, const double* gin, double* go
     const int ntx = (P.nx + 61) / 62;
     const int nty = (P.y_hi - P.y_lo + TYI) / TYI;
     if (P.wet)
-        hipLaunchKernelGGL((k_step_ov<TYI, true>), dim3(ntx * nty), dim3(64 * (TYI + 2)), 0, s, P,
-                           gin, gout, gw);
+        hipLaunchKernelGGL((k_step_ov<TYI, GEO_WET>), dim3(ntx * nty), dim3(64 * (TYI + 2)), 0, s,
+                           P, gin, gout, gw);
     else
-        hipLaunchKernelGGL((k_step_ov<TYI, false>), dim3(ntx * nty), dim3(64 * (TYI + 2)), 0, s,
+        hipLaunchKernelGGL((k_step_ov<TYI, GEO_ROWS>), dim3(ntx * nty), dim3(64 * (TYI + 2)), 0, s,
                            P, gin, gout, gw);
     return hipGetLastError();
 }
@@ -303,11 +315,11 @@ static hipError_t launch_step2_t(const KParams& P, const double* gin, double* go
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
     if (P.wet)
-        hipLaunchKernelGGL((k_step2<TX, TY, true>), dim3(ntx * nty), dim3(TX * TY), 0, s, P, gin,
-                           gout, gw);
+        hipLaunchKernelGGL((k_step2<TX, TY, GEO_WET>), dim3(ntx * nty), dim3(TX * TY), 0, s, P,
+                           gin, gout, gw);
     else
-        hipLaunchKernelGGL((k_step2<TX, TY, false>), dim3(ntx * nty), dim3(TX * TY), 0, s, P, gin,
-                           gout, gw);
+        hipLaunchKernelGGL((k_step2<TX, TY, GEO_ROWS>), dim3(ntx * nty), dim3(TX * TY), 0, s, P,
+                           gin, gout, gw);
     return hipGetLastError();
 }
 

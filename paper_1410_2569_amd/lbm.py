@@ -19,7 +19,7 @@ ABI_VERSION = 1
 OK, E_INVAL, E_SIZE, E_HIP, E_NONFINITE, E_ABI, E_STATE = 0, -1, -2, -3, -4, -5, -6
 WALL = {"rho": 0, "psi": 1, "modpsi": 2}
 EOS = {"cs": 0, "piecewise": 1}
-WALLS = {"periodic": 0, "bounce_back": 1, "wet_node": 2}
+WALLS = {"periodic": 0, "bounce_back": 1, "wet_node": 2, "mask": 3}
 SCHEDULE = {"fused": 0, "two_pass": 1, "two_step": 2}
 
 
@@ -74,6 +74,10 @@ SIGNATURES = {
     "lbm_step": (C.c_int, [C.c_void_p, C.c_int64]),
     "lbm_observables": (C.c_int, [C.c_void_p, C.POINTER(Obs)]),
     "lbm_observables_window": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.POINTER(Obs)]),
+    "lbm_observables_plane": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double,
+                                        C.POINTER(Obs)]),
+    "lbm_create_masked": (C.c_int, [_P, C.c_void_p, _dp, _dp, C.c_void_p, C.c_size_t, C.c_void_p,
+                                    C.POINTER(C.c_void_p)]),
     "lbm_read_rho": (C.c_int, [C.c_void_p, _dp, C.c_size_t]),
     "lbm_read_f": (C.c_int, [C.c_void_p, _dp, C.c_size_t]),
     "lbm_state_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
@@ -198,24 +202,36 @@ def workspace_size(q: Params) -> int:
 
 
 class Sim:
-    """One lattice on the current HIP device, in a torch-allocated workspace."""
+    """One lattice on the current HIP device, in a torch-allocated workspace. With
+    walls = 3 ("mask") pass the solid mask ((ny, nx), nonzero = solid) as `solid` (or under
+    params["solid"]) and G_w per node, shape (ny, nx)."""
 
-    def __init__(self, params, gw, rho0, device="cuda", stream=None):
+    def __init__(self, params, gw, rho0, device="cuda", stream=None, solid=None):
         import torch
 
+        if solid is None and isinstance(params, dict):
+            solid = params.get("solid")
         self.q = params if isinstance(params, Params) else make_params(params)
         self.nx, self.ny = self.q.nx, self.q.ny
+        self.masked = self.q.walls == WALLS["mask"]
         nbytes = workspace_size(self.q)
         # 256-byte aligned: torch's caching allocator hands out 512-byte aligned blocks
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
-        g = np.ascontiguousarray(gw if gw is not None else np.zeros((2, self.nx)),
-                                 dtype=np.float64)
+        gshape = (self.ny, self.nx) if self.masked else (2, self.nx)
+        g = np.ascontiguousarray(gw if gw is not None else np.zeros(gshape), dtype=np.float64)
         r = np.ascontiguousarray(rho0, dtype=np.float64)
-        assert g.shape == (2, self.nx) and r.shape == (self.ny, self.nx)
+        assert g.shape == gshape and r.shape == (self.ny, self.nx)
         h = C.c_void_p()
-        check(lib().lbm_create(C.byref(self.q), _dptr(g), _dptr(r), C.c_void_p(self.ws.data_ptr()),
-                               nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        ws, st = C.c_void_p(self.ws.data_ptr()), C.c_void_p(self.stream.cuda_stream)
+        if self.masked:
+            m = np.ascontiguousarray(np.asarray(solid) != 0, dtype=np.uint8)
+            assert m.shape == (self.ny, self.nx)
+            check(lib().lbm_create_masked(C.byref(self.q), m.ctypes.data_as(C.c_void_p),
+                                          _dptr(g), _dptr(r), ws, nbytes, st, C.byref(h)))
+        else:
+            check(lib().lbm_create(C.byref(self.q), _dptr(g), _dptr(r), ws, nbytes, st,
+                                   C.byref(h)))
         self.h = h
 
     def __del__(self):
@@ -238,9 +254,14 @@ class Sim:
     def current_step(self) -> int:
         return lib().lbm_current_step(self.h)
 
-    def observables(self, x_lo=-math.inf, x_hi=math.inf, allow_nonfinite=False) -> dict:
+    def observables(self, x_lo=-math.inf, x_hi=math.inf, allow_nonfinite=False,
+                    y_wall=None) -> dict:
+        """Observables; y_wall: contact plane of the angle fit (default: the wall plane)."""
         o = Obs()
-        rc = lib().lbm_observables_window(self.h, x_lo, x_hi, C.byref(o))
+        if y_wall is None:
+            rc = lib().lbm_observables_window(self.h, x_lo, x_hi, C.byref(o))
+        else:
+            rc = lib().lbm_observables_plane(self.h, x_lo, x_hi, float(y_wall), C.byref(o))
         if rc == E_NONFINITE and allow_nonfinite:
             return o.as_dict()
         self._chk(rc)
@@ -268,7 +289,7 @@ class Sim:
 
     def set_gw(self, gw):
         g = np.ascontiguousarray(gw, dtype=np.float64)
-        assert g.shape == (2, self.nx)
+        assert g.shape == ((self.ny, self.nx) if self.masked else (2, self.nx))
         self._chk(lib().lbm_set_gw(self.h, _dptr(g)))
 
     # ---- adjoint -----------------------------------------------------------------------------

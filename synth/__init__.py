@@ -243,6 +243,52 @@ def paper_figures() -> list[dict]:
     return [paper_setup(form, g) for form in FORMS for g in PAPER_GW[form]]
 
 
+# Rough surface of Sec. III.B: a 300 x 150 lattice, square pillars 20 nodes high and 6 wide with
+# gaps of 3 on a flat base, a droplet of R = 30 on the pillar tops; Eq. (7) is not applied across
+# the solid (no ghost layer).
+ROUGH = dict(nx=300, ny=150, height=20, width=6, gap=3, radius=30.0)
+# G_w printed in Table II for the rough-surface comparison.
+ROUGH_GW = {"rho": 0.255, "modpsi": 0.375}
+
+
+def pillar_mask(nx: int = ROUGH["nx"], ny: int = ROUGH["ny"], height: int = ROUGH["height"],
+                width: int = ROUGH["width"], gap: int = ROUGH["gap"]) -> np.ndarray:
+    """Solid mask (ny, nx), 1 = solid: a base row y = 0, a top row y = ny-1, and pillars
+    occupying rows 1 .. height in columns whose position within the period width + gap is below
+    width; the pattern is centred so that x = nx/2 is the middle of a pillar. height = 0 gives
+    the flat reference surface."""
+    m = np.zeros((ny, nx), dtype=np.uint8)
+    m[0, :] = 1
+    m[ny - 1, :] = 1
+    if height > 0:
+        period = width + gap
+        x = np.arange(nx)
+        off = (nx // 2 - width // 2) % period
+        pil = ((x - off) % period) < width
+        m[1:height + 1, pil] = 1
+    return m
+
+
+def rough_setup(form: str, gw_printed: float, height: int = ROUGH["height"],
+                gw_scale: float | None = None, lift: float = 0.0, seed: int = 17) -> dict:
+    """The rough-surface case of Sec. III.B (height = 0: the same flat base without pillars).
+    Bottom surface plane y_s = height + 0.5 (halfway bounce-back); droplet of R = 30 centred at
+    (nx/2, y_s + R + lift); every solid node carries G_w = scale x printed, the top row 0."""
+    nx, ny = ROUGH["nx"], ROUGH["ny"]
+    m = pillar_mask(nx, ny, height)
+    scale = PAPER_GW_SCALE[form] if gw_scale is None else gw_scale
+    gw = np.where(m != 0, scale * gw_printed, 0.0)
+    gw[ny - 1, :] = 0.0
+    y_s = height + 0.5
+    rho0 = droplet_rho(nx, ny, PAPER["rho_l"], PAPER["rho_v"],
+                       [(nx / 2.0, y_s + ROUGH["radius"] + lift)], [ROUGH["radius"]], width=4.0,
+                       seed=seed, walls=False)
+    rho0[m != 0] = 0.0
+    p = paper_params(nx=nx, ny=ny, walls=3, ghost=0, wall_force=form, solid=m)
+    return dict(params=p, gw=gw, rho0=rho0, mask=m, y_surface=y_s, form=form,
+                gw_printed=gw_printed)
+
+
 def c1_small() -> dict:
     """120x60, psi-based wall force G_w = -0.2 on both walls, droplet R = 20 on the bottom wall,
     10,000 steps."""
