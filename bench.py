@@ -388,6 +388,96 @@ def paper_run(args) -> dict:
     return out
 
 
+# G_w at which the flat surface of the rough-surface setup gives about 138 degrees in this model
+# (psi = 0 on solid nodes), found by a scan; the printed 0.255 / 0.375 detach the droplet here.
+ROUGH_CASES = (("rho", -1.86), ("modpsi", -2.76))
+
+
+def rough_run(args) -> dict:
+    """Sec. III.B: flat and pillared surfaces (300 x 150, pillars 20 x 6, gaps 3), Eq. (15),
+    density-based and modified forms; each run advanced by --rough-steps steps with the fused
+    kernel. Reports the apparent angle against Cassie's law, Eq. (17), applied to the flat angle
+    of the same G_w, the liquid fraction of the gaps under the droplet, and Table II's densities."""
+    import numpy as np
+
+    import paper_1410_2569_amd as L
+    import synth
+
+    N = args.rough_steps
+    fr = synth.ROUGH["width"] / (synth.ROUGH["width"] + synth.ROUGH["gap"])
+    rows, lu, secs = [], 0, 0.0
+    for form, g in ROUGH_CASES:
+        res = {}
+        for h in (0, synth.ROUGH["height"]):
+            c = synth.rough_setup(form, g, height=h, gw_scale=1.0)
+            s = L.Sim(c["params"], c["gw"], c["rho0"])
+            s.step(args.warmup)
+            t = _timed(lambda: s.step(N))
+            fluid = int((c["mask"] == 0).sum())
+            lu += fluid * N
+            secs += t
+            o = s.observables(allow_nonfinite=True, y_wall=c["y_surface"])
+            rho = s.rho()
+            mid = 0.5 * (c["params"]["rho_l"] + c["params"]["rho_v"])
+            gap_fill = None
+            if h:
+                foot = rho[h + 1] >= mid  # columns under the droplet, just above the tops
+                gaps = (c["mask"][1:h + 1] == 0) & foot[None, :]
+                gap_fill = round(float((rho[1:h + 1][gaps] >= mid).mean()), 3) if gaps.any() else 0.0
+            res[h] = dict(theta=None if math.isnan(o["theta_deg"]) else round(o["theta_deg"], 2),
+                          rho_min=round(o["rho_min"], 4), rho_max=round(o["rho_max"], 2),
+                          gap_liquid_fraction=gap_fill, seconds=round(t, 3))
+        flat, rough = res[0], res[synth.ROUGH["height"]]
+        cassie = None
+        if flat["theta"] is not None:
+            cassie = round(math.degrees(math.acos(fr * math.cos(math.radians(flat["theta"]))
+                                                  + fr - 1.0)), 2)
+        rows.append({"form": form, "G_w": g, "flat": flat, "rough": rough,
+                     "cassie_from_flat": cassie})
+        log("rough:", rows[-1])
+    mlups = lu / secs / 1e6
+    avg = secs / (len(ROUGH_CASES) * 2 * N)
+    fluid_avg = lu / (len(ROUGH_CASES) * 2 * N)
+    ach = BYTES_PER_LU * fluid_avg / avg / 1e9
+    out = {"metric": "MLUPS of the rough-surface runs (Sec. III.B)", "value": round(mlups, 1),
+           "unit": "MLUPS", "n_gpus": 1, "steps": N, "warmup": args.warmup,
+           "ms_per_step": round(avg * 1e3, 6), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "300x150, flat base or pillars 20 high, 6 wide, gaps 3; Eq. (15); "
+                                  "droplet R=30; density-based and modified forms; one lattice "
+                                  "per run", "runs": 2 * len(ROUGH_CASES)},
+           "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "lbm::k_step<64,8,true,GEO_MASK>", "bytes_per_lu": BYTES_PER_LU,
+                        "lu_per_launch": round(fluid_avg), "avg_launch_us": round(avg * 1e6, 3)},
+           "cases": rows}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = rough_cpu_baseline()
+    return out
+
+
+def rough_cpu_baseline(budget_s: float = 12.0) -> dict:
+    """Oracle on the pillared density-based case: as many steps as fit the budget."""
+    import oracle
+    import synth
+
+    form, g = ROUGH_CASES[0]
+    c = synth.rough_setup(form, g, gw_scale=1.0)
+    q = oracle.make_params(c["params"])
+    f = oracle.init_rest(q, c["rho0"])
+    oracle.run(q, c["gw"], f, 1)
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        oracle.run(q, c["gw"], f, 20)
+        steps += 20
+    dt = time.perf_counter() - t0
+    fluid = int((c["mask"] == 0).sum())
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    return {"value": round(fluid * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle", "sample": f"{steps} steps of the pillared 300x150 case ({form}, "
+                                        f"G_w {g}), {dt:.1f} s"}
+
+
 COPY_BYTES = 9 * 512 * 1024 * 8  # one population buffer of the 1024x512 workload
 
 
@@ -437,12 +527,13 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=20_000)
     ap.add_argument("--adj-fd-runs", type=int, default=64,
                     help="forward runs timed for the finite-difference baseline (of 512)")
-    ap.add_argument("--workload", default="sweep", choices=["sweep", "c5", "paper"],
+    ap.add_argument("--workload", default="sweep", choices=["sweep", "c5", "paper", "rough"],
                     help="sweep: the 1024x512 sweep (default); c5: 8 x 2048x1024 ensemble with "
                          "six droplets each, forward in one persistent launch, adjoint over "
                          "the last 2,000 steps; paper: the printed points of Figs. 2-4 in the "
-                         "paper's own setup")
+                         "paper's own setup; rough: flat and pillared surfaces of Sec. III.B")
     ap.add_argument("--paper-steps", type=int, default=30_000)
+    ap.add_argument("--rough-steps", type=int, default=100_000)
     ap.add_argument("--c5-steps", type=int, default=30_000)
     ap.add_argument("--c5-adj-steps", type=int, default=2_000)
     ap.add_argument("--c5-K", type=int, default=45)
@@ -475,6 +566,9 @@ def main():
         return
     if args.workload == "paper":
         print(json.dumps(paper_run(args)), flush=True)
+        return
+    if args.workload == "rough":
+        print(json.dumps(rough_run(args)), flush=True)
         return
     runs = synth.c2_sweep()[: args.runs]
     sims = []
