@@ -478,6 +478,101 @@ def rough_cpu_baseline(budget_s: float = 12.0) -> dict:
                                         f"G_w {g}), {dt:.1f} s"}
 
 
+SPREAD_WINDOW = (0.2, 1.5)  # t / tau_rho: the inertial regime, t comparable to tau_rho
+
+
+def spreading_run(args) -> dict:
+    """Sec. III.B dynamic wetting: the surface tension from the Laplace law (five free droplets
+    as one ensemble), then the three spreading runs of Fig. 7 (modified form, printed G_w -0.3,
+    -0.1, 0.2) with the contact line recorded on the device every 10 steps, and the power law
+    r/R = C (t/tau)^n fitted over SPREAD_WINDOW."""
+    import numpy as np
+    import torch
+
+    import paper_1410_2569_amd as L
+    import synth
+    from paper_1410_2569_amd import analysis as A
+
+    lap = synth.laplace_setup()
+    b = L.Batch([c["params"] for c in lap], [np.zeros((2, c["params"]["nx"])) for c in lap],
+                [c["rho0"] for c in lap])
+    b.step(30_000)
+    radii, dp = [], []
+    for i, c in enumerate(lap):
+        rho = b.f(i).sum(0)
+        n = rho.shape[0]
+        radii.append(math.sqrt(((rho - 1.0) / 499.0).sum() / math.pi))
+        dp.append(L.lbm.pressure(c["params"], rho[n // 2, n // 2])
+                  - L.lbm.pressure(c["params"], rho[0, 0]))
+    gamma, icpt = A.laplace_gamma(radii, dp)
+    del b
+    tau = A.inertial_time(synth.PAPER["rho_l"], synth.PAPER["radius"], gamma)
+    log(f"spreading: gamma {gamma:.4f} (intercept {icpt:.4f}), tau_rho {tau:.1f} steps")
+    N, every = args.spread_steps, 10
+    rows, lu, secs = [], 0, 0.0
+    for gp in synth.SPREAD_GW:
+        c = synth.spreading_setup(gp)
+        s = L.Sim(c["params"], c["gw"], c["rho0"])
+        holder = {}
+        t = _timed(lambda: holder.setdefault("s", s.record_contact_line(N, every, row=1)))
+        a = holder["s"].cpu().numpy()
+        fluid = c["params"]["nx"] * (c["params"]["ny"] - 2)
+        lu += fluid * N
+        secs += t
+        r = 0.5 * (a[:, 1] - a[:, 0]) / synth.PAPER["radius"]
+        tt = np.arange(len(r)) * every / tau
+        C, n, k = A.fit_power_law(tt, r, *SPREAD_WINDOW)
+        C2, n2, _ = A.fit_power_law(tt, r, 0.1, 1.0)
+        o = s.observables(allow_nonfinite=True)
+        rows.append({"G_w_printed": gp, "G_w": float(c["gw"][0, 0]), "n": round(n, 4),
+                     "C": round(C, 4), "n_printed": synth.SPREAD_EXPONENT[gp],
+                     "n_window_0.1_1.0": round(n2, 4), "samples": k,
+                     "theta_end": None if math.isnan(o["theta_deg"]) else round(o["theta_deg"], 2),
+                     "theta_printed": synth.SPREAD_ANGLE[gp], "r_over_R_end": round(float(r[-1]), 4)})
+        log("spreading:", rows[-1])
+    mlups = lu / secs / 1e6
+    launches = N // 2  # two-step launches per run (the default schedule)
+    return {"metric": "MLUPS of the dynamic-wetting runs (Sec. III.B) with device-side contact-line "
+                      "recording", "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+            "steps": N, "warmup": 0, "ms_per_step": round(secs / (3 * N) * 1e3, 6),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "paper setup 300x100 fluid nodes, wet-node walls, modified form, "
+                                   "droplet R=30 released 2 nodes above the wall, printed G_w -0.3, "
+                                   "-0.1, 0.2; contact line recorded every 10 steps", "runs": 3},
+            "roofline": {"bound": "hbm",
+                         "achieved": round(BYTES_PER_LU * lu / secs / 1e9, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(BYTES_PER_LU * lu / secs / 1e9 / HBM_PEAK_GBS, 4),
+                         "traffic": None, "kernel": "lbm::k_step2<64,8,GEO_WET> + k_contact_line",
+                         "bytes_per_lu": BYTES_PER_LU, "lu_per_launch": 2 * 30000,
+                         "avg_launch_us": round(secs / (3 * launches) * 1e6, 3)},
+            "gamma": round(gamma, 5), "laplace_intercept": round(icpt, 5),
+            "tau_rho_steps": round(tau, 1), "fit_window_t_over_tau": list(SPREAD_WINDOW),
+            "runs": rows}
+
+
+def spreading_cpu_baseline(budget_s: float = 12.0) -> dict:
+    """Oracle on the first spreading run: as many steps as fit the budget."""
+    import oracle
+    import synth
+
+    c = synth.spreading_setup(synth.SPREAD_GW[0])
+    q = oracle.make_params(c["params"])
+    f = oracle.init_rest(q, c["rho0"])
+    oracle.run(q, c["gw"], f, 1)
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        oracle.run(q, c["gw"], f, 20)
+        steps += 20
+    dt = time.perf_counter() - t0
+    fluid = q.nx * (q.ny - 2)
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    return {"value": round(fluid * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle", "sample": f"{steps} steps of the spreading run at printed G_w "
+                                        f"{synth.SPREAD_GW[0]}, {dt:.1f} s"}
+
+
 COPY_BYTES = 9 * 512 * 1024 * 8  # one population buffer of the 1024x512 workload
 
 
@@ -527,13 +622,16 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=20_000)
     ap.add_argument("--adj-fd-runs", type=int, default=64,
                     help="forward runs timed for the finite-difference baseline (of 512)")
-    ap.add_argument("--workload", default="sweep", choices=["sweep", "c5", "paper", "rough"],
+    ap.add_argument("--workload", default="sweep",
+                    choices=["sweep", "c5", "paper", "rough", "spreading"],
                     help="sweep: the 1024x512 sweep (default); c5: 8 x 2048x1024 ensemble with "
                          "six droplets each, forward in one persistent launch, adjoint over "
                          "the last 2,000 steps; paper: the printed points of Figs. 2-4 in the "
-                         "paper's own setup; rough: flat and pillared surfaces of Sec. III.B")
+                         "paper's own setup; rough: flat and pillared surfaces of Sec. III.B; "
+                         "spreading: dynamic wetting of Sec. III.B")
     ap.add_argument("--paper-steps", type=int, default=30_000)
     ap.add_argument("--rough-steps", type=int, default=100_000)
+    ap.add_argument("--spread-steps", type=int, default=20_000)
     ap.add_argument("--c5-steps", type=int, default=30_000)
     ap.add_argument("--c5-adj-steps", type=int, default=2_000)
     ap.add_argument("--c5-K", type=int, default=45)
@@ -569,6 +667,12 @@ def main():
         return
     if args.workload == "rough":
         print(json.dumps(rough_run(args)), flush=True)
+        return
+    if args.workload == "spreading":
+        out = spreading_run(args)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = spreading_cpu_baseline()
+        print(json.dumps(out), flush=True)
         return
     runs = synth.c2_sweep()[: args.runs]
     sims = []

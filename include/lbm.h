@@ -124,6 +124,11 @@ int lbm_cs_temperature(double a, double b, double R, double ratio, double *T);
 int lbm_piecewise_spinodals(double rho_v, double rho_l, double th_v, double th_m, double th_l,
                             double *rho1, double *rho2);
 
+/* Equation of state p_EOS(rho) of the parameter block (host only): the bulk pressure of Eq. (8)
+ * for the pseudopotential of Sec. II.B. LBM_E_INVAL for invalid parameters or rho outside the
+ * EOS domain. */
+int lbm_pressure(const lbm_params *p, double rho, double *out);
+
 /* ---- Single instance ---------------------------------------------------------------------- */
 
 /* Bytes of device workspace a context with these parameters needs. */
@@ -168,6 +173,16 @@ int lbm_observables_window(lbm_ctx *c, double x_lo, double x_hi, lbm_obs *out);
  * theta = acos((y_wall - yc)/r)): the apparent angle on pillars whose tops end at y_wall. The
  * default plane is y = 0.5 (bounce-back and masked geometries) or 1 (wet-node walls). */
 int lbm_observables_plane(lbm_ctx *c, double x_lo, double x_hi, double y_wall, lbm_obs *out);
+
+/* Dynamic wetting (Sec. III.B, Fig. 7): advance n steps (a multiple of `every`) and record the
+ * contact line on fluid row `row` at steps 0, every, 2 every, ..., n of this call, without any
+ * host synchronisation. Sample k is written to d_series[2k] (leftmost rho_mid crossing where rho
+ * rises, x linearly interpolated on the edge) and d_series[2k+1] (rightmost crossing where it
+ * falls); both NaN when the row holds no liquid. d_series: caller-owned device memory of
+ * count >= 2 (n/every + 1) doubles, written asynchronously on the context stream. The spreading
+ * radius is (d_series[2k+1] - d_series[2k]) / 2. LBM_E_SIZE if count is too small. */
+int lbm_record_contact_line(lbm_ctx *c, int64_t n, int32_t every, int32_t row, double *d_series,
+                            size_t count);
 
 /* Copy rho^n ([ny][nx], count >= nx*ny) or the pre-collision populations f^n ([9][ny][nx]) to
  * host memory. Synchronises the stream. Solid rows read 0. */

@@ -196,6 +196,28 @@ def interface_points(q: Params, rho: np.ndarray, rho_mid: float, y_min: float,
     return np.array(pts, dtype=np.float64).reshape(-1, 2)
 
 
+def contact_line(q: Params, rho: np.ndarray, row: int) -> tuple[float, float]:
+    """Contact line of a droplet on fluid row `row` (dynamic wetting, Sec. III.B): the leftmost
+    x where rho rises through rho_mid = (rho_l + rho_v)/2 and the rightmost where it falls, each
+    linearly interpolated on its lattice edge (x, x+1); edges across the periodic seam or touching
+    a solid node are skipped. (nan, nan) when the row holds no liquid segment."""
+    mid = 0.5 * (q.rho_l + q.rho_v)
+    fl = fluid_mask(q)
+    r = rho[row]
+    rising, falling = [], []
+    for x in range(q.nx - 1):
+        if not (fl[row, x] and fl[row, x + 1]):
+            continue
+        a, b = r[x], r[x + 1]
+        if (a >= mid) == (b >= mid):
+            continue
+        p = x + (mid - a) / (b - a)
+        (rising if b >= mid else falling).append(p)
+    if not rising or not falling or min(rising) >= max(falling):
+        return float("nan"), float("nan")
+    return float(min(rising)), float(max(falling))
+
+
 def kasa_fit(pts: np.ndarray) -> tuple[float, float, float]:
     """Kasa circle fit: least squares of x^2 + y^2 + D x + E y + F = 0 -> (xc, yc, r)."""
     A = np.column_stack([pts[:, 0], pts[:, 1], np.ones(len(pts))])

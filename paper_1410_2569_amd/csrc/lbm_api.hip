@@ -353,6 +353,22 @@ int lbm_piecewise_spinodals(double rho_v, double rho_l, double th_v, double th_m
     return LBM_E_INVAL;
 }
 
+// p_EOS(rho) on the host: Carnahan-Starling or Eq. (15). With psi = sqrt(2 (p - rho/3)/G) the
+// bulk pressure of Eq. (8), rho c_s^2 + G c^2 psi^2 / 2, equals it.
+int lbm_pressure(const lbm_params* p, double rho, double* out) {
+    if (!out || validate(p, nullptr) != LBM_OK || !std::isfinite(rho) || rho < 0.0) return LBM_E_INVAL;
+    if (p->eos == LBM_EOS_CS) {
+        const double e = p->b * rho / 4.0, om = 1.0 - e;
+        if (!(om > 0.0)) return LBM_E_INVAL;
+        *out = rho * p->R * p->T * (1.0 + e + e * e - e * e * e) / (om * om * om) - p->a * rho * rho;
+    } else {
+        const double p1 = p->rho1 * p->th_v, p2 = p1 + (p->rho2 - p->rho1) * p->th_m;
+        *out = rho <= p->rho1 ? rho * p->th_v
+             : (rho <= p->rho2 ? p1 + (rho - p->rho1) * p->th_m : p2 + (rho - p->rho2) * p->th_l);
+    }
+    return LBM_OK;
+}
+
 int lbm_workspace_size(const lbm_params* p, size_t* bytes) {
     if (!bytes) return LBM_E_INVAL;
     int rc = validate(p, nullptr);
@@ -611,6 +627,29 @@ int lbm_observables_plane(lbm_ctx* c, double x_lo, double x_hi, double y_wall, l
 int lbm_observables_window(lbm_ctx* c, double x_lo, double x_hi, lbm_obs* out) {
     if (!c) return LBM_E_INVAL;
     return lbm_observables_plane(c, x_lo, x_hi, wall_plane(c->p.walls), out);
+}
+
+int lbm_record_contact_line(lbm_ctx* c, int64_t n, int32_t every, int32_t row, double* d_series,
+                            size_t count) {
+    if (!c || !d_series || n < 0 || every < 1 || n % every) return LBM_E_INVAL;
+    if (row < c->kp.y_lo || row > c->kp.y_hi) return fail(c, LBM_E_INVAL, "row outside the fluid rows");
+    const size_t samples = (size_t)(n / every) + 1;
+    if (count < 2 * samples) return fail(c, LBM_E_SIZE, "series buffer too small");
+    (void)hipGetLastError();  // report only errors of this call
+    const double mid = 0.5 * (c->p.rho_l + c->p.rho_v);
+    for (size_t k = 0; k < samples; ++k) {
+        if (k) {
+            int after = c->cur;
+            hipError_t e = enqueue_steps(c, every, c->cur, c->stream, &after);
+            if (e != hipSuccess) return hip_fail(c, e, "record steps");
+            c->cur = after;
+            c->step += every;
+        }
+        hipError_t e = lbm::launch_contact_line(c->kp, c->g[c->cur], row, mid, d_series + 2 * k,
+                                                c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "contact line");
+    }
+    return LBM_OK;
 }
 
 int lbm_observables(lbm_ctx* c, lbm_obs* out) {

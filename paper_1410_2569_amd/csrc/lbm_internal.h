@@ -36,6 +36,8 @@ hipError_t launch_init(const KParams& P, const double* rho0, double* g, hipStrea
 hipError_t launch_pull(const KParams& P, const double* gin, double* fout, hipStream_t s);
 hipError_t launch_rho_psi(const KParams& P, const double* gin, double* psi, double* rho,
                           hipStream_t s);
+hipError_t launch_contact_line(const KParams& P, const double* gin, int row, double mid,
+                               double* out, hipStream_t s);
 int obs_blocks(const KParams& P);
 hipError_t launch_obs(const KParams& P, const double* gin, const double* rho, const double* psi,
                       const double* gw, const ObsArgs& A, double* part, double* out,

@@ -68,6 +68,7 @@ SIGNATURES = {
     "lbm_maxwell_cs": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double, _dp, _dp, _dp]),
     "lbm_cs_temperature": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double, _dp]),
     "lbm_piecewise_spinodals": (C.c_int, [C.c_double] * 5 + [_dp, _dp]),
+    "lbm_pressure": (C.c_int, [_P, C.c_double, _dp]),
     "lbm_workspace_size": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
     "lbm_create": (C.c_int, [_P, _dp, _dp, C.c_void_p, C.c_size_t, C.c_void_p,
                              C.POINTER(C.c_void_p)]),
@@ -76,6 +77,8 @@ SIGNATURES = {
     "lbm_observables_window": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.POINTER(Obs)]),
     "lbm_observables_plane": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double,
                                         C.POINTER(Obs)]),
+    "lbm_record_contact_line": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
+                                          C.c_void_p, C.c_size_t]),
     "lbm_create_masked": (C.c_int, [_P, C.c_void_p, _dp, _dp, C.c_void_p, C.c_size_t, C.c_void_p,
                                     C.POINTER(C.c_void_p)]),
     "lbm_read_rho": (C.c_int, [C.c_void_p, _dp, C.c_size_t]),
@@ -162,6 +165,14 @@ def piecewise_spinodals(rho_v: float, rho_l: float, th_v: float, th_m: float, th
     check(lib().lbm_piecewise_spinodals(rho_v, rho_l, th_v, th_m, th_l, C.byref(r1),
                                         C.byref(r2)))
     return r1.value, r2.value
+
+
+def pressure(q, rho: float) -> float:
+    """p_EOS(rho) of parameter block q (library's host EOS)."""
+    q = q if isinstance(q, Params) else make_params(q)
+    out = C.c_double()
+    check(lib().lbm_pressure(C.byref(q), float(rho), C.byref(out)))
+    return out.value
 
 
 def make_params(p: dict) -> Params:
@@ -266,6 +277,19 @@ class Sim:
             return o.as_dict()
         self._chk(rc)
         return o.as_dict()
+
+    def record_contact_line(self, n: int, every: int, row: int = 1, out=None):
+        """Advance n steps recording the contact line on `row` every `every` steps (device-side;
+        no host synchronisation). Returns a (n/every + 1, 2) float64 device tensor of
+        (left, right) crossings, filled asynchronously on the context stream."""
+        import torch
+        k = n // every + 1
+        if out is None:
+            out = torch.empty((k, 2), dtype=torch.float64, device=self.ws.device)
+        assert out.is_contiguous() and out.dtype == torch.float64
+        self._chk(lib().lbm_record_contact_line(self.h, int(n), int(every), int(row),
+                                                C.c_void_p(out.data_ptr()), out.numel()))
+        return out
 
     def rho(self) -> np.ndarray:
         out = np.empty((self.ny, self.nx))

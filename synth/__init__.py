@@ -289,6 +289,35 @@ def rough_setup(form: str, gw_printed: float, height: int = ROUGH["height"],
                 gw_printed=gw_printed)
 
 
+# Dynamic wetting (Sec. III.B, Figs. 6-7): the modified form at three printed G_w, a droplet of
+# R = 30 released half an interface width (2 nodes) above the wall plane.
+SPREAD_GW = (-0.3, -0.1, 0.2)  # printed; equilibrium angles 19.0, 69.4 and 126.3 degrees
+SPREAD_ANGLE = {-0.3: 19.0, -0.1: 69.4, 0.2: 126.3}
+SPREAD_EXPONENT = {-0.3: 0.51, -0.1: 0.485, 0.2: 0.425}  # printed fits r/R = C (t/tau)^n
+
+
+def spreading_setup(gw_printed: float, gap: float = 2.0, form: str = "modpsi") -> dict:
+    """A dynamic-wetting case in the paper's setup (wet-node walls, Eq. 15, 300 x 100 fluid
+    nodes): bottom G_w = PAPER_GW_SCALE[form] x printed, neutral top wall, droplet of R = 30
+    whose lowest point lies `gap` nodes above the wall plane y = 1."""
+    p = paper_params(wall_force=form)
+    gw = gw_uniform(p["nx"], PAPER_GW_SCALE[form] * gw_printed, 0.0)
+    rho0 = paper_droplet(p["nx"], p["ny"], height=PAPER["radius"] + gap)
+    return dict(params=p, gw=gw, rho0=rho0, gw_printed=gw_printed, form=form, row=1)
+
+
+def laplace_setup(radii=(18.0, 22.0, 26.0, 30.0, 34.0), n: int = 160) -> list[dict]:
+    """Free droplets in fully periodic n x n boxes under Eq. (15) (Laplace law, surface tension
+    for the inertial time scale of Sec. III.B)."""
+    out = []
+    for k, R in enumerate(radii):
+        p = paper_params(nx=n, ny=n, walls=0)
+        rho0 = droplet_rho(n, n, PAPER["rho_l"], PAPER["rho_v"], [(n / 2.0, n / 2.0)], [R],
+                           width=4.0, seed=40 + k, walls=False)
+        out.append(dict(params=p, gw=None, rho0=rho0, radius=R))
+    return out
+
+
 def c1_small() -> dict:
     """120x60, psi-based wall force G_w = -0.2 on both walls, droplet R = 20 on the bottom wall,
     10,000 steps."""

@@ -1,0 +1,88 @@
+"""Dynamic wetting on the GPU (Sec. III.B, Figs. 6-7).
+
+The device-side contact-line recorder against the oracle (element by element on the recorded
+time series, every schedule), then the physics of the spreading runs: surface tension from the
+Laplace law, the power law r/R = C (t/tau)^n over t/tau in [0.2, 1.5] with the printed exponents,
+and the final angles of the non-spreading cases.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+WINDOW = (0.2, 1.5)
+
+
+@pytest.mark.parametrize("schedule,every", [("two_step", 100), ("fused", 75), ("two_pass", 50)])
+def test_contact_line_series_parity(orc, gpu, schedule, every):
+    import torch
+    c = synth.spreading_setup(-0.1)
+    q = orc.make_params(c["params"])
+    pg = dict(c["params"], rho1=q.rho1, rho2=q.rho2)
+    sim = gpu.Sim(pg, c["gw"], c["rho0"])
+    sim.set_schedule(schedule)
+    n = 6 * every
+    ser = sim.record_contact_line(n, every, row=1)
+    torch.cuda.synchronize()
+    got = ser.cpu().numpy()
+    assert sim.current_step == n
+    f = orc.init_rest(q, c["rho0"])
+    for k in range(got.shape[0]):
+        if k:
+            orc.run(q, c["gw"], f, every)
+        ref = orc.contact_line(q, f.sum(0), 1)
+        if math.isnan(ref[0]):
+            assert np.isnan(got[k]).all(), (k, got[k])
+        else:
+            assert np.abs(got[k] - np.array(ref)).max() <= 1e-7, (k, got[k], ref)
+    assert np.isfinite(got[-1]).all()
+
+
+@pytest.fixture(scope="module")
+def gamma(gpu):
+    from paper_1410_2569_amd import analysis as A
+    cases = synth.laplace_setup()
+    b = gpu.Batch([c["params"] for c in cases], [np.zeros((2, c["params"]["nx"])) for c in cases],
+                  [c["rho0"] for c in cases])
+    b.step(30_000)
+    radii, dp = [], []
+    for i, c in enumerate(cases):
+        rho = b.f(i).sum(0)
+        n = rho.shape[0]
+        radii.append(math.sqrt(((rho - 1.0) / 499.0).sum() / math.pi))
+        dp.append(gpu.lbm.pressure(c["params"], rho[n // 2, n // 2])
+                  - gpu.lbm.pressure(c["params"], rho[0, 0]))
+    g, icpt = A.laplace_gamma(radii, dp)
+    resid = np.array(dp) - (g / np.array(radii) + icpt)
+    print("gamma", g, "intercept", icpt, "residuals", resid)
+    assert g > 0 and np.abs(resid).max() <= 0.01 * max(dp)
+    return g
+
+
+def test_spreading_power_law(gpu, gamma):
+    import torch
+    from paper_1410_2569_amd import analysis as A
+    tau = A.inertial_time(synth.PAPER["rho_l"], synth.PAPER["radius"], gamma)
+    ns = []
+    for gp in synth.SPREAD_GW:
+        c = synth.spreading_setup(gp)
+        sim = gpu.Sim(c["params"], c["gw"], c["rho0"])
+        ser = sim.record_contact_line(20_000, 10, row=1)
+        torch.cuda.synchronize()
+        a = ser.cpu().numpy()
+        r = 0.5 * (a[:, 1] - a[:, 0]) / synth.PAPER["radius"]
+        t = np.arange(len(r)) * 10 / tau
+        C, n, k = A.fit_power_law(t, r, *WINDOW)
+        o = sim.observables()
+        print(f"G_w {gp}: n {n:.4f} (printed {synth.SPREAD_EXPONENT[gp]}), C {C:.3f}, "
+              f"{k} samples, final theta {o['theta_deg']:.2f}")
+        assert k >= 100
+        assert abs(n - synth.SPREAD_EXPONENT[gp]) <= 0.05
+        ns.append(n)
+        if gp != -0.3:  # the strongly wetting case is still spreading after 20,000 steps
+            assert abs(o["theta_deg"] - synth.SPREAD_ANGLE[gp]) <= 2.0
+    assert ns[0] > ns[1] > ns[2], "the exponent falls as the equilibrium angle grows"
