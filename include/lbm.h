@@ -262,15 +262,33 @@ typedef struct lbm_batch lbm_batch;
 int lbm_batch_workspace_size(const lbm_params *p, int32_t count, const lbm_tune *tune,
                              size_t *bytes);
 /* p[count]: parameters; gw_host[count] ([2][nx] each) and rho0_host[count] ([ny][nx] each):
- * host arrays, copied; d_ws: caller-owned device workspace (256-byte aligned). */
+ * host arrays, copied; d_ws: caller-owned device workspace (256-byte aligned). Solid masks are
+ * rejected here (LBM_E_INVAL): use lbm_batch_create_masked. */
 int lbm_batch_create(const lbm_params *p, int32_t count, const double *const *gw_host,
                      const double *const *rho0_host, const lbm_tune *tune, void *d_ws,
                      size_t bytes, void *hip_stream, lbm_batch **out);
+/* An ensemble of solid-mask lattices (every p[i].walls = LBM_WALLS_MASK; see lbm_create_masked):
+ * solid_host[count] ([ny][nx] bytes each), gw_host[count] ([ny][nx] G_w per node each),
+ * rho0_host[count]; all copied. Schedules 0 and 1 only (LBM_E_INVAL for schedule 2). */
+int lbm_batch_create_masked(const lbm_params *p, int32_t count, const uint8_t *const *solid_host,
+                            const double *const *gw_host, const double *const *rho0_host,
+                            const lbm_tune *tune, void *d_ws, size_t bytes, void *hip_stream,
+                            lbm_batch **out);
 /* Advance every instance by n steps (asynchronous). */
 int lbm_batch_step(lbm_batch *b, int64_t n);
 /* Observables of every instance into out[count]; synchronises. LBM_E_HIP if a persistent run
  * was aborted by the grid-barrier time-out (workgroups not co-resident). */
 int lbm_batch_observables(lbm_batch *b, lbm_obs *out);
+/* Same with the contact plane of every instance given (y_wall[count]; see
+ * lbm_observables_plane), or the default planes when y_wall is NULL. */
+int lbm_batch_observables_plane(lbm_batch *b, const double *y_wall, lbm_obs *out);
+/* Dynamic wetting for an ensemble (see lbm_record_contact_line): advance every instance n steps
+ * (a multiple of every) and record the contact line of instance i on its fluid row rows[i] at
+ * steps 0, every, ..., n of the call: sample k of instance i in d_series[2 (k count + i)] and
+ * d_series[2 (k count + i) + 1]. d_series: device memory of >= 2 count (n/every + 1) doubles,
+ * filled asynchronously on the ensemble's stream. */
+int lbm_batch_record_contact_line(lbm_batch *b, int64_t n, int32_t every, const int32_t *rows,
+                                  double *d_series, size_t count);
 /* Pre-collision populations f^n of instance `index` ([9][ny][nx] host array). */
 int lbm_batch_read_f(lbm_batch *b, int32_t index, double *host, size_t count);
 /* State of instance `index` as a checkpoint blob (the format of lbm_save_state, loadable into

@@ -131,6 +131,7 @@ KParams kparams_of(const lbm_params* p, const Layout& L) {
     k.p1 = p->rho1 * p->th_v;
     k.p2 = k.p1 + (p->rho2 - p->rho1) * p->th_m;
     k.two_over_G = 2.0 / p->G;
+    k.rho_mid = 0.5 * (p->rho_l + p->rho_v);
     k.negG = -p->G;
     const double tau_e = 1.0 / p->s_e, tau_z = 1.0 / p->s_zeta;
     k.c_sig_e = 12.0 * p->sigma * p->G * p->G / (tau_e - 0.5);
@@ -893,7 +894,9 @@ struct lbm_batch {
     int64_t step;
     lbm_tune tune;
     int grid;  // persistent grid size
-    bool wet;  // some instance uses the wet-node wall
+    int geo;   // lbm::GEO_ROWS, GEO_WET (some instance wet-node) or GEO_MASK (all masked)
+    std::vector<int32_t> rows;  // contact-line rows of the last record call (host copy)
+    int* d_rows;
     hipGraphExec_t graph[2];  // per-step schedule: kGraphChunk launches starting at parity 0 / 1
     hipGraphExec_t pgraph;    // persistent schedule: reset + persistent kernel for pgraph_n steps
     int64_t pgraph_n;
@@ -907,7 +910,7 @@ constexpr int kGraphChunk = 64;
 constexpr int kSpinLimit = 1 << 22;
 
 struct BatchLayout {
-    size_t off_desc, off_tiles, off_bar, total;
+    size_t off_desc, off_tiles, off_bar, off_rows, total;
     std::vector<size_t> off_inst;  // per instance: g0, g1, gw, psi, part, fin
     std::vector<Layout> L;
     int ntiles;
@@ -923,7 +926,7 @@ bool batch_layout(const lbm_params* p, int32_t count, int tile, BatchLayout* B) 
     long long nt = 0;
     B->tile0.resize(count); B->ntx.resize(count); B->nty.resize(count); B->L.resize(count);
     for (int i = 0; i < count; ++i) {
-        const int ylo = p[i].walls ? 1 : 0, yhi = p[i].walls ? p[i].ny - 2 : p[i].ny - 1;
+        const int ylo = y_lo_of(&p[i]), yhi = y_hi_of(&p[i]);
         B->ntx[i] = (p[i].nx + TX - 1) / TX;
         B->nty[i] = (yhi - ylo + TY) / TY;
         B->tile0[i] = (int)nt;
@@ -936,6 +939,8 @@ bool batch_layout(const lbm_params* p, int32_t count, int tile, BatchLayout* B) 
     o += align_up((size_t)nt * sizeof(int), kAlign);
     B->off_bar = o;
     o += kAlign;
+    B->off_rows = o;
+    o += align_up((size_t)count * sizeof(int), kAlign);
     B->off_inst.resize(count);
     for (int i = 0; i < count; ++i) {
         B->off_inst[i] = o;
@@ -968,7 +973,7 @@ int lbm_batch_workspace_size(const lbm_params* p, int32_t count, const lbm_tune*
     for (int i = 0; i < count; ++i) {
         int rc = validate(&p[i], nullptr);
         if (rc) return rc;
-        if (is_mask(&p[i])) return LBM_E_INVAL;
+        if (is_mask(&p[i]) != is_mask(&p[0])) return LBM_E_INVAL;  // all masked or none
     }
     BatchLayout B;
     if (!batch_layout(p, count, tune ? tune->tile : 0, &B)) return LBM_E_INVAL;
@@ -976,9 +981,10 @@ int lbm_batch_workspace_size(const lbm_params* p, int32_t count, const lbm_tune*
     return LBM_OK;
 }
 
-int lbm_batch_create(const lbm_params* p, int32_t count, const double* const* gw_host,
-                     const double* const* rho0_host, const lbm_tune* tune, void* d_ws,
-                     size_t bytes, void* stream, lbm_batch** out) {
+static int batch_create_impl(const lbm_params* p, int32_t count,
+                             const uint8_t* const* solid_host, const double* const* gw_host,
+                             const double* const* rho0_host, const lbm_tune* tune, void* d_ws,
+                             size_t bytes, void* stream, lbm_batch** out) {
     if (!out) return LBM_E_INVAL;
     *out = nullptr;
     if (!p || count < 1 || !rho0_host || !gw_host || !d_ws) return LBM_E_INVAL;
@@ -986,10 +992,13 @@ int lbm_batch_create(const lbm_params* p, int32_t count, const double* const* gw
     for (int i = 0; i < count; ++i) {
         int rc = validate(&p[i], nullptr);
         if (rc) return rc;
-        if (is_mask(&p[i])) return LBM_E_INVAL;  // ensembles: flat walls or periodic lattices
+        // masked ensembles come with a mask for every instance, others with none
+        if (is_mask(&p[i]) != (solid_host != nullptr)) return LBM_E_INVAL;
+        if (solid_host && !solid_host[i]) return LBM_E_INVAL;
         if (!rho0_host[i] || (p[i].walls && !gw_host[i])) return LBM_E_INVAL;
     }
     lbm_tune tn = tune ? *tune : lbm_tune{1, 0, 0, 0};
+    if (solid_host && tn.schedule == 2) return LBM_E_INVAL;  // two steps per launch: flat walls
     BatchLayout B;
     if (!batch_layout(p, count, tn.tile, &B)) return LBM_E_INVAL;
     if (bytes < B.total) return LBM_E_SIZE;
@@ -1007,8 +1016,10 @@ int lbm_batch_create(const lbm_params* p, int32_t count, const double* const* gw
     b->d_bar = (unsigned*)(b->ws + B.off_bar);
     b->d_flag = (int*)(b->ws + B.off_bar + 64);
     b->ntiles = B.ntiles;
-    b->wet = false;
-    for (int i = 0; i < count; ++i) b->wet = b->wet || p[i].walls == LBM_WALLS_WET_NODE;
+    b->geo = solid_host ? lbm::GEO_MASK : lbm::GEO_ROWS;
+    for (int i = 0; i < count; ++i)
+        if (p[i].walls == LBM_WALLS_WET_NODE) b->geo = lbm::GEO_WET;
+    b->d_rows = (int*)(b->ws + B.off_rows);
     b->cur = 0;
     b->step = 0;
     b->tune = tn;
@@ -1020,6 +1031,7 @@ int lbm_batch_create(const lbm_params* p, int32_t count, const double* const* gw
     hipError_t e = hipMemsetAsync(b->ws, 0, B.total, s);
     if (e != hipSuccess) { delete b; return LBM_E_HIP; }
     std::vector<int> tile_inst(B.ntiles);
+    std::vector<std::vector<unsigned short>> links(count);  // host staging until the final sync
     for (int i = 0; i < count; ++i) {
         const Layout& L = B.L[i];
         char* base = b->ws + B.off_inst[i];
@@ -1038,16 +1050,32 @@ int lbm_batch_create(const lbm_params* p, int32_t count, const double* const* gw
         b->part.push_back((double*)(base + L.off_part));
         b->fin.push_back((double*)(base + L.off_fin));
         for (int t = 0; t < B.ntx[i] * B.nty[i]; ++t) tile_inst[B.tile0[i] + t] = i;
+        const uint8_t* solid = solid_host ? solid_host[i] : nullptr;
         for (long long k = 0; k < (long long)p[i].nx * p[i].ny; ++k) {
             const int y = (int)(k / p[i].nx);
-            if (p[i].walls && (y == 0 || y == p[i].ny - 1)) continue;
+            if (solid ? solid[k] != 0 : (y < y_lo_of(&p[i]) || y > y_hi_of(&p[i]))) continue;
             if (!finite_pos(rho0_host[i][k])) { delete b; return LBM_E_INVAL; }
         }
+        const int gw_rows = solid ? p[i].ny : 2;
         if (gw_host[i]) {
+            for (long long k = 0; k < (long long)gw_rows * p[i].nx; ++k)
+                if (!std::isfinite(gw_host[i][k])) { delete b; return LBM_E_INVAL; }
             e = hipMemcpy2DAsync(d.gw, L.pitch * sizeof(double), gw_host[i],
-                                 p[i].nx * sizeof(double), p[i].nx * sizeof(double), 2,
+                                 p[i].nx * sizeof(double), p[i].nx * sizeof(double), gw_rows,
                                  hipMemcpyHostToDevice, s);
             if (e != hipSuccess) { delete b; return LBM_E_HIP; }
+        }
+        if (solid) {
+            links[i] = mask_links(&p[i], solid, L.pitch);
+            unsigned short* dl = (unsigned short*)(base + L.off_links);
+            e = hipMemcpyAsync(dl, links[i].data(), links[i].size() * sizeof(unsigned short),
+                               hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) { delete b; return LBM_E_HIP; }
+            kp.links = dl;
+            kp.gwn = d.gw;
+            d.P = kp;
+            b->kp.back() = kp;
+            b->desc.back() = d;
         }
         e = hipMemcpy2DAsync(d.g[1], L.pitch * sizeof(double), rho0_host[i],
                              p[i].nx * sizeof(double), p[i].nx * sizeof(double), p[i].ny,
@@ -1073,10 +1101,33 @@ int lbm_batch_create(const lbm_params* p, int32_t count, const double* const* gw
     return LBM_OK;
 }
 
+int lbm_batch_create(const lbm_params* p, int32_t count, const double* const* gw_host,
+                     const double* const* rho0_host, const lbm_tune* tune, void* d_ws,
+                     size_t bytes, void* stream, lbm_batch** out) {
+    if (p && count > 0 && is_mask(&p[0])) {
+        if (out) *out = nullptr;
+        return LBM_E_INVAL;  // masked ensembles: lbm_batch_create_masked
+    }
+    return batch_create_impl(p, count, nullptr, gw_host, rho0_host, tune, d_ws, bytes, stream,
+                             out);
+}
+
+int lbm_batch_create_masked(const lbm_params* p, int32_t count, const uint8_t* const* solid_host,
+                            const double* const* gw_host, const double* const* rho0_host,
+                            const lbm_tune* tune, void* d_ws, size_t bytes, void* stream,
+                            lbm_batch** out) {
+    if (!solid_host) {
+        if (out) *out = nullptr;
+        return LBM_E_INVAL;
+    }
+    return batch_create_impl(p, count, solid_host, gw_host, rho0_host, tune, d_ws, bytes, stream,
+                             out);
+}
+
 static int batch_direct(lbm_batch* b, int64_t n) {
     if (b->tune.schedule == 2) {
         for (; n >= 2; n -= 2) {
-            hipError_t e = lbm::launch_batch_step2(b->tune.tile, b->wet, b->d_inst,
+            hipError_t e = lbm::launch_batch_step2(b->tune.tile, b->geo, b->d_inst,
                                                    b->d_tile_inst, b->ntiles, b->cur, b->stream);
             if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, std::string("batch step: ") + hipGetErrorString(e));
             b->cur ^= 1;
@@ -1084,7 +1135,7 @@ static int batch_direct(lbm_batch* b, int64_t n) {
         }
     }
     for (int64_t i = 0; i < n; ++i) {
-        hipError_t e = lbm::launch_batch_step(b->tune.tile, b->wet, b->d_inst, b->d_tile_inst,
+        hipError_t e = lbm::launch_batch_step(b->tune.tile, b->geo, b->d_inst, b->d_tile_inst,
                                               b->ntiles, b->cur, b->stream);
         if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, std::string("batch step: ") + hipGetErrorString(e));
         b->cur ^= 1;
@@ -1128,7 +1179,7 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
         if (n > (int64_t)1 << 30) return batch_fail(b, LBM_E_INVAL, "too many steps in one call");
         const int cur = b->cur;
         auto persistent = [&]() {
-            return lbm::launch_batch_persistent(b->tune.tile, b->wet, b->grid, b->d_inst,
+            return lbm::launch_batch_persistent(b->tune.tile, b->geo, b->grid, b->d_inst,
                                                 b->d_tile_inst, b->ntiles, (int)n, cur, b->d_bar,
                                                 b->d_flag, kSpinLimit, b->stream);
         };
@@ -1153,10 +1204,10 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
             int rc = capture(b, &b->graph[cur], [&]() {
                 const bool two = b->tune.schedule == 2;  // two steps per launch
                 for (int i = 0; i < (two ? kGraphChunk / 2 : kGraphChunk); ++i) {
-                    hipError_t e = two ? lbm::launch_batch_step2(b->tune.tile, b->wet, b->d_inst,
+                    hipError_t e = two ? lbm::launch_batch_step2(b->tune.tile, b->geo, b->d_inst,
                                                                  b->d_tile_inst, b->ntiles,
                                                                  (cur + i) & 1, b->stream)
-                                       : lbm::launch_batch_step(b->tune.tile, b->wet, b->d_inst,
+                                       : lbm::launch_batch_step(b->tune.tile, b->geo, b->d_inst,
                                                                 b->d_tile_inst, b->ntiles,
                                                                 (cur + i) & 1, b->stream);
                     if (e != hipSuccess) return e;
@@ -1181,8 +1232,11 @@ static int batch_check_abort(lbm_batch* b) {
     return LBM_OK;
 }
 
-int lbm_batch_observables(lbm_batch* b, lbm_obs* out) {
+int lbm_batch_observables_plane(lbm_batch* b, const double* y_wall, lbm_obs* out) {
     if (!b || !out) return LBM_E_INVAL;
+    if (y_wall)
+        for (int i = 0; i < b->count; ++i)
+            if (!std::isfinite(y_wall[i])) return LBM_E_INVAL;
     int rc = batch_check_abort(b);
     if (rc) return rc;
     std::vector<double> q((size_t)b->count * 32);
@@ -1191,12 +1245,13 @@ int lbm_batch_observables(lbm_batch* b, lbm_obs* out) {
         const KParams& P = b->kp[i];
         const lbm::InstDesc& d = b->desc[i];
         lbm::ObsArgs& A = args[i];
+        const double yw = y_wall ? y_wall[i] : wall_plane(b->p[i].walls);
         A.rho_mid = 0.5 * (b->p[i].rho_l + b->p[i].rho_v);
-        A.y_min = wall_plane(b->p[i].walls) + 3.0;
+        A.y_min = yw + 3.0;
         A.x_lo = -INFINITY;
         A.x_hi = INFINITY;
         A.cx = 0.5 * P.nx;
-        A.cy = wall_plane(b->p[i].walls);
+        A.cy = yw;
         double* rho = d.g[b->cur ^ 1];
         hipError_t e = lbm::launch_rho_psi(P, d.g[b->cur], b->psi[i], rho, b->stream);
         if (e == hipSuccess)
@@ -1215,6 +1270,38 @@ int lbm_batch_observables(lbm_batch* b, lbm_obs* out) {
         bad |= out[i].nonfinite != 0;
     }
     return bad ? LBM_E_NONFINITE : LBM_OK;
+}
+
+int lbm_batch_observables(lbm_batch* b, lbm_obs* out) {
+    return lbm_batch_observables_plane(b, nullptr, out);
+}
+
+int lbm_batch_record_contact_line(lbm_batch* b, int64_t n, int32_t every, const int32_t* rows,
+                                  double* d_series, size_t count) {
+    if (!b || !rows || !d_series || n < 0 || every < 1 || n % every) return LBM_E_INVAL;
+    for (int i = 0; i < b->count; ++i)
+        if (rows[i] < b->kp[i].y_lo || rows[i] > b->kp[i].y_hi)
+            return batch_fail(b, LBM_E_INVAL, "row outside the fluid rows");
+    const size_t samples = (size_t)(n / every) + 1;
+    if (count < 2 * samples * (size_t)b->count) return batch_fail(b, LBM_E_SIZE, "series buffer too small");
+    int rc = batch_check_abort(b);
+    if (rc) return rc;
+    (void)hipGetLastError();
+    b->rows.assign(rows, rows + b->count);  // kept alive for the asynchronous copy
+    hipError_t e = hipMemcpyAsync(b->d_rows, b->rows.data(), b->count * sizeof(int),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "record rows");
+    for (size_t k = 0; k < samples; ++k) {
+        if (k) {
+            rc = lbm_batch_step(b, every);
+            if (rc) return rc;
+        }
+        e = lbm::launch_batch_contact_line(b->d_inst, b->d_rows, b->count, b->cur,
+                                           d_series + 2 * (size_t)b->count * k, b->stream);
+        if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "batch contact line");
+    }
+    return LBM_OK;
 }
 
 int lbm_batch_read_f(lbm_batch* b, int32_t index, double* host, size_t count) {

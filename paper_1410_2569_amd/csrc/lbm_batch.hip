@@ -8,6 +8,8 @@
 //              between steps. The barrier publishes the step's stores at agent scope (release),
 //              waits for every workgroup, then acquires; its wait is bounded and raises an abort
 //              flag on timeout so every workgroup always exits.
+#include <algorithm>
+
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
@@ -20,7 +22,8 @@ __device__ __forceinline__ void batch_tile_origin(const InstDesc* D, int t, int 
     y0 = D->P.y_lo + (lt / D->ntx) * TY;
 }
 
-// GEO: GEO_WET when some instance uses the wet-node wall, else GEO_ROWS (chosen at launch).
+// GEO: GEO_MASK for an ensemble of solid masks, GEO_WET when some instance uses the wet-node
+// wall, else GEO_ROWS (chosen at launch).
 template <int TX, int TY, int GEO>
 __global__ __launch_bounds__(TX* TY) void k_batch_step(const InstDesc* __restrict__ inst,
                                                        const int* __restrict__ tile_inst,
@@ -101,6 +104,14 @@ __global__ __launch_bounds__(TX* TY) void k_batch_persistent(const InstDesc* __r
     }
 }
 
+// Contact lines of every instance (one block per instance): out[2i], out[2i+1] on rows[i].
+__global__ __launch_bounds__(256) void k_batch_contact_line(const InstDesc* __restrict__ inst,
+                                                            const int* __restrict__ rows, int cur,
+                                                            double* __restrict__ out) {
+    const InstDesc* D = inst + blockIdx.x;
+    contact_line_block(D->P, D->g[cur], rows[blockIdx.x], D->P.rho_mid, out + 2 * blockIdx.x);
+}
+
 // Clears the barrier counter and abort flag (a kernel rather than a memset node, so the pair can
 // sit in a hipGraph).
 __global__ void k_batch_reset(unsigned* bar, int* flag) {
@@ -112,9 +123,12 @@ __global__ void k_batch_reset(unsigned* bar, int* flag) {
 
 // ------------------------------------------------------------------------------------------------
 template <int TX, int TY>
-static hipError_t launch_batch_t(bool wet, const InstDesc* inst, const int* tile_inst, int ntiles,
+static hipError_t launch_batch_t(int geo, const InstDesc* inst, const int* tile_inst, int ntiles,
                                  int cur, hipStream_t s) {
-    if (wet)
+    if (geo == GEO_MASK)
+        hipLaunchKernelGGL((k_batch_step<TX, TY, GEO_MASK>), dim3(ntiles), dim3(TX * TY), 0, s,
+                           inst, tile_inst, ntiles, cur);
+    else if (geo == GEO_WET)
         hipLaunchKernelGGL((k_batch_step<TX, TY, GEO_WET>), dim3(ntiles), dim3(TX * TY), 0, s, inst,
                            tile_inst, ntiles, cur);
     else
@@ -124,13 +138,16 @@ static hipError_t launch_batch_t(bool wet, const InstDesc* inst, const int* tile
 }
 
 template <int TX, int TY>
-static hipError_t launch_persist_t(bool wet, int grid, const InstDesc* inst, const int* tile_inst,
+static hipError_t launch_persist_t(int geo, int grid, const InstDesc* inst, const int* tile_inst,
                                    int ntiles, int nsteps, int cur, unsigned* bar, int* flag,
                                    int spin_limit, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, bar, flag);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (wet)
+    if (geo == GEO_MASK)
+        hipLaunchKernelGGL((k_batch_persistent<TX, TY, GEO_MASK>), dim3(grid), dim3(TX * TY), 0, s,
+                           inst, tile_inst, ntiles, nsteps, cur, bar, flag, spin_limit);
+    else if (geo == GEO_WET)
         hipLaunchKernelGGL((k_batch_persistent<TX, TY, GEO_WET>), dim3(grid), dim3(TX * TY), 0, s,
                            inst, tile_inst, ntiles, nsteps, cur, bar, flag, spin_limit);
     else
@@ -139,17 +156,19 @@ static hipError_t launch_persist_t(bool wet, int grid, const InstDesc* inst, con
     return hipGetLastError();
 }
 
-// Resident workgroups per CU of the persistent kernel (the smaller of its two variants, so a
-// grid sized by it fits whichever is launched).
+// Resident workgroups per CU of the persistent kernel (the smallest of its variants, so a grid
+// sized by it fits whichever is launched).
 template <int TX, int TY>
 static int occupancy_t() {
-    int a = 0, b = 0;
+    int a = 0, b = 0, c = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_batch_persistent<TX, TY, GEO_ROWS>,
                                                      TX * TY, 0) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_batch_persistent<TX, TY, GEO_WET>,
+                                                     TX * TY, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_batch_persistent<TX, TY, GEO_MASK>,
                                                      TX * TY, 0) != hipSuccess)
         return 0;
-    return a < b ? a : b;
+    return std::min(a, std::min(b, c));
 }
 
 int batch_tiles(int tile) { return tile >= 0 && tile < 4; }
@@ -157,9 +176,10 @@ int batch_tiles(int tile) { return tile >= 0 && tile < 4; }
 // Two steps per launch (schedule 2): tile 0 -> 64x8 output tiles, tile 3 -> 64x16; the work-list
 // must have been built for that tile shape.
 template <int TX, int TY>
-static hipError_t launch_batch2_t(bool wet, const InstDesc* inst, const int* tile_inst, int ntiles,
+static hipError_t launch_batch2_t(int geo, const InstDesc* inst, const int* tile_inst, int ntiles,
                                   int cur, hipStream_t s) {
-    if (wet)
+    if (geo == GEO_MASK) return hipErrorInvalidValue;  // two steps per launch: flat walls only
+    if (geo == GEO_WET)
         hipLaunchKernelGGL((k_batch_step2<TX, TY, GEO_WET>), dim3(ntiles), dim3(TX * TY), 0, s, inst,
                            tile_inst, ntiles, cur);
     else
@@ -168,35 +188,41 @@ static hipError_t launch_batch2_t(bool wet, const InstDesc* inst, const int* til
     return hipGetLastError();
 }
 
-hipError_t launch_batch_step2(int tile, bool wet, const InstDesc* inst, const int* tile_inst,
+hipError_t launch_batch_step2(int tile, int geo, const InstDesc* inst, const int* tile_inst,
                               int ntiles, int cur, hipStream_t s) {
-    if (tile == 2) return launch_batch2_t<64, 16>(wet, inst, tile_inst, ntiles, cur, s);
-    return launch_batch2_t<64, 8>(wet, inst, tile_inst, ntiles, cur, s);
+    if (tile == 2) return launch_batch2_t<64, 16>(geo, inst, tile_inst, ntiles, cur, s);
+    return launch_batch2_t<64, 8>(geo, inst, tile_inst, ntiles, cur, s);
 }
 
-hipError_t launch_batch_step(int tile, bool wet, const InstDesc* inst, const int* tile_inst,
+hipError_t launch_batch_step(int tile, int geo, const InstDesc* inst, const int* tile_inst,
                              int ntiles, int cur, hipStream_t s) {
     switch (tile) {
-        case 1: return launch_batch_t<64, 8>(wet, inst, tile_inst, ntiles, cur, s);
-        case 2: return launch_batch_t<64, 16>(wet, inst, tile_inst, ntiles, cur, s);
-        case 3: return launch_batch_t<128, 4>(wet, inst, tile_inst, ntiles, cur, s);
-        default: return launch_batch_t<64, 4>(wet, inst, tile_inst, ntiles, cur, s);
+        case 1: return launch_batch_t<64, 8>(geo, inst, tile_inst, ntiles, cur, s);
+        case 2: return launch_batch_t<64, 16>(geo, inst, tile_inst, ntiles, cur, s);
+        case 3: return launch_batch_t<128, 4>(geo, inst, tile_inst, ntiles, cur, s);
+        default: return launch_batch_t<64, 4>(geo, inst, tile_inst, ntiles, cur, s);
     }
 }
 
-hipError_t launch_batch_persistent(int tile, bool wet, int grid, const InstDesc* inst,
+hipError_t launch_batch_persistent(int tile, int geo, int grid, const InstDesc* inst,
                                    const int* tile_inst, int ntiles, int nsteps, int cur,
                                    unsigned* bar, int* flag, int spin_limit, hipStream_t s) {
     switch (tile) {
-        case 1: return launch_persist_t<64, 8>(wet, grid, inst, tile_inst, ntiles, nsteps, cur,
+        case 1: return launch_persist_t<64, 8>(geo, grid, inst, tile_inst, ntiles, nsteps, cur,
                                                bar, flag, spin_limit, s);
-        case 2: return launch_persist_t<64, 16>(wet, grid, inst, tile_inst, ntiles, nsteps, cur,
+        case 2: return launch_persist_t<64, 16>(geo, grid, inst, tile_inst, ntiles, nsteps, cur,
                                                 bar, flag, spin_limit, s);
-        case 3: return launch_persist_t<128, 4>(wet, grid, inst, tile_inst, ntiles, nsteps, cur,
+        case 3: return launch_persist_t<128, 4>(geo, grid, inst, tile_inst, ntiles, nsteps, cur,
                                                 bar, flag, spin_limit, s);
-        default: return launch_persist_t<64, 4>(wet, grid, inst, tile_inst, ntiles, nsteps, cur,
+        default: return launch_persist_t<64, 4>(geo, grid, inst, tile_inst, ntiles, nsteps, cur,
                                                 bar, flag, spin_limit, s);
     }
+}
+
+hipError_t launch_batch_contact_line(const InstDesc* inst, const int* rows, int count, int cur,
+                                     double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_contact_line, dim3(count), dim3(256), 0, s, inst, rows, cur, out);
+    return hipGetLastError();
 }
 
 int batch_persistent_occupancy(int tile) {

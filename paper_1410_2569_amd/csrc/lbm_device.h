@@ -37,6 +37,7 @@ struct KParams {
     double s_e, s_z, s_j, s_q;            // relaxation rates (s_rho drops out: rho is conserved)
     double h_e, h_z, h_j, h_q;            // 1 - s/2
     double s_nu_c, nu_v, dnu, rho_v, inv_drho;  // shear rate: constant, or interpolated
+    double rho_mid;               // (rho_l + rho_v) / 2, the interface level of the observables
     const unsigned short* links;  // walls = 3: [ny][pitch] solid and bounce-back bits
     const double* gwn;            // walls = 3: [ny][pitch] G_w of solid nodes
 };
@@ -628,6 +629,48 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
     }
 }
 
+
+}  // namespace lbm
+
+namespace lbm {
+
+// Contact line on row `row` (dynamic wetting, Sec. III.B): the rho_mid crossings of the row,
+// linearly interpolated on the edges (x, x+1) that do not cross the periodic seam. out[0] = the
+// leftmost crossing where rho rises through rho_mid, out[1] = the rightmost where it falls; both
+// NaN when the row holds no liquid segment. Called by a whole block of 256 threads; min and max
+// do not depend on the reduction order.
+__device__ __forceinline__ void contact_line_block(const KParams& P, const double* __restrict__ gin,
+                                                  int row, double mid, double* __restrict__ out) {
+    __shared__ double lo[256], hi[256];
+    double l = __builtin_huge_val(), h = -__builtin_huge_val();
+    for (int x = threadIdx.x; x + 1 < P.nx; x += 256) {
+        if (is_solid_node(P, x, row) || is_solid_node(P, x + 1, row)) continue;
+        double f[9];
+        pull9_any(P, gin, x, row, f);
+        const double ra = sum9(f);
+        pull9_any(P, gin, x + 1, row, f);
+        const double rb = sum9(f);
+        if ((ra >= mid) == (rb >= mid)) continue;
+        const double px = x + (mid - ra) / (rb - ra);
+        if (rb >= mid) l = fmin(l, px);
+        else h = fmax(h, px);
+    }
+    lo[threadIdx.x] = l;
+    hi[threadIdx.x] = h;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            lo[threadIdx.x] = fmin(lo[threadIdx.x], lo[threadIdx.x + w]);
+            hi[threadIdx.x] = fmax(hi[threadIdx.x], hi[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const bool ok = lo[0] < hi[0];
+        out[0] = ok ? lo[0] : __builtin_nan("");
+        out[1] = ok ? hi[0] : __builtin_nan("");
+    }
+}
 
 }  // namespace lbm
 

@@ -56,14 +56,18 @@ hipError_t launch_loss_seed(const KParams& P, double w_c, double w_w, double yc,
 
 // batch
 int batch_tiles(int tile);
-// wet: some instance uses the wet-node wall (selects the kernels compiled with that rule)
-hipError_t launch_batch_step(int tile, bool wet, const InstDesc* inst, const int* tile_inst,
+// geo: GEO_ROWS, GEO_WET (some instance uses the wet-node wall) or GEO_MASK (every instance has
+// a solid mask); selects the kernels compiled for that geometry. Two steps per launch do not take
+// GEO_MASK (hipErrorInvalidValue).
+hipError_t launch_batch_step(int tile, int geo, const InstDesc* inst, const int* tile_inst,
                              int ntiles, int cur, hipStream_t s);
-hipError_t launch_batch_step2(int tile, bool wet, const InstDesc* inst, const int* tile_inst,
+hipError_t launch_batch_step2(int tile, int geo, const InstDesc* inst, const int* tile_inst,
                               int ntiles, int cur, hipStream_t s);
-hipError_t launch_batch_persistent(int tile, bool wet, int grid, const InstDesc* inst,
+hipError_t launch_batch_persistent(int tile, int geo, int grid, const InstDesc* inst,
                                    const int* tile_inst, int ntiles, int nsteps, int cur,
                                    unsigned* bar, int* flag, int spin_limit, hipStream_t s);
+hipError_t launch_batch_contact_line(const InstDesc* inst, const int* rows, int count, int cur,
+                                     double* out, hipStream_t s);
 int batch_persistent_occupancy(int tile);
 
 }  // namespace lbm

@@ -79,6 +79,12 @@ SIGNATURES = {
                                         C.POINTER(Obs)]),
     "lbm_record_contact_line": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
                                           C.c_void_p, C.c_size_t]),
+    "lbm_batch_create_masked": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(_dp),
+                                          C.POINTER(_dp), C.c_void_p, C.c_void_p, C.c_size_t,
+                                          C.c_void_p, C.POINTER(C.c_void_p)]),
+    "lbm_batch_observables_plane": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
+    "lbm_batch_record_contact_line": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32,
+                                                C.POINTER(C.c_int32), C.c_void_p, C.c_size_t]),
     "lbm_create_masked": (C.c_int, [_P, C.c_void_p, _dp, _dp, C.c_void_p, C.c_size_t, C.c_void_p,
                                     C.POINTER(C.c_void_p)]),
     "lbm_read_rho": (C.c_int, [C.c_void_p, _dp, C.c_size_t]),
@@ -343,22 +349,32 @@ class Sim:
 
 
 class Batch:
-    """An ensemble of uneven lattices advanced together by the batch kernels."""
+    """An ensemble of uneven lattices advanced together by the batch kernels. An ensemble of solid
+    masks (walls = 3 for every instance) takes the masks as `solids` (or params["solid"]) and G_w
+    per node."""
 
-    def __init__(self, params_list, gw_list, rho0_list, tune=None, device="cuda", stream=None):
+    def __init__(self, params_list, gw_list, rho0_list, tune=None, device="cuda", stream=None,
+                 solids=None):
         import torch
 
         self.n = len(params_list)
+        if solids is None and all(isinstance(pr, dict) and "solid" in pr for pr in params_list):
+            solids = [pr["solid"] for pr in params_list]
         arr = (Params * self.n)()
         for i, pr in enumerate(params_list):
             arr[i] = pr if isinstance(pr, Params) else make_params(pr)
         self.params = arr
-        self._gw = [np.ascontiguousarray(g if g is not None else np.zeros((2, arr[i].nx)),
+        self.masked = solids is not None
+        shape = (lambda q: (q.ny, q.nx)) if self.masked else (lambda q: (2, q.nx))
+        self._gw = [np.ascontiguousarray(g if g is not None else np.zeros(shape(arr[i])),
                                          dtype=np.float64) for i, g in enumerate(gw_list)]
         self._rho = [np.ascontiguousarray(r, dtype=np.float64) for r in rho0_list]
         for i in range(self.n):
-            assert self._gw[i].shape == (2, arr[i].nx)
+            assert self._gw[i].shape == shape(arr[i])
             assert self._rho[i].shape == (arr[i].ny, arr[i].nx)
+        if self.masked:
+            self._solid = [np.ascontiguousarray(np.asarray(m) != 0, dtype=np.uint8) for m in solids]
+            sp = (C.c_void_p * self.n)(*[m.ctypes.data for m in self._solid])
         gwp = (_dp * self.n)(*[_dptr(g) for g in self._gw])
         rp = (_dp * self.n)(*[_dptr(r) for r in self._rho])
         t = None
@@ -375,8 +391,13 @@ class Batch:
         self.stream = stream if stream is not None else torch.cuda.Stream(self.ws.device)
         torch.cuda.current_stream(self.ws.device).synchronize()
         h = C.c_void_p()
-        rc = lib().lbm_batch_create(arr, self.n, gwp, rp, tp, C.c_void_p(self.ws.data_ptr()),
-                                    nbytes.value, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        ws, st = C.c_void_p(self.ws.data_ptr()), C.c_void_p(self.stream.cuda_stream)
+        if self.masked:
+            rc = lib().lbm_batch_create_masked(arr, self.n, sp, gwp, rp, tp, ws, nbytes.value, st,
+                                               C.byref(h))
+        else:
+            rc = lib().lbm_batch_create(arr, self.n, gwp, rp, tp, ws, nbytes.value, st,
+                                        C.byref(h))
         check(rc)
         self.h = h
 
@@ -404,12 +425,30 @@ class Batch:
         self._chk(lib().lbm_batch_get_tune(self.h, C.byref(t), C.byref(g)))
         return dict(t.as_dict(), grid=g.value)
 
-    def observables(self, allow_nonfinite=False) -> list:
+    def observables(self, allow_nonfinite=False, y_wall=None) -> list:
+        """Observables of every instance; y_wall: contact plane per instance (default planes)."""
         out = (Obs * self.n)()
-        rc = lib().lbm_batch_observables(self.h, out)
+        if y_wall is None:
+            rc = lib().lbm_batch_observables(self.h, out)
+        else:
+            yw = (C.c_double * self.n)(*[float(v) for v in y_wall])
+            rc = lib().lbm_batch_observables_plane(self.h, yw, out)
         if not (rc == E_NONFINITE and allow_nonfinite):
             self._chk(rc)
         return [o.as_dict() for o in out]
+
+    def record_contact_line(self, n: int, every: int, rows, out=None):
+        """Advance n steps recording every instance's contact line on rows[i] every `every`
+        steps (device-side). Returns a (n/every + 1, count, 2) float64 device tensor."""
+        import torch
+        k = n // every + 1
+        if out is None:
+            out = torch.empty((k, self.n, 2), dtype=torch.float64, device=self.ws.device)
+        assert out.is_contiguous() and out.dtype == torch.float64
+        rw = (C.c_int32 * self.n)(*[int(r) for r in rows])
+        self._chk(lib().lbm_batch_record_contact_line(self.h, int(n), int(every), rw,
+                                                      C.c_void_p(out.data_ptr()), out.numel()))
+        return out
 
     def save_state(self, index: int) -> bytes:
         """Checkpoint blob of one instance, loadable by Sim.load_state."""

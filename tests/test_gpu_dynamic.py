@@ -86,3 +86,23 @@ def test_spreading_power_law(gpu, gamma):
         if gp != -0.3:  # the strongly wetting case is still spreading after 20,000 steps
             assert abs(o["theta_deg"] - synth.SPREAD_ANGLE[gp]) <= 2.0
     assert ns[0] > ns[1] > ns[2], "the exponent falls as the equilibrium angle grows"
+
+
+def test_ensemble_recorder_matches_single_runs(gpu):
+    """The three spreading runs as one ensemble: the recorded contact lines equal those of the
+    lattices recorded alone (the same per-node arithmetic, bit for bit)."""
+    import torch
+    cases = [synth.spreading_setup(g) for g in synth.SPREAD_GW]
+    b = gpu.Batch([c["params"] for c in cases], [c["gw"] for c in cases],
+                  [c["rho0"] for c in cases], tune={"tile": 1, "schedule": 2})
+    ser = b.record_contact_line(600, 50, rows=[1, 1, 1])
+    torch.cuda.synchronize()
+    got = ser.cpu().numpy()
+    assert got.shape == (13, 3, 2) and b.current_step == 600
+    for i, c in enumerate(cases):
+        s = gpu.Sim(c["params"], c["gw"], c["rho0"])
+        one = s.record_contact_line(600, 50, row=1)
+        torch.cuda.synchronize()
+        a = one.cpu().numpy()
+        assert np.array_equal(np.isnan(a), np.isnan(got[:, i])), i
+        assert np.array_equal(np.nan_to_num(a), np.nan_to_num(got[:, i])), i

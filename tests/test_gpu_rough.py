@@ -138,5 +138,36 @@ def test_mask_rejected_where_unsupported(orc, gpu):
             sim.set_schedule(sched)
     with pytest.raises(gpu.LBMError):
         sim.adjoint_workspace(100, 10)
-    with pytest.raises(Exception):
-        gpu.Batch([pg], [gw], [rho0])
+
+
+@pytest.mark.parametrize("tile,schedule", [(0, 0), (1, 0), (2, 0), (3, 0), (1, 1)])
+def test_masked_ensemble_bitwise_equals_lone_runs(orc, gpu, tile, schedule):
+    """Pillared lattices of several sizes and forms as one ensemble: every instance carries the
+    same bits as the lattice stepped alone, and the per-instance contact planes feed the fits."""
+    cases = []
+    for i, (form, nx, ny, h) in enumerate([("rho", 63, 40, 6), ("modpsi", 49, 30, 4),
+                                           ("psi", 77, 33, 8)]):
+        q, pg, m, gw, rho0 = pillar_case(orc, form, nx=nx, ny=ny, height=h)
+        cases.append((pg, m, gw, rho0, h + 0.5))
+    steps = 131
+    b = gpu.Batch([c[0] for c in cases], [c[2] for c in cases], [c[3] for c in cases],
+                  tune={"tile": tile, "schedule": schedule}, solids=[c[1] for c in cases])
+    b.step(steps)
+    obs = b.observables(y_wall=[c[4] for c in cases], allow_nonfinite=True)
+    for i, (pg, m, gw, rho0, yw) in enumerate(cases):
+        s = gpu.Sim(pg, gw, rho0, solid=m)
+        s.step(steps)
+        assert np.array_equal(b.f(i), s.f()), f"instance {i}"
+        o = s.observables(y_wall=yw, allow_nonfinite=True)
+        assert o["rho_min"] == obs[i]["rho_min"] and o["n_fit"] == obs[i]["n_fit"]
+
+
+def test_masked_ensemble_rejects_two_steps_and_mixing(orc, gpu):
+    q, pg, m, gw, rho0 = pillar_case(orc, "rho")
+    with pytest.raises(gpu.LBMError):
+        gpu.Batch([pg], [gw], [rho0], tune={"tile": 1, "schedule": 2}, solids=[m])
+    flat = synth.base_params(nx=40, ny=20)
+    rf = synth.droplet_rho(40, 20, q.rho_l, q.rho_v, [(20.0, 0.5)], [6.0])
+    with pytest.raises((gpu.LBMError, AssertionError)):  # the binding or the library refuses
+        gpu.Batch([pg, dict(flat, rho_l=q.rho_l, rho_v=q.rho_v)], [gw, np.zeros((2, 40))],
+                  [rho0, rf])
