@@ -8,7 +8,7 @@
  * ---------------------------------
  * - All functions are extern "C", return int: LBM_OK (0) or a negative LBM_E_* code. They never
  *   abort or exit. lbm_strerror() names a code; lbm_last_error() gives the message of the last
- *   failure on a context.
+ *   failure on a context, or with NULL that of the last failed creation on the calling thread.
  * - Arithmetic is IEEE binary64 throughout.
  * - Lattice: nx columns (x, periodic) by ny rows (y). With walls = 1 or 2, rows y = 0 and
  *   y = ny-1 are solid nodes (flat walls) and the fluid occupies rows 1 .. ny-2. walls = 1:

@@ -44,6 +44,15 @@ namespace {
 
 constexpr size_t kAlign = 256;
 
+// Message of the last failed lbm_create* / lbm_batch_create* on this thread (no handle exists
+// then); returned by lbm_last_error(NULL) and lbm_batch_last_error(NULL).
+thread_local std::string g_create_err;
+
+int create_fail(int code, const char* what, hipError_t e) {
+    g_create_err = std::string(what) + ": " + hipGetErrorString(e);
+    return code;
+}
+
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
@@ -278,7 +287,7 @@ const char* lbm_strerror(int code) {
     }
 }
 
-const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : ""; }
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
 int lbm_maxwell_cs(double a, double b, double R, double T, double* rho_v, double* rho_l,
                    double* p0) {
@@ -448,11 +457,11 @@ static int create_impl(const lbm_params* p, const uint8_t* solid, const double* 
 
     hipStream_t s = c->stream;
     hipError_t e;
-    if ((e = hipMemsetAsync(c->ws, 0, L.total, s)) != hipSuccess) { delete c; return LBM_E_HIP; }
+    if ((e = lbm::launch_zero(c->ws, L.total, s)) != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create: workspace clear", e); }
     if (gw_host) {
         e = hipMemcpy2DAsync(c->gw, L.pitch * sizeof(double), gw_host, p->nx * sizeof(double),
                              p->nx * sizeof(double), gw_rows, hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) { delete c; return LBM_E_HIP; }
+        if (e != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create: G_w copy", e); }
     }
     if (solid) {
         // the fused single step with the tile shapes that stage the halo is the masked schedule
@@ -463,16 +472,16 @@ static int create_impl(const lbm_params* p, const uint8_t* solid, const double* 
         e = hipMemcpyAsync(d_links, lk.data(), lk.size() * sizeof(unsigned short),
                            hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);  // lk is a host temporary
-        if (e != hipSuccess) { delete c; return LBM_E_HIP; }
+        if (e != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create: links copy", e); }
         c->kp.links = d_links;
         c->kp.gwn = c->gw;
     }
     // stage rho0 in the second population buffer, then build the first from it
     e = hipMemcpy2DAsync(c->g[1], L.pitch * sizeof(double), rho0_host, p->nx * sizeof(double),
                          p->nx * sizeof(double), p->ny, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) { delete c; return LBM_E_HIP; }
-    if ((e = lbm::launch_init(c->kp, c->g[1], c->g[0], s)) != hipSuccess) { delete c; return LBM_E_HIP; }
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) { delete c; return LBM_E_HIP; }
+    if (e != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create: rho0 copy", e); }
+    if ((e = lbm::launch_init(c->kp, c->g[1], c->g[0], s)) != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create launch_init", e); }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create hipStreamSynchronize", e); }
     *out = c;
     return LBM_OK;
 }
@@ -675,7 +684,7 @@ int lbm_read_rho(lbm_ctx* c, double* host, size_t count) {
     if (!c || !host) return LBM_E_INVAL;
     if (count < (size_t)c->p.nx * c->p.ny) return LBM_E_SIZE;
     double* scratch = c->g[c->cur ^ 1];
-    hipError_t e = hipMemsetAsync(scratch, 0, (size_t)c->kp.plane * sizeof(double), c->stream);
+    hipError_t e = lbm::launch_zero(scratch, (size_t)c->kp.plane * sizeof(double), c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "read_rho memset");
     e = lbm::launch_rho_psi(c->kp, c->g[c->cur], c->psi, scratch, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "read_rho");
@@ -686,7 +695,7 @@ int lbm_read_f(lbm_ctx* c, double* host, size_t count) {
     if (!c || !host) return LBM_E_INVAL;
     if (count < (size_t)9 * c->p.nx * c->p.ny) return LBM_E_SIZE;
     double* scratch = c->g[c->cur ^ 1];
-    hipError_t e = hipMemsetAsync(scratch, 0, (size_t)9 * c->kp.plane * sizeof(double), c->stream);
+    hipError_t e = lbm::launch_zero(scratch, (size_t)9 * c->kp.plane * sizeof(double), c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "read_f memset");
     e = lbm::launch_pull(c->kp, c->g[c->cur], scratch, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "read_f");
@@ -820,7 +829,7 @@ int lbm_backward(lbm_ctx* c, int64_t nsteps, int32_t K, void* d_adj, size_t byte
     char* w = (char*)d_adj;
     const size_t fb = (size_t)9 * P.plane * sizeof(double);
     (void)hipGetLastError();  // report only errors of this call
-    hipError_t e = hipMemsetAsync(w + A.off_a, 0, A.total - A.off_a, s);
+    hipError_t e = lbm::launch_zero(w + A.off_a, A.total - A.off_a, s);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint clear");
 
     double sums[3];
@@ -907,6 +916,8 @@ struct lbm_batch {
 namespace {
 
 constexpr int kGraphChunk = 64;
+
+
 constexpr int kSpinLimit = 1 << 22;
 
 struct BatchLayout {
@@ -1028,8 +1039,8 @@ static int batch_create_impl(const lbm_params* p, int32_t count,
     b->pgraph_n = -1;
     b->pgraph_cur = -1;
     hipStream_t s = b->stream;
-    hipError_t e = hipMemsetAsync(b->ws, 0, B.total, s);
-    if (e != hipSuccess) { delete b; return LBM_E_HIP; }
+    hipError_t e = lbm::launch_zero(b->ws, B.total, s);
+    if (e != hipSuccess) { delete b; return create_fail(LBM_E_HIP, "create: workspace clear", e); }
     std::vector<int> tile_inst(B.ntiles);
     std::vector<std::vector<unsigned short>> links(count);  // host staging until the final sync
     for (int i = 0; i < count; ++i) {
@@ -1063,14 +1074,14 @@ static int batch_create_impl(const lbm_params* p, int32_t count,
             e = hipMemcpy2DAsync(d.gw, L.pitch * sizeof(double), gw_host[i],
                                  p[i].nx * sizeof(double), p[i].nx * sizeof(double), gw_rows,
                                  hipMemcpyHostToDevice, s);
-            if (e != hipSuccess) { delete b; return LBM_E_HIP; }
+            if (e != hipSuccess) { delete b; return create_fail(LBM_E_HIP, "create: G_w copy", e); }
         }
         if (solid) {
             links[i] = mask_links(&p[i], solid, L.pitch);
             unsigned short* dl = (unsigned short*)(base + L.off_links);
             e = hipMemcpyAsync(dl, links[i].data(), links[i].size() * sizeof(unsigned short),
                                hipMemcpyHostToDevice, s);
-            if (e != hipSuccess) { delete b; return LBM_E_HIP; }
+            if (e != hipSuccess) { delete b; return create_fail(LBM_E_HIP, "create: links copy", e); }
             kp.links = dl;
             kp.gwn = d.gw;
             d.P = kp;
@@ -1080,16 +1091,16 @@ static int batch_create_impl(const lbm_params* p, int32_t count,
         e = hipMemcpy2DAsync(d.g[1], L.pitch * sizeof(double), rho0_host[i],
                              p[i].nx * sizeof(double), p[i].nx * sizeof(double), p[i].ny,
                              hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) { delete b; return LBM_E_HIP; }
-        if ((e = lbm::launch_init(kp, d.g[1], d.g[0], s)) != hipSuccess) { delete b; return LBM_E_HIP; }
+        if (e != hipSuccess) { delete b; return create_fail(LBM_E_HIP, "create: rho0 copy", e); }
+        if ((e = lbm::launch_init(kp, d.g[1], d.g[0], s)) != hipSuccess) { delete b; return create_fail(LBM_E_HIP, "create launch_init", e); }
     }
     e = hipMemcpyAsync(b->d_inst, b->desc.data(), count * sizeof(lbm::InstDesc),
                        hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) { delete b; return LBM_E_HIP; }
+    if (e != hipSuccess) { delete b; return create_fail(LBM_E_HIP, "create: descriptor copy", e); }
     e = hipMemcpyAsync(b->d_tile_inst, tile_inst.data(), B.ntiles * sizeof(int),
                        hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) { delete b; return LBM_E_HIP; }
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) { delete b; return LBM_E_HIP; }
+    if (e != hipSuccess) { delete b; return create_fail(LBM_E_HIP, "create: tile table copy", e); }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) { delete b; return create_fail(LBM_E_HIP, "create hipStreamSynchronize", e); }
     // persistent grid: co-resident workgroups only (occupancy x compute units)
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
@@ -1312,7 +1323,7 @@ int lbm_batch_read_f(lbm_batch* b, int32_t index, double* host, size_t count) {
     if (count < (size_t)9 * P.nx * P.ny) return LBM_E_SIZE;
     const lbm::InstDesc& d = b->desc[index];
     double* scratch = d.g[b->cur ^ 1];
-    hipError_t e = hipMemsetAsync(scratch, 0, (size_t)9 * P.plane * sizeof(double), b->stream);
+    hipError_t e = lbm::launch_zero(scratch, (size_t)9 * P.plane * sizeof(double), b->stream);
     if (e == hipSuccess) e = lbm::launch_pull(P, d.g[b->cur], scratch, b->stream);
     for (int a = 0; a < 9 && e == hipSuccess; ++a)
         e = hipMemcpy2DAsync(host + (size_t)a * P.nx * P.ny, P.nx * sizeof(double),
@@ -1363,7 +1374,7 @@ int lbm_batch_destroy(lbm_batch* b) {
     return LBM_OK;
 }
 
-const char* lbm_batch_last_error(const lbm_batch* b) { return b ? b->err.c_str() : ""; }
+const char* lbm_batch_last_error(const lbm_batch* b) { return b ? b->err.c_str() : g_create_err.c_str(); }
 
 // Try every tile shape x schedule (and, for the persistent schedule, the full and half
 // occupancy) on the given ensemble for `steps` steps each; return the fastest in *best and its

@@ -32,6 +32,7 @@ hipError_t launch_step(const KParams& P, int schedule, int tile, const double* g
                        double* psi, const double* gw, hipStream_t s);
 hipError_t launch_step2(const KParams& P, int tile2, const double* gin, double* gout,
                         const double* gw, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);  // bytes and p 8-byte aligned
 hipError_t launch_init(const KParams& P, const double* rho0, double* g, hipStream_t s);
 hipError_t launch_pull(const KParams& P, const double* gin, double* fout, hipStream_t s);
 hipError_t launch_rho_psi(const KParams& P, const double* gin, double* psi, double* rho,

@@ -11,6 +11,8 @@
 //   two-step  two time steps per launch with the intermediate state in LDS (step2_tile).
 // With the wet-node wall scheme the boundary nodes also write their force (16 B) to the solid row,
 // which the next pull reads back; that traffic is confined to two rows of the lattice.
+#include <algorithm>
+
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
@@ -278,6 +280,13 @@ __global__ __launch_bounds__(256) void k_contact_line(KParams P, const double* _
     contact_line_block(P, gin, row, mid, out);
 }
 
+// Zero fill of n 8-byte words (grid-stride). The library clears its buffers with this kernel
+// rather than a runtime memset, so the clear is ordered like every other kernel of the stream.
+__global__ __launch_bounds__(256) void k_zero(unsigned long long* __restrict__ p, size_t n) {
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = 0ull;
+}
+
 // ------------------------------------------------------------------------------------------------
 // Host-side launchers
 // ------------------------------------------------------------------------------------------------
@@ -371,6 +380,15 @@ hipError_t launch_step(const KParams& P, int schedule, int tile, const double* g
         case 7: return launch_step_ov<14>(P, gin, gout, gw, s);
         default: return launch_step_t<64, 4, true>(P, gin, gout, psi, gw, s);
     }
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+    if (bytes % 8 || ((uintptr_t)p) % 8) return hipErrorInvalidValue;
+    const size_t n = bytes / 8;
+    if (n == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, (unsigned long long*)p, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_init(const KParams& P, const double* rho0, double* g, hipStream_t s) {

@@ -128,6 +128,10 @@ def lib() -> C.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1410_2569_amd.build`")
+        # torch ships its own HIP runtime under the same soname as the system one liblbm.so was
+        # linked against; loading torch first makes both use torch's (loading liblbm.so first
+        # would bind torch to the system runtime, which then finds no device)
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
@@ -143,12 +147,13 @@ def _dptr(a: np.ndarray):
 
 
 def check(rc: int, ctx=None):
+    """Raise LBMError for a failed call; the message adds the context's last error, or (without a
+    context) the reason of the last failed creation on this thread."""
     if rc != OK:
         msg = lib().lbm_strerror(rc).decode()
-        if ctx:
-            extra = lib().lbm_last_error(ctx)
-            if extra:
-                msg += ": " + extra.decode()
+        extra = lib().lbm_last_error(ctx)
+        if extra:
+            msg += ": " + extra.decode()
         raise LBMError(rc, msg)
 
 
