@@ -500,21 +500,27 @@ def spreading_run(args) -> dict:
     import synth
     from paper_1410_2569_amd import analysis as A
 
-    lap = synth.laplace_setup()
-    b = L.Batch([c["params"] for c in lap], [np.zeros((2, c["params"]["nx"])) for c in lap],
-                [c["rho0"] for c in lap])
-    b.step(30_000)
-    radii, dp = [], []
-    for i, c in enumerate(lap):
-        rho = b.f(i).sum(0)
-        n = rho.shape[0]
-        radii.append(math.sqrt(((rho - 1.0) / 499.0).sum() / math.pi))
-        dp.append(L.lbm.pressure(c["params"], rho[n // 2, n // 2])
-                  - L.lbm.pressure(c["params"], rho[0, 0]))
-    gamma, icpt = A.laplace_gamma(radii, dp)
-    del b
+    if args.spread_gamma is not None:
+        gamma, icpt = float(args.spread_gamma), None  # given: the Laplace stage is skipped
+    else:
+        lap = synth.laplace_setup()
+        b = L.Batch([c["params"] for c in lap], [np.zeros((2, c["params"]["nx"])) for c in lap],
+                    [c["rho0"] for c in lap])
+        b.step(30_000)
+        radii, dp = [], []
+        for i, c in enumerate(lap):
+            rho = b.f(i).sum(0)
+            n = rho.shape[0]
+            area = ((rho - 1.0) / 499.0).sum()
+            if not area > 0:
+                raise RuntimeError(f"Laplace droplet {i} has no liquid left (area {area})")
+            radii.append(math.sqrt(area / math.pi))
+            dp.append(L.lbm.pressure(c["params"], rho[n // 2, n // 2])
+                      - L.lbm.pressure(c["params"], rho[0, 0]))
+        gamma, icpt = A.laplace_gamma(radii, dp)
+        del b
     tau = A.inertial_time(synth.PAPER["rho_l"], synth.PAPER["radius"], gamma)
-    log(f"spreading: gamma {gamma:.4f} (intercept {icpt:.4f}), tau_rho {tau:.1f} steps")
+    log(f"spreading: gamma {gamma:.4f} (intercept {icpt}), tau_rho {tau:.1f} steps")
     N, every = args.spread_steps, 10
     from paper_1410_2569_amd import tune as T
     cs = [synth.spreading_setup(gp) for gp in synth.SPREAD_GW]
@@ -565,7 +571,8 @@ def spreading_run(args) -> dict:
                          "bytes_per_lu": BYTES_PER_LU,
                          "lu_per_launch": fluid * (2 if two else 1),
                          "avg_launch_us": round(secs / launches * 1e6, 3)},
-            "gamma": round(gamma, 5), "laplace_intercept": round(icpt, 5),
+            "gamma": round(gamma, 5),
+            "laplace_intercept": None if icpt is None else round(icpt, 5),
             "tau_rho_steps": round(tau, 1), "fit_window_t_over_tau": list(SPREAD_WINDOW),
             "runs": rows}
 
@@ -650,6 +657,8 @@ def main():
     ap.add_argument("--paper-steps", type=int, default=30_000)
     ap.add_argument("--rough-steps", type=int, default=100_000)
     ap.add_argument("--spread-steps", type=int, default=20_000)
+    ap.add_argument("--spread-gamma", type=float, default=None,
+                    help="surface tension to use instead of measuring it (Laplace stage skipped)")
     ap.add_argument("--c5-steps", type=int, default=30_000)
     ap.add_argument("--c5-adj-steps", type=int, default=2_000)
     ap.add_argument("--c5-K", type=int, default=45)
