@@ -24,17 +24,23 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source of the library and link liblbm.so. Always recompiles."""
-    objs = []
+    """Compile every HIP source of the library (in parallel) and link liblbm.so. Always
+    recompiles."""
+    from concurrent.futures import ThreadPoolExecutor
+
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(HERE, "_build", src.replace(".hip", ".o"))
-        cmd = [HIPCC, *FLAGS, "-I", os.path.join(os.path.dirname(HERE), "include"), "-c",
-               os.path.join(CSRC, src), "-o", obj]
+        cmds.append([HIPCC, *FLAGS, "-I", os.path.join(os.path.dirname(HERE), "include"), "-c",
+                     os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    for cmd in cmds:
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        objs.append(obj)
+    with ThreadPoolExecutor(max_workers=len(cmds)) as pool:
+        for f in [pool.submit(subprocess.check_call, cmd) for cmd in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

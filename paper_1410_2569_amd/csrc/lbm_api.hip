@@ -904,6 +904,7 @@ struct lbm_batch {
     lbm_tune tune;
     int grid;  // persistent grid size
     int geo;   // lbm::GEO_ROWS, GEO_WET (some instance wet-node) or GEO_MASK (all masked)
+    int eos;   // lbm::EOS_CS or EOS_PW shared by every instance, else EOS_ANY
     std::vector<int32_t> rows;  // contact-line rows of the last record call (host copy)
     int* d_rows;
     hipGraphExec_t graph[2];  // per-step schedule: kGraphChunk launches starting at parity 0 / 1
@@ -1028,6 +1029,9 @@ static int batch_create_impl(const lbm_params* p, int32_t count,
     b->d_flag = (int*)(b->ws + B.off_bar + 64);
     b->ntiles = B.ntiles;
     b->geo = solid_host ? lbm::GEO_MASK : lbm::GEO_ROWS;
+    b->eos = p[0].eos == LBM_EOS_CS ? lbm::EOS_CS : lbm::EOS_PW;
+    for (int i = 1; i < count; ++i)
+        if (p[i].eos != p[0].eos) b->eos = lbm::EOS_ANY;
     for (int i = 0; i < count; ++i)
         if (p[i].walls == LBM_WALLS_WET_NODE) b->geo = lbm::GEO_WET;
     b->d_rows = (int*)(b->ws + B.off_rows);
@@ -1138,7 +1142,7 @@ int lbm_batch_create_masked(const lbm_params* p, int32_t count, const uint8_t* c
 static int batch_direct(lbm_batch* b, int64_t n) {
     if (b->tune.schedule == 2) {
         for (; n >= 2; n -= 2) {
-            hipError_t e = lbm::launch_batch_step2(b->tune.tile, b->geo, b->d_inst,
+            hipError_t e = lbm::launch_batch_step2(b->tune.tile, b->geo, b->eos, b->d_inst,
                                                    b->d_tile_inst, b->ntiles, b->cur, b->stream);
             if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, std::string("batch step: ") + hipGetErrorString(e));
             b->cur ^= 1;
@@ -1146,7 +1150,7 @@ static int batch_direct(lbm_batch* b, int64_t n) {
         }
     }
     for (int64_t i = 0; i < n; ++i) {
-        hipError_t e = lbm::launch_batch_step(b->tune.tile, b->geo, b->d_inst, b->d_tile_inst,
+        hipError_t e = lbm::launch_batch_step(b->tune.tile, b->geo, b->eos, b->d_inst, b->d_tile_inst,
                                               b->ntiles, b->cur, b->stream);
         if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, std::string("batch step: ") + hipGetErrorString(e));
         b->cur ^= 1;
@@ -1190,7 +1194,7 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
         if (n > (int64_t)1 << 30) return batch_fail(b, LBM_E_INVAL, "too many steps in one call");
         const int cur = b->cur;
         auto persistent = [&]() {
-            return lbm::launch_batch_persistent(b->tune.tile, b->geo, b->grid, b->d_inst,
+            return lbm::launch_batch_persistent(b->tune.tile, b->geo, b->eos, b->grid, b->d_inst,
                                                 b->d_tile_inst, b->ntiles, (int)n, cur, b->d_bar,
                                                 b->d_flag, kSpinLimit, b->stream);
         };
@@ -1215,10 +1219,10 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
             int rc = capture(b, &b->graph[cur], [&]() {
                 const bool two = b->tune.schedule == 2;  // two steps per launch
                 for (int i = 0; i < (two ? kGraphChunk / 2 : kGraphChunk); ++i) {
-                    hipError_t e = two ? lbm::launch_batch_step2(b->tune.tile, b->geo, b->d_inst,
+                    hipError_t e = two ? lbm::launch_batch_step2(b->tune.tile, b->geo, b->eos, b->d_inst,
                                                                  b->d_tile_inst, b->ntiles,
                                                                  (cur + i) & 1, b->stream)
-                                       : lbm::launch_batch_step(b->tune.tile, b->geo, b->d_inst,
+                                       : lbm::launch_batch_step(b->tune.tile, b->geo, b->eos, b->d_inst,
                                                                 b->d_tile_inst, b->ntiles,
                                                                 (cur + i) & 1, b->stream);
                     if (e != hipSuccess) return e;

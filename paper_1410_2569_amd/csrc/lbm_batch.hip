@@ -9,6 +9,7 @@
 //              waits for every workgroup, then acquires; its wait is bounded and raises an abort
 //              flag on timeout so every workgroup always exits.
 #include <algorithm>
+#include <type_traits>
 
 #include "lbm_device.h"
 #include "lbm_internal.h"
@@ -23,8 +24,9 @@ __device__ __forceinline__ void batch_tile_origin(const InstDesc* D, int t, int 
 }
 
 // GEO: GEO_MASK for an ensemble of solid masks, GEO_WET when some instance uses the wet-node
-// wall, else GEO_ROWS (chosen at launch).
-template <int TX, int TY, int GEO>
+// wall, else GEO_ROWS; EOS: the equation of state shared by every instance, or EOS_ANY (chosen at
+// launch).
+template <int TX, int TY, int GEO, int EOS>
 __global__ __launch_bounds__(TX* TY) void k_batch_step(const InstDesc* __restrict__ inst,
                                                        const int* __restrict__ tile_inst,
                                                        int ntiles, int cur) {
@@ -33,11 +35,11 @@ __global__ __launch_bounds__(TX* TY) void k_batch_step(const InstDesc* __restric
     const InstDesc* D = inst + tile_inst[t];
     int x0, y0;
     batch_tile_origin(D, t, TX, TY, x0, y0);
-    step_tile<TX, TY, true, GEO>(D->P, D->g[cur], D->g[cur ^ 1], nullptr, D->gw, x0, y0, sp);
+    step_tile<TX, TY, true, GEO, EOS>(D->P, D->g[cur], D->g[cur ^ 1], nullptr, D->gw, x0, y0, sp);
 }
 
 // Two steps per launch over the work-list (the tiles are the output tiles of step2_tile).
-template <int TX, int TY, int GEO>
+template <int TX, int TY, int GEO, int EOS>
 __global__ __launch_bounds__(TX* TY) void k_batch_step2(const InstDesc* __restrict__ inst,
                                                         const int* __restrict__ tile_inst,
                                                         int ntiles, int cur) {
@@ -46,7 +48,7 @@ __global__ __launch_bounds__(TX* TY) void k_batch_step2(const InstDesc* __restri
     const InstDesc* D = inst + tile_inst[t];
     int x0, y0;
     batch_tile_origin(D, t, TX, TY, x0, y0);
-    step2_tile<TX, TY, GEO>(D->P, D->g[cur], D->g[cur ^ 1], D->gw, x0, y0, lds);
+    step2_tile<TX, TY, GEO, EOS>(D->P, D->g[cur], D->g[cur ^ 1], D->gw, x0, y0, lds);
 }
 
 // Grid-wide barrier number `target / gridDim.x`. Returns false when the run was aborted.
@@ -78,7 +80,7 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, int
     return *verdict != 0;
 }
 
-template <int TX, int TY, int GEO>
+template <int TX, int TY, int GEO, int EOS>
 __global__ __launch_bounds__(TX* TY) void k_batch_persistent(const InstDesc* __restrict__ inst,
                                                              const int* __restrict__ tile_inst,
                                                              int ntiles, int nsteps, int cur0,
@@ -96,8 +98,8 @@ __global__ __launch_bounds__(TX* TY) void k_batch_persistent(const InstDesc* __r
             const InstDesc* D = inst + tile_inst[t];
             int x0, y0;
             batch_tile_origin(D, t, TX, TY, x0, y0);
-            step_tile<TX, TY, true, GEO>(D->P, D->g[cur], D->g[cur ^ 1], nullptr, D->gw, x0, y0,
-                                         sp);
+            step_tile<TX, TY, true, GEO, EOS>(D->P, D->g[cur], D->g[cur ^ 1], nullptr, D->gw, x0,
+                                              y0, sp);
             __syncthreads();  // the LDS tile is reused by the next tile
         }
         if (!grid_barrier(bar, (unsigned)(s + 1) * (unsigned)G, flag, spin_limit, &verdict)) return;
@@ -122,107 +124,111 @@ __global__ void k_batch_reset(unsigned* bar, int* flag) {
 }
 
 // ------------------------------------------------------------------------------------------------
-template <int TX, int TY>
-static hipError_t launch_batch_t(int geo, const InstDesc* inst, const int* tile_inst, int ntiles,
-                                 int cur, hipStream_t s) {
-    if (geo == GEO_MASK)
-        hipLaunchKernelGGL((k_batch_step<TX, TY, GEO_MASK>), dim3(ntiles), dim3(TX * TY), 0, s,
-                           inst, tile_inst, ntiles, cur);
-    else if (geo == GEO_WET)
-        hipLaunchKernelGGL((k_batch_step<TX, TY, GEO_WET>), dim3(ntiles), dim3(TX * TY), 0, s, inst,
-                           tile_inst, ntiles, cur);
-    else
-        hipLaunchKernelGGL((k_batch_step<TX, TY, GEO_ROWS>), dim3(ntiles), dim3(TX * TY), 0, s, inst,
-                           tile_inst, ntiles, cur);
-    return hipGetLastError();
+// Calls f(geo, eos) with the ensemble's geometry and equation-of-state variants as compile-time
+// constants.
+template <class F>
+static hipError_t dispatch(int geo, int eos, F&& f) {
+    auto with_eos = [&](auto g) {
+        if (eos == EOS_CS) return f(g, std::integral_constant<int, EOS_CS>{});
+        if (eos == EOS_PW) return f(g, std::integral_constant<int, EOS_PW>{});
+        return f(g, std::integral_constant<int, EOS_ANY>{});
+    };
+    if (geo == GEO_MASK) return with_eos(std::integral_constant<int, GEO_MASK>{});
+    if (geo == GEO_WET) return with_eos(std::integral_constant<int, GEO_WET>{});
+    return with_eos(std::integral_constant<int, GEO_ROWS>{});
 }
 
 template <int TX, int TY>
-static hipError_t launch_persist_t(int geo, int grid, const InstDesc* inst, const int* tile_inst,
-                                   int ntiles, int nsteps, int cur, unsigned* bar, int* flag,
-                                   int spin_limit, hipStream_t s) {
+static hipError_t launch_batch_t(int geo, int eos, const InstDesc* inst, const int* tile_inst,
+                                 int ntiles, int cur, hipStream_t s) {
+    return dispatch(geo, eos, [&](auto g, auto e) {
+        hipLaunchKernelGGL((k_batch_step<TX, TY, decltype(g)::value, decltype(e)::value>),
+                           dim3(ntiles), dim3(TX * TY), 0, s, inst, tile_inst, ntiles, cur);
+        return hipGetLastError();
+    });
+}
+
+template <int TX, int TY>
+static hipError_t launch_persist_t(int geo, int eos, int grid, const InstDesc* inst,
+                                   const int* tile_inst, int ntiles, int nsteps, int cur,
+                                   unsigned* bar, int* flag, int spin_limit, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, bar, flag);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (geo == GEO_MASK)
-        hipLaunchKernelGGL((k_batch_persistent<TX, TY, GEO_MASK>), dim3(grid), dim3(TX * TY), 0, s,
-                           inst, tile_inst, ntiles, nsteps, cur, bar, flag, spin_limit);
-    else if (geo == GEO_WET)
-        hipLaunchKernelGGL((k_batch_persistent<TX, TY, GEO_WET>), dim3(grid), dim3(TX * TY), 0, s,
-                           inst, tile_inst, ntiles, nsteps, cur, bar, flag, spin_limit);
-    else
-        hipLaunchKernelGGL((k_batch_persistent<TX, TY, GEO_ROWS>), dim3(grid), dim3(TX * TY), 0, s,
-                           inst, tile_inst, ntiles, nsteps, cur, bar, flag, spin_limit);
-    return hipGetLastError();
+    hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) return e0;
+    return dispatch(geo, eos, [&](auto g, auto e) {
+        hipLaunchKernelGGL((k_batch_persistent<TX, TY, decltype(g)::value, decltype(e)::value>),
+                           dim3(grid), dim3(TX * TY), 0, s, inst, tile_inst, ntiles, nsteps, cur,
+                           bar, flag, spin_limit);
+        return hipGetLastError();
+    });
 }
 
-// Resident workgroups per CU of the persistent kernel (the smallest of its variants, so a grid
-// sized by it fits whichever is launched).
+// Resident workgroups per CU of the persistent kernel: the smallest over its variants, so a grid
+// sized by it fits whichever is launched.
 template <int TX, int TY>
 static int occupancy_t() {
-    int a = 0, b = 0, c = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_batch_persistent<TX, TY, GEO_ROWS>,
-                                                     TX * TY, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_batch_persistent<TX, TY, GEO_WET>,
-                                                     TX * TY, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_batch_persistent<TX, TY, GEO_MASK>,
-                                                     TX * TY, 0) != hipSuccess)
-        return 0;
-    return std::min(a, std::min(b, c));
+    int lo = 1 << 30;
+    for (int geo : {GEO_ROWS, GEO_WET, GEO_MASK})
+        for (int eos : {EOS_CS, EOS_PW, EOS_ANY}) {
+            int n = 0;
+            hipError_t r = dispatch(geo, eos, [&](auto g, auto e) {
+                return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &n, k_batch_persistent<TX, TY, decltype(g)::value, decltype(e)::value>,
+                    TX * TY, 0);
+            });
+            if (r != hipSuccess) return 0;
+            lo = std::min(lo, n);
+        }
+    return lo;
 }
 
 int batch_tiles(int tile) { return tile >= 0 && tile < 4; }
 
-// Two steps per launch (schedule 2): tile 0 -> 64x8 output tiles, tile 3 -> 64x16; the work-list
-// must have been built for that tile shape.
 template <int TX, int TY>
-static hipError_t launch_batch2_t(int geo, const InstDesc* inst, const int* tile_inst, int ntiles,
-                                  int cur, hipStream_t s) {
-    if (geo == GEO_MASK) return hipErrorInvalidValue;  // two steps per launch: flat walls only
-    if (geo == GEO_WET)
-        hipLaunchKernelGGL((k_batch_step2<TX, TY, GEO_WET>), dim3(ntiles), dim3(TX * TY), 0, s, inst,
-                           tile_inst, ntiles, cur);
-    else
-        hipLaunchKernelGGL((k_batch_step2<TX, TY, GEO_ROWS>), dim3(ntiles), dim3(TX * TY), 0, s, inst,
-                           tile_inst, ntiles, cur);
-    return hipGetLastError();
+static hipError_t launch_batch2_t(int geo, int eos, const InstDesc* inst, const int* tile_inst,
+                                  int ntiles, int cur, hipStream_t s) {
+    return dispatch(geo, eos, [&](auto g, auto e) {
+        if constexpr (decltype(g)::value == GEO_MASK) {
+            return hipErrorInvalidValue;  // two steps per launch: flat walls only
+        } else {
+            hipLaunchKernelGGL((k_batch_step2<TX, TY, decltype(g)::value, decltype(e)::value>),
+                               dim3(ntiles), dim3(TX * TY), 0, s, inst, tile_inst, ntiles, cur);
+            return hipGetLastError();
+        }
+    });
 }
 
-hipError_t launch_batch_step2(int tile, int geo, const InstDesc* inst, const int* tile_inst,
-                              int ntiles, int cur, hipStream_t s) {
-    if (tile == 2) return launch_batch2_t<64, 16>(geo, inst, tile_inst, ntiles, cur, s);
-    return launch_batch2_t<64, 8>(geo, inst, tile_inst, ntiles, cur, s);
+// Two steps per launch (schedule 2): tile 2 -> 64x16 output tiles, otherwise 64x8; the work-list
+// must have been built for that tile shape.
+hipError_t launch_batch_step2(int tile, int geo, int eos, const InstDesc* inst,
+                              const int* tile_inst, int ntiles, int cur, hipStream_t s) {
+    if (tile == 2) return launch_batch2_t<64, 16>(geo, eos, inst, tile_inst, ntiles, cur, s);
+    return launch_batch2_t<64, 8>(geo, eos, inst, tile_inst, ntiles, cur, s);
 }
 
-hipError_t launch_batch_step(int tile, int geo, const InstDesc* inst, const int* tile_inst,
-                             int ntiles, int cur, hipStream_t s) {
+hipError_t launch_batch_step(int tile, int geo, int eos, const InstDesc* inst,
+                             const int* tile_inst, int ntiles, int cur, hipStream_t s) {
     switch (tile) {
-        case 1: return launch_batch_t<64, 8>(geo, inst, tile_inst, ntiles, cur, s);
-        case 2: return launch_batch_t<64, 16>(geo, inst, tile_inst, ntiles, cur, s);
-        case 3: return launch_batch_t<128, 4>(geo, inst, tile_inst, ntiles, cur, s);
-        default: return launch_batch_t<64, 4>(geo, inst, tile_inst, ntiles, cur, s);
+        case 1: return launch_batch_t<64, 8>(geo, eos, inst, tile_inst, ntiles, cur, s);
+        case 2: return launch_batch_t<64, 16>(geo, eos, inst, tile_inst, ntiles, cur, s);
+        case 3: return launch_batch_t<128, 4>(geo, eos, inst, tile_inst, ntiles, cur, s);
+        default: return launch_batch_t<64, 4>(geo, eos, inst, tile_inst, ntiles, cur, s);
     }
 }
 
-hipError_t launch_batch_persistent(int tile, int geo, int grid, const InstDesc* inst,
+hipError_t launch_batch_persistent(int tile, int geo, int eos, int grid, const InstDesc* inst,
                                    const int* tile_inst, int ntiles, int nsteps, int cur,
                                    unsigned* bar, int* flag, int spin_limit, hipStream_t s) {
     switch (tile) {
-        case 1: return launch_persist_t<64, 8>(geo, grid, inst, tile_inst, ntiles, nsteps, cur,
-                                               bar, flag, spin_limit, s);
-        case 2: return launch_persist_t<64, 16>(geo, grid, inst, tile_inst, ntiles, nsteps, cur,
-                                                bar, flag, spin_limit, s);
-        case 3: return launch_persist_t<128, 4>(geo, grid, inst, tile_inst, ntiles, nsteps, cur,
-                                                bar, flag, spin_limit, s);
-        default: return launch_persist_t<64, 4>(geo, grid, inst, tile_inst, ntiles, nsteps, cur,
-                                                bar, flag, spin_limit, s);
+        case 1: return launch_persist_t<64, 8>(geo, eos, grid, inst, tile_inst, ntiles, nsteps,
+                                               cur, bar, flag, spin_limit, s);
+        case 2: return launch_persist_t<64, 16>(geo, eos, grid, inst, tile_inst, ntiles, nsteps,
+                                                cur, bar, flag, spin_limit, s);
+        case 3: return launch_persist_t<128, 4>(geo, eos, grid, inst, tile_inst, ntiles, nsteps,
+                                                cur, bar, flag, spin_limit, s);
+        default: return launch_persist_t<64, 4>(geo, eos, grid, inst, tile_inst, ntiles, nsteps,
+                                                cur, bar, flag, spin_limit, s);
     }
-}
-
-hipError_t launch_batch_contact_line(const InstDesc* inst, const int* rows, int count, int cur,
-                                     double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_contact_line, dim3(count), dim3(256), 0, s, inst, rows, cur, out);
-    return hipGetLastError();
 }
 
 int batch_persistent_occupancy(int tile) {
@@ -232,6 +238,12 @@ int batch_persistent_occupancy(int tile) {
         case 3: return occupancy_t<128, 4>();
         default: return occupancy_t<64, 4>();
     }
+}
+
+hipError_t launch_batch_contact_line(const InstDesc* inst, const int* rows, int count, int cur,
+                                     double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_contact_line, dim3(count), dim3(256), 0, s, inst, rows, cur, out);
+    return hipGetLastError();
 }
 
 }  // namespace lbm

@@ -45,6 +45,9 @@ struct KParams {
 // Geometry variants compiled into the step kernels. GEO_ROWS: periodic lattice or bounce-back
 // rows; GEO_WET: also the wet-node rule where P.wet says so; GEO_MASK: solid mask.
 enum { GEO_ROWS = 0, GEO_WET = 1, GEO_MASK = 2 };
+// Equation-of-state variants compiled into the step kernels: one EOS only, or the run-time choice
+// of P.eos (off the step loop, and ensembles that mix both).
+enum { EOS_CS = 0, EOS_PW = 1, EOS_ANY = 2 };
 
 __device__ __forceinline__ int wrap_once(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
@@ -64,11 +67,13 @@ __device__ __forceinline__ int wrapx(int x, int nx) {
 // so every kernel that inlines these functions (plain step, every tile shape, ensembles,
 // persistent loop, adjoint recomputation) produces the same bits.
 
-// p_EOS(rho) and psi(rho); a negative radicand yields NaN, caught by the observables.
+// p_EOS(rho) and psi(rho); a negative radicand yields NaN, caught by the observables. EOS selects
+// the equation of state compiled in (EOS_ANY: P.eos at run time).
+template <int EOS = EOS_ANY>
 __device__ __forceinline__ double psi_of_rho(const KParams& P, double rho) {
 #pragma clang fp contract(off)
     double p;
-    if (P.eos == 0) {
+    if (EOS == EOS_CS || (EOS == EOS_ANY && P.eos == 0)) {
         const double eta = P.b4 * rho;
         const double om = 1.0 - eta;
         const double num = fma(eta, fma(eta, om, 1.0), 1.0);  // 1 + eta + eta^2 - eta^3
@@ -202,7 +207,7 @@ __device__ __forceinline__ bool slot_source(const KParams& P, int gx, int gy, in
 }
 
 // psi at lattice position (gx, gy) (see slot_source), evaluated from the pulled populations.
-template <int GEO>
+template <int GEO, int EOS = EOS_ANY>
 __device__ __forceinline__ double psi_at(const KParams& P, const double* __restrict__ g, int gx,
                                          int gy) {
 #pragma clang fp contract(off)
@@ -210,7 +215,8 @@ __device__ __forceinline__ double psi_at(const KParams& P, const double* __restr
     if (!slot_source(P, gx, gy, sx, sy)) return 0.0;
     double f[9];
     pull9<GEO>(P, g, sx, sy, f);
-    return psi_of_rho(P, ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8]);
+    return psi_of_rho<EOS>(P, ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) +
+                                  f[8]);
 }
 
 __device__ __forceinline__ double sum9(const double f[9]) {
@@ -405,7 +411,7 @@ namespace lbm {
 // threads with the LDS array sp of (TY + 2) * (TX + 2) doubles. FUSED: psi of the tile and its
 // halo is evaluated from the pulled populations; otherwise it is staged from psi_g. Contains
 // __syncthreads() and no early return, so it can run inside loops over tiles.
-template <int TX, int TY, bool FUSED, int GEO>
+template <int TX, int TY, bool FUSED, int GEO, int EOS = EOS_ANY>
 __device__ __forceinline__ void step_tile(const KParams& P, const double* __restrict__ gin,
                                           double* __restrict__ gout,
                                           const double* __restrict__ psi_g,
@@ -426,18 +432,18 @@ __device__ __forceinline__ void step_tile(const KParams& P, const double* __rest
         if constexpr (GEO == GEO_MASK) pull9_mask(P, gin, x, y, lk, f);
         else pull9<GEO>(P, gin, x, y, f);
         rho = sum9(f);
-        if (FUSED) psi_c = psi_of_rho(P, rho);
+        if (FUSED) psi_c = psi_of_rho<EOS>(P, rho);
     }
     if (FUSED) {
         // own slot: computed above, or (outside the fluid) the value at that lattice position
-        sp[(ty + 1) * LW + tx + 1] = active ? psi_c : psi_at<GEO>(P, gin, x, y);
+        sp[(ty + 1) * LW + tx + 1] = active ? psi_c : psi_at<GEO, EOS>(P, gin, x, y);
         for (int h = threadIdx.x; h < NH; h += NT) {
             int hx, hy;  // tile-local coordinates in [-1, TX] x [-1, TY]
             if (h < LW) { hx = h - 1; hy = -1; }
             else if (h < 2 * LW) { hx = h - LW - 1; hy = TY; }
             else if (h < 2 * LW + TY) { hx = -1; hy = h - 2 * LW; }
             else { hx = TX; hy = h - 2 * LW - TY; }
-            sp[(hy + 1) * LW + hx + 1] = psi_at<GEO>(P, gin, x0 + hx, y0 + hy);
+            sp[(hy + 1) * LW + hx + 1] = psi_at<GEO, EOS>(P, gin, x0 + hx, y0 + hy);
         }
     } else {
         // stage psi (ghost rows already mirrored by the psi pass) with its halo
@@ -514,7 +520,7 @@ struct Step2Lds {
     double ps2[W1 * H1];
 };
 
-template <int TX, int TY, int GEO>
+template <int TX, int TY, int GEO, int EOS = EOS_ANY>
 __device__ __forceinline__ void step2_tile(const KParams& P, const double* __restrict__ gin,
                                            double* __restrict__ gout,
                                            const double* __restrict__ gw, int x0, int y0,
@@ -548,10 +554,10 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
         if (fluid) {
             pull9<GEO>(P, gin, wrapx(x0 - 2 + lx, P.nx), gy, fk[r]);
             rk[r] = sum9(fk[r]);
-            ps = psi_of_rho(P, rk[r]);
+            ps = psi_of_rho<EOS>(P, rk[r]);
             ok[r] = true;
         } else {
-            ps = psi_at<GEO>(P, gin, x0 - 2 + lx, y0 - 2 + ly);  // solid row: ghost value or 0
+            ps = psi_at<GEO, EOS>(P, gin, x0 - 2 + lx, y0 - 2 + ly);  // solid row: ghost or 0
         }
         ps1[(ly + 1) * W3 + lx + 1] = ps;
     }
@@ -562,7 +568,7 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
         else if (h < 2 * W3) { lx = h - W3; ly = H3 - 1; }
         else if (h < 2 * W3 + H2) { lx = 0; ly = h - 2 * W3 + 1; }
         else { lx = W3 - 1; ly = h - 2 * W3 - H2 + 1; }
-        ps1[ly * W3 + lx] = psi_at<GEO>(P, gin, x0 - 3 + lx, y0 - 3 + ly);
+        ps1[ly * W3 + lx] = psi_at<GEO, EOS>(P, gin, x0 - 3 + lx, y0 - 3 + ly);
     }
     __syncthreads();
 
@@ -601,7 +607,7 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
             const int ly2 = P.walls ? sy - (y0 - 2) : ly + 1;
             double f[9];
             pull9_lds<GEO>(P, g1, PL, W2, ly2 * W2 + lx + 1, sy, f);
-            v = psi_of_rho(P, sum9(f));
+            v = psi_of_rho<EOS>(P, sum9(f));
         }
         ps2[s] = v;
     }

@@ -12,6 +12,7 @@
 // With the wet-node wall scheme the boundary nodes also write their force (16 B) to the solid row,
 // which the next pull reads back; that traffic is confined to two rows of the lattice.
 #include <algorithm>
+#include <type_traits>
 
 #include "lbm_device.h"
 #include "lbm_internal.h"
@@ -21,8 +22,8 @@ namespace lbm {
 // ------------------------------------------------------------------------------------------------
 // Time step
 // ------------------------------------------------------------------------------------------------
-// GEO: the geometry variant compiled in (GEO_ROWS, GEO_WET, GEO_MASK), chosen at launch.
-template <int TX, int TY, bool FUSED, int GEO>
+// GEO, EOS: the geometry and equation-of-state variants compiled in, chosen at launch.
+template <int TX, int TY, bool FUSED, int GEO, int EOS>
 __global__ __launch_bounds__(TX* TY) void k_step(KParams P, const double* __restrict__ gin,
                                                  double* __restrict__ gout,
                                                  const double* __restrict__ psi_g,
@@ -31,15 +32,15 @@ __global__ __launch_bounds__(TX* TY) void k_step(KParams P, const double* __rest
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
     const int tile = xcd_tile(blockIdx.x, ntx * nty);
-    step_tile<TX, TY, FUSED, GEO>(P, gin, gout, psi_g, gw, (tile % ntx) * TX,
-                                  P.y_lo + (tile / ntx) * TY, sp);
+    step_tile<TX, TY, FUSED, GEO, EOS>(P, gin, gout, psi_g, gw, (tile % ntx) * TX,
+                                       P.y_lo + (tile / ntx) * TY, sp);
 }
 
 // Overlapped tiles: one 64-lane wave spans TXI = 62 interior columns plus the halo column on each
 // side, and the workgroup has TYI interior rows plus a halo row above and below. Every thread
 // pulls exactly one node and evaluates its psi (one memory round trip per tile, all loads
 // coalesced rows); the interior threads then collide and store.
-template <int TYI, int GEO>
+template <int TYI, int GEO, int EOS>
 __global__ __launch_bounds__(64 * (TYI + 2)) void k_step_ov(KParams P,
                                                             const double* __restrict__ gin,
                                                             double* __restrict__ gout,
@@ -62,7 +63,7 @@ __global__ __launch_bounds__(64 * (TYI + 2)) void k_step_ov(KParams P,
     if (has) {
         pull9<GEO>(P, gin, sx, sy, f);
         rho = sum9(f);
-        psi_c = psi_of_rho(P, rho);
+        psi_c = psi_of_rho<EOS>(P, rho);
     }
     sp[r * LW + l] = psi_c;
     __syncthreads();
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(64 * (TYI + 2)) void k_step_ov(KParams P,
 }
 
 // Two steps per launch over TX x TY output tiles (step2_tile).
-template <int TX, int TY, int GEO>
+template <int TX, int TY, int GEO, int EOS>
 __global__ __launch_bounds__(TX* TY) void k_step2(KParams P, const double* __restrict__ gin,
                                                   double* __restrict__ gout,
                                                   const double* __restrict__ gw) {
@@ -91,7 +92,8 @@ __global__ __launch_bounds__(TX* TY) void k_step2(KParams P, const double* __res
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
     const int tile = xcd_tile(blockIdx.x, ntx * nty);
-    step2_tile<TX, TY, GEO>(P, gin, gout, gw, (tile % ntx) * TX, P.y_lo + (tile / ntx) * TY, lds);
+    step2_tile<TX, TY, GEO, EOS>(P, gin, gout, gw, (tile % ntx) * TX, P.y_lo + (tile / ntx) * TY,
+                                 lds);
 }
 
 // psi pass of the two-pass schedule; also writes the mirrored ghost rows.
@@ -294,35 +296,46 @@ static dim3 node_grid(const KParams& P) {
     return dim3((P.nx + 63) / 64, (P.y_hi - P.y_lo + 4) / 4);
 }
 
+// Calls f(geo, eos) with the geometry and equation of state of P as compile-time constants.
+template <class F>
+static hipError_t dispatch(const KParams& P, F&& f) {
+    auto with_eos = [&](auto geo) {
+        if (P.eos == 0) return f(geo, std::integral_constant<int, EOS_CS>{});
+        return f(geo, std::integral_constant<int, EOS_PW>{});
+    };
+    if (P.mask) return with_eos(std::integral_constant<int, GEO_MASK>{});
+    if (P.wet) return with_eos(std::integral_constant<int, GEO_WET>{});
+    return with_eos(std::integral_constant<int, GEO_ROWS>{});
+}
+
 template <int TX, int TY, bool FUSED>
 static hipError_t launch_step_t(const KParams& P, const double* gin, double* gout,
                                 const double* psi, const double* gw, hipStream_t s) {
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
-    if (P.mask)
-        hipLaunchKernelGGL((k_step<TX, TY, FUSED, GEO_MASK>), dim3(ntx * nty), dim3(TX * TY), 0, s,
-                           P, gin, gout, psi, gw);
-    else if (P.wet)
-        hipLaunchKernelGGL((k_step<TX, TY, FUSED, GEO_WET>), dim3(ntx * nty), dim3(TX * TY), 0, s,
-                           P, gin, gout, psi, gw);
-    else
-        hipLaunchKernelGGL((k_step<TX, TY, FUSED, GEO_ROWS>), dim3(ntx * nty), dim3(TX * TY), 0, s,
-                           P, gin, gout, psi, gw);
-    return hipGetLastError();
+    return dispatch(P, [&](auto geo, auto eos) {
+        hipLaunchKernelGGL((k_step<TX, TY, FUSED, decltype(geo)::value, decltype(eos)::value>),
+                           dim3(ntx * nty), dim3(TX * TY), 0, s, P, gin, gout, psi, gw);
+        return hipGetLastError();
+    });
 }
 
+// The overlapped tiles and two steps per launch have no solid-mask variant (the API rejects
+// those schedules for a mask).
 template <int TYI>
 static hipError_t launch_step_ov(const KParams& P, const double* gin, double* gout,
                                  const double* gw, hipStream_t s) {
     const int ntx = (P.nx + 61) / 62;
     const int nty = (P.y_hi - P.y_lo + TYI) / TYI;
-    if (P.wet)
-        hipLaunchKernelGGL((k_step_ov<TYI, GEO_WET>), dim3(ntx * nty), dim3(64 * (TYI + 2)), 0, s,
-                           P, gin, gout, gw);
-    else
-        hipLaunchKernelGGL((k_step_ov<TYI, GEO_ROWS>), dim3(ntx * nty), dim3(64 * (TYI + 2)), 0, s,
-                           P, gin, gout, gw);
-    return hipGetLastError();
+    return dispatch(P, [&](auto geo, auto eos) {
+        if constexpr (decltype(geo)::value == GEO_MASK) {
+            return hipErrorInvalidValue;
+        } else {
+            hipLaunchKernelGGL((k_step_ov<TYI, decltype(geo)::value, decltype(eos)::value>),
+                               dim3(ntx * nty), dim3(64 * (TYI + 2)), 0, s, P, gin, gout, gw);
+            return hipGetLastError();
+        }
+    });
 }
 
 template <int TX, int TY>
@@ -330,13 +343,15 @@ static hipError_t launch_step2_t(const KParams& P, const double* gin, double* go
                                  const double* gw, hipStream_t s) {
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
-    if (P.wet)
-        hipLaunchKernelGGL((k_step2<TX, TY, GEO_WET>), dim3(ntx * nty), dim3(TX * TY), 0, s, P,
-                           gin, gout, gw);
-    else
-        hipLaunchKernelGGL((k_step2<TX, TY, GEO_ROWS>), dim3(ntx * nty), dim3(TX * TY), 0, s, P,
-                           gin, gout, gw);
-    return hipGetLastError();
+    return dispatch(P, [&](auto geo, auto eos) {
+        if constexpr (decltype(geo)::value == GEO_MASK) {
+            return hipErrorInvalidValue;
+        } else {
+            hipLaunchKernelGGL((k_step2<TX, TY, decltype(geo)::value, decltype(eos)::value>),
+                               dim3(ntx * nty), dim3(TX * TY), 0, s, P, gin, gout, gw);
+            return hipGetLastError();
+        }
+    });
 }
 
 // Two steps in one launch; tile2 selects the output tile: 0 64x8, 1 64x4, 2 128x4, 3 64x16.
