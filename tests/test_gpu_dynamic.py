@@ -17,7 +17,8 @@ pytestmark = pytest.mark.gpu
 WINDOW = (0.2, 1.5)
 
 
-@pytest.mark.parametrize("schedule,every", [("two_step", 100), ("fused", 75), ("two_pass", 50)])
+@pytest.mark.parametrize("schedule,every", [("two_step", 100), ("two_step", 75), ("fused", 75),
+                                            ("two_pass", 50)])
 def test_contact_line_series_parity(orc, gpu, schedule, every):
     import torch
     c = synth.spreading_setup(-0.1)
