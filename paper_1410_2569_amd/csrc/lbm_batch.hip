@@ -48,7 +48,7 @@ __global__ __launch_bounds__(TX* TY) void k_batch_step2(const InstDesc* __restri
     const InstDesc* D = inst + tile_inst[t];
     int x0, y0;
     batch_tile_origin(D, t, TX, TY, x0, y0);
-    step2_tile<TX, TY, GEO, EOS>(D->P, D->g[cur], D->g[cur ^ 1], D->gw, x0, y0, lds);
+    step2_tile_any<TX, TY, GEO, EOS>(D->P, D->g[cur], D->g[cur ^ 1], D->gw, x0, y0, lds);
 }
 
 // Grid-wide barrier number `target / gridDim.x`. Returns false when the run was aborted.

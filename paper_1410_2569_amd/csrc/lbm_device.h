@@ -511,6 +511,37 @@ __device__ __forceinline__ void pull9_lds(const KParams& P, const double* g1, in
     }
 }
 
+// Pull of a node whose neighbours are all fluid nodes of the same lattice, reached without the
+// periodic wrap: the plain streaming of Eq. (5), the same loads as pull9 makes there.
+__device__ __forceinline__ void pull9_in(const KParams& P, const double* __restrict__ g, int x,
+                                         int y, double f[9]) {
+    const long long pl = P.plane;
+    const unsigned r0 = (unsigned)y * P.pitch + x, rm = r0 - P.pitch, rp = r0 + P.pitch;
+    f[0] = g[r0];
+    f[1] = (g + 1 * pl)[r0 - 1];
+    f[3] = (g + 3 * pl)[r0 + 1];
+    f[2] = (g + 2 * pl)[rm];
+    f[5] = (g + 5 * pl)[rm - 1];
+    f[6] = (g + 6 * pl)[rm + 1];
+    f[4] = (g + 4 * pl)[rp];
+    f[7] = (g + 7 * pl)[rp + 1];
+    f[8] = (g + 8 * pl)[rp - 1];
+}
+
+// pull9_lds for a node away from the wall rows.
+__device__ __forceinline__ void pull9_lds_in(const double* g1, int plane, int W, int l,
+                                             double f[9]) {
+    f[0] = g1[l];
+    f[1] = g1[1 * plane + l - 1];
+    f[3] = g1[3 * plane + l + 1];
+    f[2] = g1[2 * plane + l - W];
+    f[5] = g1[5 * plane + l - W - 1];
+    f[6] = g1[6 * plane + l - W + 1];
+    f[4] = g1[4 * plane + l + W];
+    f[7] = g1[7 * plane + l + W + 1];
+    f[8] = g1[8 * plane + l + W - 1];
+}
+
 template <int TX, int TY>
 struct Step2Lds {
     static constexpr int W3 = TX + 6, H3 = TY + 6, W2 = TX + 4, H2 = TY + 4, W1 = TX + 2,
@@ -520,7 +551,10 @@ struct Step2Lds {
     double ps2[W1 * H1];
 };
 
-template <int TX, int TY, int GEO, int EOS = EOS_ANY>
+// IN: the tile is interior (step2_interior): every pull of R3 stays inside the lattice, clear of
+// the wall rows and the periodic seam, so no node needs a wall, ghost or wrap rule. Both
+// variants give the same bits on such a tile.
+template <int TX, int TY, int GEO, int EOS = EOS_ANY, bool IN = false>
 __device__ __forceinline__ void step2_tile(const KParams& P, const double* __restrict__ gin,
                                            double* __restrict__ gout,
                                            const double* __restrict__ gw, int x0, int y0,
@@ -546,6 +580,13 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
         rk[r] = 1.0;
         if (s >= PL) continue;
         const int lx = s % W2, ly = s / W2;
+        if constexpr (IN) {
+            pull9_in(P, gin, x0 - 2 + lx, y0 - 2 + ly, fk[r]);
+            rk[r] = sum9(fk[r]);
+            ps1[(ly + 1) * W3 + lx + 1] = psi_of_rho<EOS>(P, rk[r]);
+            ok[r] = true;
+            continue;
+        }
         double ps = 0.0;
         int gy = y0 - 2 + ly;
         bool fluid;
@@ -568,7 +609,13 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
         else if (h < 2 * W3) { lx = h - W3; ly = H3 - 1; }
         else if (h < 2 * W3 + H2) { lx = 0; ly = h - 2 * W3 + 1; }
         else { lx = W3 - 1; ly = h - 2 * W3 - H2 + 1; }
-        ps1[ly * W3 + lx] = psi_at<GEO, EOS>(P, gin, x0 - 3 + lx, y0 - 3 + ly);
+        if constexpr (IN) {
+            double f[9];
+            pull9_in(P, gin, x0 - 3 + lx, y0 - 3 + ly, f);
+            ps1[ly * W3 + lx] = psi_of_rho<EOS>(P, sum9(f));
+        } else {
+            ps1[ly * W3 + lx] = psi_at<GEO, EOS>(P, gin, x0 - 3 + lx, y0 - 3 + ly);
+        }
     }
     __syncthreads();
 
@@ -578,18 +625,20 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
         if (!ok[r]) continue;
         const int s = threadIdx.x + r * NT;
         const int lx = s % W2, ly = s / W2;
-        const int gx = wrapx(x0 - 2 + lx, P.nx);
-        const int gy = P.walls ? y0 - 2 + ly : wrapx(y0 - 2 + ly, P.ny);
         const double* c = ps1 + (ly + 1) * W3 + lx + 1;
         double sx, sy;
         cohesion_sum(c[-W3 - 1], c[-W3], c[-W3 + 1], c[-1], c[1], c[W3 - 1], c[W3], c[W3 + 1],
                      sx, sy);
         double Ax = 0.0, Ay = 0.0;
-        if (P.walls && (gy == 1 || gy == P.ny - 2)) adhesion_sum(P, gw, gx, gy, Ax, Ay);
-        // a boundary node's force feeds the reconstruction of step n+2, which only nodes of R1
-        // perform; those have their solid-row slot inside R2
-        if (GEO == GEO_WET && P.wet && ly >= 1 && ly <= H2 - 2)
-            store_wall_force<GEO>(P, g1, s, PL, W2, gy, rk[r], c[0], sx, sy, Ax, Ay);
+        if constexpr (!IN) {
+            const int gx = wrapx(x0 - 2 + lx, P.nx);
+            const int gy = P.walls ? y0 - 2 + ly : wrapx(y0 - 2 + ly, P.ny);
+            if (P.walls && (gy == 1 || gy == P.ny - 2)) adhesion_sum(P, gw, gx, gy, Ax, Ay);
+            // a boundary node's force feeds the reconstruction of step n+2, which only nodes of
+            // R1 perform; those have their solid-row slot inside R2
+            if (GEO == GEO_WET && P.wet && ly >= 1 && ly <= H2 - 2)
+                store_wall_force<GEO>(P, g1, s, PL, W2, gy, rk[r], c[0], sx, sy, Ax, Ay);
+        }
         collide(P, fk[r], rk[r], c[0], sx, sy, Ax, Ay);
 #pragma unroll
         for (int a = 0; a < 9; ++a) g1[a * PL + s] = fk[r][a];
@@ -599,6 +648,12 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
     // C: psi of step n+2 on R1 (solid rows take the mirrored fluid row, or 0)
     for (int s = threadIdx.x; s < W1 * H1; s += NT) {
         const int lx = s % W1, ly = s / W1;
+        if constexpr (IN) {
+            double f[9];
+            pull9_lds_in(g1, PL, W2, (ly + 1) * W2 + lx + 1, f);
+            ps2[s] = psi_of_rho<EOS>(P, sum9(f));
+            continue;
+        }
         const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
         int sx, sy;
         double v = 0.0;
@@ -616,18 +671,21 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
     // D: step n+2 on the tile
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int x = x0 + tx, y = y0 + ty;
-    if (x < P.nx && y <= P.y_hi) {
+    if (IN || (x < P.nx && y <= P.y_hi)) {
         double f[9];
-        pull9_lds<GEO>(P, g1, PL, W2, (ty + 2) * W2 + tx + 2, y, f);
+        if constexpr (IN) pull9_lds_in(g1, PL, W2, (ty + 2) * W2 + tx + 2, f);
+        else pull9_lds<GEO>(P, g1, PL, W2, (ty + 2) * W2 + tx + 2, y, f);
         const double rho = sum9(f);
         const double* c = ps2 + (ty + 1) * W1 + tx + 1;
         double sx, sy;
         cohesion_sum(c[-W1 - 1], c[-W1], c[-W1 + 1], c[-1], c[1], c[W1 - 1], c[W1], c[W1 + 1],
                      sx, sy);
         double Ax = 0.0, Ay = 0.0;
-        if (P.walls && (y == 1 || y == P.ny - 2)) adhesion_sum(P, gw, x, y, Ax, Ay);
-        store_wall_force<GEO>(P, gout, (long long)y * P.pitch + x, P.plane, P.pitch, y, rho, c[0],
-                              sx, sy, Ax, Ay);
+        if constexpr (!IN) {
+            if (P.walls && (y == 1 || y == P.ny - 2)) adhesion_sum(P, gw, x, y, Ax, Ay);
+            store_wall_force<GEO>(P, gout, (long long)y * P.pitch + x, P.plane, P.pitch, y, rho,
+                                  c[0], sx, sy, Ax, Ay);
+        }
         collide(P, f, rho, c[0], sx, sy, Ax, Ay);
         const unsigned i = (unsigned)y * P.pitch + x;
 #pragma unroll
@@ -635,6 +693,28 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
     }
 }
 
+
+// True when the pulls of every node of the tile's R3 (see step2_tile) stay inside the lattice
+// without the periodic wrap and touch no wall rule: R3 and its pull neighbours lie in columns
+// [0, nx) and, with walls, in rows [1, ny-2] (only nodes of rows 1 and ny-2 have solid
+// neighbours), without walls in rows [0, ny).
+__device__ __forceinline__ bool step2_interior(const KParams& P, int TX, int TY, int x0, int y0) {
+    if (x0 - 4 < 0 || x0 + TX + 3 > P.nx - 1) return false;
+    if (P.walls) return y0 - 3 >= 2 && y0 + TY + 2 <= P.ny - 3;
+    return y0 - 4 >= 0 && y0 + TY + 3 <= P.ny - 1;
+}
+
+// step2_tile with the interior variant where it applies (a uniform branch per workgroup).
+template <int TX, int TY, int GEO, int EOS>
+__device__ __forceinline__ void step2_tile_any(const KParams& P, const double* __restrict__ gin,
+                                               double* __restrict__ gout,
+                                               const double* __restrict__ gw, int x0, int y0,
+                                               Step2Lds<TX, TY>& L) {
+    if (step2_interior(P, TX, TY, x0, y0))
+        step2_tile<TX, TY, GEO, EOS, true>(P, gin, gout, gw, x0, y0, L);
+    else
+        step2_tile<TX, TY, GEO, EOS, false>(P, gin, gout, gw, x0, y0, L);
+}
 
 }  // namespace lbm
 

@@ -92,8 +92,8 @@ __global__ __launch_bounds__(TX* TY) void k_step2(KParams P, const double* __res
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
     const int tile = xcd_tile(blockIdx.x, ntx * nty);
-    step2_tile<TX, TY, GEO, EOS>(P, gin, gout, gw, (tile % ntx) * TX, P.y_lo + (tile / ntx) * TY,
-                                 lds);
+    step2_tile_any<TX, TY, GEO, EOS>(P, gin, gout, gw, (tile % ntx) * TX,
+                                     P.y_lo + (tile / ntx) * TY, lds);
 }
 
 // psi pass of the two-pass schedule; also writes the mirrored ghost rows.

@@ -159,6 +159,32 @@ def test_tile_shapes_and_schedules_bitwise(orc, gpu):
     assert np.array_equal(sim.f(), ref)
 
 
+@pytest.mark.parametrize("walls", [0, 1, 2])
+def test_interior_tiles_bitwise(orc, gpu, walls):
+    """Two-step tiles away from the walls and the periodic seam run a variant without wall, ghost
+    or wrap rules; on lattices where most tiles are such, every two-step tile shape gives the
+    bits of the single-step schedule, and the oracle's values."""
+    nx, ny, steps = 211, 61, 90
+    p = synth.base_params(nx=nx, ny=ny, walls=walls, wall_force="modpsi")
+    q = orc.make_params(p)
+    centre = [(100.0, 0.5 if walls else 30.0)]
+    rho0 = synth.droplet_rho(nx, ny, q.rho_l, q.rho_v, centre, [22.0], jitter=1e-2, seed=walls,
+                             walls=bool(walls))
+    pg = dict(p, rho_l=q.rho_l, rho_v=q.rho_v)
+    gw = synth.gw_smooth(nx, 0.1, 0.05, seed=2) if walls else None
+    sim = gpu.Sim(pg, gw, rho0)
+    sim.set_schedule("fused")
+    sim.step(steps)
+    ref = sim.f()
+    f = orc.run(q, gw, orc.init_rest(q, rho0), steps)
+    assert_f_close(q, ref, f, what=f"walls={walls}")
+    for t in range(4):
+        sim = gpu.Sim(pg, gw, rho0)
+        sim.set_schedule(32 + t)
+        sim.step(steps)
+        assert np.array_equal(sim.f(), ref), f"walls={walls}: two-step tile {t}"
+
+
 @pytest.mark.parametrize("nx,ny,walls", [(3, 4, 1), (5, 6, 1), (7, 3, 0), (61, 9, 1), (63, 10, 0),
                                          (125, 17, 1)])
 def test_tiny_and_ragged_lattices_all_tiles(orc, gpu, nx, ny, walls):
