@@ -147,8 +147,8 @@ int lbm_create(const lbm_params *p, const double *gw_host, const double *rho0_ho
  * rough surfaces of Sec. III.B). solid_host: [ny][nx] bytes, nonzero = solid node; gw_host:
  * [ny][nx] G_w of every solid node (values on fluid nodes are ignored); rho0_host: [ny][nx]
  * initial density (solid nodes ignored, fluid nodes > 0). All copied. x and y are periodic: a
- * closed channel lists its wall rows in the mask. Such a context runs the fused schedule (tile
- * shapes 0-3) or the two-pass schedule; the ensemble and adjoint entry points reject it.
+ * closed channel lists its wall rows in the mask. Such a context runs every schedule but the
+ * overlapped fused tiles (lbm_set_schedule); the adjoint entry points reject it.
  * LBM_E_INVAL for any other walls value, a null array or a mask without fluid nodes. */
 int lbm_create_masked(const lbm_params *p, const uint8_t *solid_host, const double *gw_host,
                       const double *rho0_host, void *d_ws, size_t ws_bytes, void *stream,
@@ -208,8 +208,8 @@ int lbm_set_gw(lbm_ctx *c, const double *gw_host);
  *   16+t   fused with tile shape t (0..7: 64x4, 64x8, 64x16, 128x4, and the overlapped
  *          62-column tiles with 4, 6, 8, 14 rows);
  *   32+t   two steps per launch with output tile t (0..3: 64x8, 64x4, 128x4, 64x16).
- * All schedules give bit-identical populations. A solid mask accepts 0, 1 and 16..19 (it
- * defaults to 16+1). */
+ * All schedules give bit-identical populations. A solid mask accepts every schedule but
+ * 20..23 (LBM_E_INVAL). */
 int lbm_set_schedule(lbm_ctx *c, int32_t schedule);
 
 /* ---- Gradients of a wetting objective with respect to the wall wettability G_w ------------- */
@@ -269,7 +269,7 @@ int lbm_batch_create(const lbm_params *p, int32_t count, const double *const *gw
                      size_t bytes, void *hip_stream, lbm_batch **out);
 /* An ensemble of solid-mask lattices (every p[i].walls = LBM_WALLS_MASK; see lbm_create_masked):
  * solid_host[count] ([ny][nx] bytes each), gw_host[count] ([ny][nx] G_w per node each),
- * rho0_host[count]; all copied. Schedules 0 and 1 only (LBM_E_INVAL for schedule 2). */
+ * rho0_host[count]; all copied. Every schedule of lbm_tune. */
 int lbm_batch_create_masked(const lbm_params *p, int32_t count, const uint8_t *const *solid_host,
                             const double *const *gw_host, const double *const *rho0_host,
                             const lbm_tune *tune, void *d_ws, size_t bytes, void *hip_stream,

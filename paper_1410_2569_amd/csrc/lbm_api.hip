@@ -464,9 +464,6 @@ static int create_impl(const lbm_params* p, const uint8_t* solid, const double* 
         if (e != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create: G_w copy", e); }
     }
     if (solid) {
-        // the fused single step with the tile shapes that stage the halo is the masked schedule
-        c->schedule = 0;
-        c->tile = 1;
         std::vector<unsigned short> lk = mask_links(p, solid, L.pitch);
         unsigned short* d_links = (unsigned short*)(c->ws + L.off_links);
         e = hipMemcpyAsync(d_links, lk.data(), lk.size() * sizeof(unsigned short),
@@ -508,9 +505,10 @@ int lbm_create_masked(const lbm_params* p, const uint8_t* solid_host, const doub
 int lbm_set_schedule(lbm_ctx* c, int32_t schedule) {
     if (!c) return LBM_E_INVAL;
     // 0 fused, 1 two-pass, 2 two steps per launch; 16 + t: fused with tile shape t;
-    // 32 + t: two steps per launch with output tile t. A solid mask: 0, 1 and tiles 0-3.
-    if (c->kp.mask && (schedule == 2 || schedule >= 20))
-        return fail(c, LBM_E_INVAL, "a solid mask runs the fused (tiles 0-3) or two-pass schedule");
+    // 32 + t: two steps per launch with output tile t. A solid mask takes every schedule but
+    // the overlapped fused tiles (16 + 4..7).
+    if (c->kp.mask && schedule >= 20 && schedule < 32)
+        return fail(c, LBM_E_INVAL, "a solid mask has no overlapped-tile schedule (tiles 4-7)");
     if (schedule >= 0 && schedule <= 2) { c->schedule = schedule; return LBM_OK; }
     if (schedule >= 16 && schedule < 16 + lbm::n_tiles()) {
         c->schedule = 0;
@@ -1010,7 +1008,6 @@ static int batch_create_impl(const lbm_params* p, int32_t count,
         if (!rho0_host[i] || (p[i].walls && !gw_host[i])) return LBM_E_INVAL;
     }
     lbm_tune tn = tune ? *tune : lbm_tune{1, 0, 0, 0};
-    if (solid_host && tn.schedule == 2) return LBM_E_INVAL;  // two steps per launch: flat walls
     BatchLayout B;
     if (!batch_layout(p, count, tn.tile, &B)) return LBM_E_INVAL;
     if (bytes < B.total) return LBM_E_SIZE;

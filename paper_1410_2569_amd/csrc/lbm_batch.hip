@@ -40,10 +40,9 @@ __global__ __launch_bounds__(TX* TY) void k_batch_step(const InstDesc* __restric
 
 // Two steps per launch over the work-list (the tiles are the output tiles of step2_tile).
 template <int TX, int TY, int GEO, int EOS>
-__global__ __launch_bounds__(TX* TY) void k_batch_step2(const InstDesc* __restrict__ inst,
-                                                        const int* __restrict__ tile_inst,
-                                                        int ntiles, int cur) {
-    __shared__ Step2Lds<TX, TY> lds;
+__global__ __launch_bounds__(step2_threads(TX, TY, GEO)) void k_batch_step2(
+    const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, int ntiles, int cur) {
+    __shared__ Step2Lds<TX, TY, GEO == GEO_MASK> lds;
     const int t = xcd_tile(blockIdx.x, ntiles);
     const InstDesc* D = inst + tile_inst[t];
     int x0, y0;
@@ -188,13 +187,10 @@ template <int TX, int TY>
 static hipError_t launch_batch2_t(int geo, int eos, const InstDesc* inst, const int* tile_inst,
                                   int ntiles, int cur, hipStream_t s) {
     return dispatch(geo, eos, [&](auto g, auto e) {
-        if constexpr (decltype(g)::value == GEO_MASK) {
-            return hipErrorInvalidValue;  // two steps per launch: flat walls only
-        } else {
-            hipLaunchKernelGGL((k_batch_step2<TX, TY, decltype(g)::value, decltype(e)::value>),
-                               dim3(ntiles), dim3(TX * TY), 0, s, inst, tile_inst, ntiles, cur);
-            return hipGetLastError();
-        }
+        constexpr int G = decltype(g)::value;
+        hipLaunchKernelGGL((k_batch_step2<TX, TY, G, decltype(e)::value>), dim3(ntiles),
+                           dim3(step2_threads(TX, TY, G)), 0, s, inst, tile_inst, ntiles, cur);
+        return hipGetLastError();
     });
 }
 

@@ -542,27 +542,55 @@ __device__ __forceinline__ void pull9_lds_in(const double* g1, int plane, int W,
     f[8] = g1[8 * plane + l + W - 1];
 }
 
-template <int TX, int TY>
+// pull9_lds with a solid mask: lk = links of the node (see pull9_mask).
+__device__ __forceinline__ void pull9_lds_mask(const double* g1, int plane, int W, int l,
+                                               unsigned lk, double f[9]) {
+    f[0] = g1[l];
+    f[1] = (lk & 2u) ? g1[3 * plane + l] : g1[1 * plane + l - 1];
+    f[2] = (lk & 4u) ? g1[4 * plane + l] : g1[2 * plane + l - W];
+    f[3] = (lk & 8u) ? g1[1 * plane + l] : g1[3 * plane + l + 1];
+    f[4] = (lk & 16u) ? g1[2 * plane + l] : g1[4 * plane + l + W];
+    f[5] = (lk & 32u) ? g1[7 * plane + l] : g1[5 * plane + l - W - 1];
+    f[6] = (lk & 64u) ? g1[8 * plane + l] : g1[6 * plane + l - W + 1];
+    f[7] = (lk & 128u) ? g1[5 * plane + l] : g1[7 * plane + l + W + 1];
+    f[8] = (lk & 256u) ? g1[6 * plane + l] : g1[8 * plane + l + W - 1];
+}
+
+// Threads of a two-step workgroup. The LDS of a tile allows two workgroups per CU; the 64 x 8
+// tile without a solid mask runs 768 threads (12 waves, 6 per SIMD with two workgroups) so that
+// more waves hide each other's latencies and its R2 (816 nodes) takes one pass on most of them
+// (832 or more threads leave room for one workgroup per CU only, and the mask variant needs too
+// many registers for 6 waves per SIMD); the other tiles run one thread per output node.
+__host__ __device__ constexpr int step2_threads(int TX, int TY, int GEO) {
+    return TX == 64 && TY == 8 && GEO != GEO_MASK ? 768 : TX * TY;
+}
+
+// LDS of step2_tile; MK: a solid mask, whose link words of R2 are kept too.
+template <int TX, int TY, bool MK = false>
 struct Step2Lds {
     static constexpr int W3 = TX + 6, H3 = TY + 6, W2 = TX + 4, H2 = TY + 4, W1 = TX + 2,
                          H1 = TY + 2, PL = W2 * H2;
     double g1[9 * PL];
     double ps1[W3 * H3];
     double ps2[W1 * H1];
+    unsigned short lk[MK ? PL : 1];
 };
 
 // IN: the tile is interior (step2_interior): every pull of R3 stays inside the lattice, clear of
-// the wall rows and the periodic seam, so no node needs a wall, ghost or wrap rule. Both
-// variants give the same bits on such a tile.
+// the wall rows, solid nodes and the periodic seam, so no node needs a wall, ghost, mask or wrap
+// rule. Both variants give the same bits on such a tile. With a solid mask (GEO_MASK) the lattice
+// is periodic in x and y, solid nodes hold psi = 0 and are not updated, links select the
+// bounce-back of each population and the adhesion sums G_w over the solid neighbours.
 template <int TX, int TY, int GEO, int EOS = EOS_ANY, bool IN = false>
 __device__ __forceinline__ void step2_tile(const KParams& P, const double* __restrict__ gin,
                                            double* __restrict__ gout,
                                            const double* __restrict__ gw, int x0, int y0,
-                                           Step2Lds<TX, TY>& L) {
-    constexpr int NT = TX * TY;
+                                           Step2Lds<TX, TY, GEO == GEO_MASK>& L) {
+    constexpr bool MK = GEO == GEO_MASK;
+    constexpr int NT = step2_threads(TX, TY, GEO);
+    static_assert(NT >= TX * TY, "one thread per output node at least");
     constexpr int W3 = TX + 6, H3 = TY + 6, W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
     constexpr int PL = W2 * H2;
-    static_assert(GEO != GEO_MASK, "two steps per launch: flat walls only");
     double* g1 = L.g1;
     double* ps1 = L.ps1;
     double* ps2 = L.ps2;
@@ -585,6 +613,20 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
             rk[r] = sum9(fk[r]);
             ps1[(ly + 1) * W3 + lx + 1] = psi_of_rho<EOS>(P, rk[r]);
             ok[r] = true;
+            continue;
+        }
+        if constexpr (MK) {
+            const int gx = wrapx(x0 - 2 + lx, P.nx), gy = wrapx(y0 - 2 + ly, P.ny);
+            const unsigned lk = P.links[(unsigned)gy * P.pitch + gx];
+            L.lk[s] = (unsigned short)lk;
+            double ps = 0.0;  // solid node
+            if (!(lk & 1u)) {
+                pull9_mask(P, gin, gx, gy, lk, fk[r]);
+                rk[r] = sum9(fk[r]);
+                ps = psi_of_rho<EOS>(P, rk[r]);
+                ok[r] = true;
+            }
+            ps1[(ly + 1) * W3 + lx + 1] = ps;
             continue;
         }
         double ps = 0.0;
@@ -630,7 +672,9 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
         cohesion_sum(c[-W3 - 1], c[-W3], c[-W3 + 1], c[-1], c[1], c[W3 - 1], c[W3], c[W3 + 1],
                      sx, sy);
         double Ax = 0.0, Ay = 0.0;
-        if constexpr (!IN) {
+        if constexpr (MK && !IN) {
+            adhesion_mask(P, wrapx(x0 - 2 + lx, P.nx), wrapx(y0 - 2 + ly, P.ny), L.lk[s], Ax, Ay);
+        } else if constexpr (!IN) {
             const int gx = wrapx(x0 - 2 + lx, P.nx);
             const int gy = P.walls ? y0 - 2 + ly : wrapx(y0 - 2 + ly, P.ny);
             if (P.walls && (gy == 1 || gy == P.ny - 2)) adhesion_sum(P, gw, gx, gy, Ax, Ay);
@@ -654,6 +698,18 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
             ps2[s] = psi_of_rho<EOS>(P, sum9(f));
             continue;
         }
+        if constexpr (MK) {
+            const int l = (ly + 1) * W2 + lx + 1;
+            const unsigned lk = L.lk[l];
+            double v = 0.0;  // solid node
+            if (!(lk & 1u)) {
+                double f[9];
+                pull9_lds_mask(g1, PL, W2, l, lk, f);
+                v = psi_of_rho<EOS>(P, sum9(f));
+            }
+            ps2[s] = v;
+            continue;
+        }
         const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
         int sx, sy;
         double v = 0.0;
@@ -668,20 +724,27 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
     }
     __syncthreads();
 
-    // D: step n+2 on the tile
+    // D: step n+2 on the tile (threads beyond the tile's nodes have no part in it)
+    const bool own = NT == TX * TY || (int)threadIdx.x < TX * TY;
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int x = x0 + tx, y = y0 + ty;
-    if (IN || (x < P.nx && y <= P.y_hi)) {
+    const int l = (ty + 2) * W2 + tx + 2;
+    unsigned lk = 0;  // links of the node (solid mask)
+    if constexpr (MK && !IN) lk = own ? L.lk[l] : 1u;
+    if (own && (IN || (x < P.nx && y <= P.y_hi)) && !(lk & 1u)) {
         double f[9];
-        if constexpr (IN) pull9_lds_in(g1, PL, W2, (ty + 2) * W2 + tx + 2, f);
-        else pull9_lds<GEO>(P, g1, PL, W2, (ty + 2) * W2 + tx + 2, y, f);
+        if constexpr (IN) pull9_lds_in(g1, PL, W2, l, f);
+        else if constexpr (MK) pull9_lds_mask(g1, PL, W2, l, lk, f);
+        else pull9_lds<GEO>(P, g1, PL, W2, l, y, f);
         const double rho = sum9(f);
         const double* c = ps2 + (ty + 1) * W1 + tx + 1;
         double sx, sy;
         cohesion_sum(c[-W1 - 1], c[-W1], c[-W1 + 1], c[-1], c[1], c[W1 - 1], c[W1], c[W1 + 1],
                      sx, sy);
         double Ax = 0.0, Ay = 0.0;
-        if constexpr (!IN) {
+        if constexpr (MK && !IN) {
+            adhesion_mask(P, x, y, lk, Ax, Ay);
+        } else if constexpr (!IN) {
             if (P.walls && (y == 1 || y == P.ny - 2)) adhesion_sum(P, gw, x, y, Ax, Ay);
             store_wall_force<GEO>(P, gout, (long long)y * P.pitch + x, P.plane, P.pitch, y, rho,
                                   c[0], sx, sy, Ax, Ay);
@@ -697,11 +760,21 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
 // True when the pulls of every node of the tile's R3 (see step2_tile) stay inside the lattice
 // without the periodic wrap and touch no wall rule: R3 and its pull neighbours lie in columns
 // [0, nx) and, with walls, in rows [1, ny-2] (only nodes of rows 1 and ny-2 have solid
-// neighbours), without walls in rows [0, ny).
-__device__ __forceinline__ bool step2_interior(const KParams& P, int TX, int TY, int x0, int y0) {
+// neighbours), otherwise in rows [0, ny). A solid mask also needs no solid node among them: the
+// whole workgroup checks the link words of the tile grown by 4 rings (a barrier).
+template <int TX, int TY, int GEO>
+__device__ __forceinline__ bool step2_interior(const KParams& P, int x0, int y0) {
     if (x0 - 4 < 0 || x0 + TX + 3 > P.nx - 1) return false;
-    if (P.walls) return y0 - 3 >= 2 && y0 + TY + 2 <= P.ny - 3;
-    return y0 - 4 >= 0 && y0 + TY + 3 <= P.ny - 1;
+    if (GEO != GEO_MASK && P.walls) return y0 - 3 >= 2 && y0 + TY + 2 <= P.ny - 3;
+    if (y0 - 4 < 0 || y0 + TY + 3 > P.ny - 1) return false;
+    if constexpr (GEO == GEO_MASK) {
+        constexpr int W4 = TX + 8, N4 = (TX + 8) * (TY + 8);
+        int solid = 0;
+        for (int s = threadIdx.x; s < N4; s += step2_threads(TX, TY, GEO))
+            solid |= P.links[(unsigned)(y0 - 4 + s / W4) * P.pitch + (x0 - 4 + s % W4)] & 1;
+        return !__syncthreads_or(solid);
+    }
+    return true;
 }
 
 // step2_tile with the interior variant where it applies (a uniform branch per workgroup).
@@ -709,8 +782,8 @@ template <int TX, int TY, int GEO, int EOS>
 __device__ __forceinline__ void step2_tile_any(const KParams& P, const double* __restrict__ gin,
                                                double* __restrict__ gout,
                                                const double* __restrict__ gw, int x0, int y0,
-                                               Step2Lds<TX, TY>& L) {
-    if (step2_interior(P, TX, TY, x0, y0))
+                                               Step2Lds<TX, TY, GEO == GEO_MASK>& L) {
+    if (step2_interior<TX, TY, GEO>(P, x0, y0))
         step2_tile<TX, TY, GEO, EOS, true>(P, gin, gout, gw, x0, y0, L);
     else
         step2_tile<TX, TY, GEO, EOS, false>(P, gin, gout, gw, x0, y0, L);

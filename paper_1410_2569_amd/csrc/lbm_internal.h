@@ -59,8 +59,7 @@ hipError_t launch_loss_seed(const KParams& P, double w_c, double w_w, double yc,
 int batch_tiles(int tile);
 // geo: GEO_ROWS, GEO_WET (some instance uses the wet-node wall) or GEO_MASK (every instance has
 // a solid mask); eos: EOS_CS or EOS_PW when every instance uses it, else EOS_ANY. They select the
-// kernels compiled for that variant. Two steps per launch do not take GEO_MASK
-// (hipErrorInvalidValue).
+// kernels compiled for that variant.
 hipError_t launch_batch_step(int tile, int geo, int eos, const InstDesc* inst,
                              const int* tile_inst, int ntiles, int cur, hipStream_t s);
 hipError_t launch_batch_step2(int tile, int geo, int eos, const InstDesc* inst,

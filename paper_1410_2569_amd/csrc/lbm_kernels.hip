@@ -85,10 +85,10 @@ __global__ __launch_bounds__(64 * (TYI + 2)) void k_step_ov(KParams P,
 
 // Two steps per launch over TX x TY output tiles (step2_tile).
 template <int TX, int TY, int GEO, int EOS>
-__global__ __launch_bounds__(TX* TY) void k_step2(KParams P, const double* __restrict__ gin,
-                                                  double* __restrict__ gout,
-                                                  const double* __restrict__ gw) {
-    __shared__ Step2Lds<TX, TY> lds;
+__global__ __launch_bounds__(step2_threads(TX, TY, GEO)) void k_step2(
+    KParams P, const double* __restrict__ gin, double* __restrict__ gout,
+    const double* __restrict__ gw) {
+    __shared__ Step2Lds<TX, TY, GEO == GEO_MASK> lds;
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
     const int tile = xcd_tile(blockIdx.x, ntx * nty);
@@ -320,8 +320,8 @@ static hipError_t launch_step_t(const KParams& P, const double* gin, double* gou
     });
 }
 
-// The overlapped tiles and two steps per launch have no solid-mask variant (the API rejects
-// those schedules for a mask).
+// The overlapped tiles have no solid-mask variant (the API rejects those schedules for a
+// mask).
 template <int TYI>
 static hipError_t launch_step_ov(const KParams& P, const double* gin, double* gout,
                                  const double* gw, hipStream_t s) {
@@ -344,13 +344,10 @@ static hipError_t launch_step2_t(const KParams& P, const double* gin, double* go
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
     return dispatch(P, [&](auto geo, auto eos) {
-        if constexpr (decltype(geo)::value == GEO_MASK) {
-            return hipErrorInvalidValue;
-        } else {
-            hipLaunchKernelGGL((k_step2<TX, TY, decltype(geo)::value, decltype(eos)::value>),
-                               dim3(ntx * nty), dim3(TX * TY), 0, s, P, gin, gout, gw);
-            return hipGetLastError();
-        }
+        constexpr int G = decltype(geo)::value;
+        hipLaunchKernelGGL((k_step2<TX, TY, G, decltype(eos)::value>), dim3(ntx * nty),
+                           dim3(step2_threads(TX, TY, G)), 0, s, P, gin, gout, gw);
+        return hipGetLastError();
     });
 }
 
