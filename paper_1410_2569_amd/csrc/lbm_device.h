@@ -644,8 +644,14 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
         }
         ps1[(ly + 1) * W3 + lx + 1] = ps;
     }
-    constexpr int NRING = 2 * W3 + 2 * H2;  // the ring of R3 outside R2
-    for (int h = threadIdx.x; h < NRING; h += NT) {
+    // The ring of R3 outside R2 goes to the waves after those with a slot in the last pass of R2,
+    // when they are enough, so that no wave evaluates more than NR psi values.
+    constexpr int NRING = 2 * W3 + 2 * H2;
+    constexpr int LAST = PL - (NR - 1) * NT;  // threads with a slot in the last pass
+    constexpr int RB = (LAST + 63) / 64 * 64;
+    constexpr int R0 = RB + NRING <= NT ? RB : 0;
+    for (int h = (int)threadIdx.x - R0; h < NRING; h += NT) {
+        if (h < 0) continue;
         int lx, ly;  // R3-local coordinates
         if (h < W3) { lx = h; ly = 0; }
         else if (h < 2 * W3) { lx = h - W3; ly = H3 - 1; }
