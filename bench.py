@@ -57,6 +57,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> dict:
+    """A plain device copy of nbytes (above the 256 MB last-level cache), timed with events: the
+    bandwidth the chip delivers to a streaming kernel, beside the 8 TB/s of the data sheet."""
+    import torch
+
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    return {"value": round(gbs, 1), "unit": "GB/s", "bytes_read_and_written": 2 * nbytes,
+            "kernel": "torch copy_"}
+
+
 def cpu_baseline(budget_s: float = 12.0) -> dict:
     """Oracle (plain C, FP64) on the first run of the sweep: as many steps as fit the budget."""
     import numpy as np  # noqa: F401
@@ -771,7 +791,9 @@ def main():
     for p in phys:
         log("bench: run", p)
 
-    tr = traffic_per_launch()
+    # the counters were taken on the default launch configuration only
+    default_cfg = two_step and args.tile2 is None
+    tr = traffic_per_launch() if default_cfg else None
     roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
             "traffic": tr,
@@ -790,6 +812,10 @@ def main():
                                    (args.schedule if args.tile is None
                                     else f"fused/tile{args.tile}"))},
            "hbm_frac_effective": round(BYTES_PER_LU * mlups * 1e6 / (HBM_PEAK_GBS * 1e9), 4),
+           # counter-measured HBM bytes of one launch over its measured duration
+           "hbm_frac_measured": (round(tr / avg_kernel_s / (HBM_PEAK_GBS * 1e9), 4) if tr
+                                 else None),
+           "copy_bandwidth": copy_bandwidth(),
            "nonfinite_runs": bad,
            "roofline": roof}
     if not args.no_extras:

@@ -695,54 +695,62 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
     }
     __syncthreads();
 
-    // C: psi of step n+2 on R1 (solid rows take the mirrored fluid row, or 0)
-    for (int s = threadIdx.x; s < W1 * H1; s += NT) {
-        const int lx = s % W1, ly = s / W1;
-        if constexpr (IN) {
-            double f[9];
-            pull9_lds_in(g1, PL, W2, (ly + 1) * W2 + lx + 1, f);
-            ps2[s] = psi_of_rho<EOS>(P, sum9(f));
-            continue;
-        }
-        if constexpr (MK) {
-            const int l = (ly + 1) * W2 + lx + 1;
-            const unsigned lk = L.lk[l];
-            double v = 0.0;  // solid node
-            if (!(lk & 1u)) {
-                double f[9];
-                pull9_lds_mask(g1, PL, W2, l, lk, f);
-                v = psi_of_rho<EOS>(P, sum9(f));
-            }
-            ps2[s] = v;
-            continue;
-        }
-        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-        int sx, sy;
-        double v = 0.0;
-        if (slot_source(P, gx, gy, sx, sy)) {
-            // the source node in the R2 grid: same column, row sy (mirrored rows stay adjacent)
-            const int ly2 = P.walls ? sy - (y0 - 2) : ly + 1;
-            double f[9];
-            pull9_lds<GEO>(P, g1, PL, W2, ly2 * W2 + lx + 1, sy, f);
-            v = psi_of_rho<EOS>(P, sum9(f));
-        }
-        ps2[s] = v;
-    }
-    __syncthreads();
-
-    // D: step n+2 on the tile (threads beyond the tile's nodes have no part in it)
-    const bool own = NT == TX * TY || (int)threadIdx.x < TX * TY;
+    // C: psi of step n+2 on R1 (solid rows take the mirrored fluid row, or 0). A thread first
+    // evaluates its own node of the tile, whose pulled populations and density stay in registers
+    // for D; the ring of R1 around the tile goes to the threads past the tile's nodes when there
+    // are enough of them, otherwise to the first threads after their own node.
+    constexpr int NTILE = TX * TY;
+    constexpr int NRING1 = 2 * W1 + 2 * TY;  // R1 outside the tile
+    const bool own = NT == NTILE || (int)threadIdx.x < NTILE;
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int x = x0 + tx, y = y0 + ty;
     const int l = (ty + 2) * W2 + tx + 2;
     unsigned lk = 0;  // links of the node (solid mask)
     if constexpr (MK && !IN) lk = own ? L.lk[l] : 1u;
-    if (own && (IN || (x < P.nx && y <= P.y_hi)) && !(lk & 1u)) {
-        double f[9];
+    const bool act = own && (IN || (x < P.nx && y <= P.y_hi)) && !(lk & 1u);
+    // psi at R1 slot (lx, ly), pulled from the populations in LDS
+    auto slot_psi = [&](int lx, int ly) -> double {
+        double g[9];
+        if constexpr (IN) {
+            pull9_lds_in(g1, PL, W2, (ly + 1) * W2 + lx + 1, g);
+        } else if constexpr (MK) {
+            const int ll = (ly + 1) * W2 + lx + 1;
+            const unsigned k = L.lk[ll];
+            if (k & 1u) return 0.0;  // solid node
+            pull9_lds_mask(g1, PL, W2, ll, k, g);
+        } else {
+            int sx, sy;
+            if (!slot_source(P, x0 - 1 + lx, y0 - 1 + ly, sx, sy)) return 0.0;
+            // the source node in the R2 grid: same column, row sy (mirrored rows stay adjacent)
+            const int ly2 = P.walls ? sy - (y0 - 2) : ly + 1;
+            pull9_lds<GEO>(P, g1, PL, W2, ly2 * W2 + lx + 1, sy, g);
+        }
+        return psi_of_rho<EOS>(P, sum9(g));
+    };
+    double f[9], rho = 1.0;
+    if (act) {
         if constexpr (IN) pull9_lds_in(g1, PL, W2, l, f);
         else if constexpr (MK) pull9_lds_mask(g1, PL, W2, l, lk, f);
         else pull9_lds<GEO>(P, g1, PL, W2, l, y, f);
-        const double rho = sum9(f);
+        rho = sum9(f);
+        ps2[(ty + 1) * W1 + tx + 1] = psi_of_rho<EOS>(P, rho);
+    } else if (own) {
+        ps2[(ty + 1) * W1 + tx + 1] = slot_psi(tx + 1, ty + 1);  // outside the lattice, or solid
+    }
+    constexpr int RR0 = NT >= NTILE + NRING1 ? NTILE : 0;
+    for (int h = (int)threadIdx.x - RR0; h < NRING1; h += NT) {
+        if (h < 0) continue;
+        int lx, ly;  // R1-local coordinates
+        if (h < W1) { lx = h; ly = 0; }
+        else if (h < 2 * W1) { lx = h - W1; ly = H1 - 1; }
+        else if (h < 2 * W1 + TY) { lx = 0; ly = h - 2 * W1 + 1; }
+        else { lx = W1 - 1; ly = h - 2 * W1 - TY + 1; }
+        ps2[ly * W1 + lx] = slot_psi(lx, ly);
+    }
+    __syncthreads();
+
+    // D: step n+2 on the tile
+    if (act) {
         const double* c = ps2 + (ty + 1) * W1 + tx + 1;
         double sx, sy;
         cohesion_sum(c[-W1 - 1], c[-W1], c[-W1 + 1], c[-1], c[1], c[W1 - 1], c[W1], c[W1 + 1],
