@@ -430,7 +430,7 @@ def rough_run(args) -> dict:
     args_b = ([c["params"] for c in cs], [c["gw"] for c in cs], [c["rho0"] for c in cs])
     best, best_t = None, math.inf
     for tune in [{"tile": t, "schedule": 0} for t in range(4)] + \
-            [{"tile": t, "schedule": 2} for t in (1, 2)]:
+            [{"tile": t, "schedule": 2} for t in range(4)]:
         b = L.Batch(*args_b, tune=tune, solids=[c["mask"] for c in cs])
         b.step(20)
         t = _timed(lambda: b.step(400), b.stream)

@@ -252,8 +252,8 @@ typedef struct {
     int32_t tile;         /* tile shape 0..3: 64x4, 64x8, 64x16, 128x4 */
     int32_t reserved;     /* must be 0 */
     int32_t waves_per_cu; /* persistent schedule: workgroups per compute unit (0 = occupancy) */
-    int32_t schedule;     /* 0 per-step launches, 1 persistent, 2 two steps per launch (tile 1
-                             or 2 only: 64x8 or 64x16 output tiles) */
+    int32_t schedule;     /* 0 per-step launches, 1 persistent, 2 two steps per launch (output
+                             tiles of the tile shape) */
 } lbm_tune;
 
 typedef struct lbm_batch lbm_batch;
@@ -299,10 +299,10 @@ int64_t lbm_batch_current_step(const lbm_batch *b);
 int lbm_batch_get_tune(const lbm_batch *b, lbm_tune *t, int32_t *grid);
 int lbm_batch_destroy(lbm_batch *b);
 const char *lbm_batch_last_error(const lbm_batch *b);
-/* Autotuner: times every tile shape x schedule (persistent at full and half occupancy, two-step
- * launches for the 64x8 and 64x16 tiles) for
- * `steps` steps on this ensemble in the given workspace and returns the fastest tune and its
- * time in milliseconds. */
+/* Autotuner: times every tile shape x schedule (per-step launches, persistent at full and half
+ * occupancy, two-step launches) for `steps` steps on this ensemble in the given workspace, in two
+ * sweeps (each candidate counts with its faster run), and returns the fastest tune and its time
+ * in milliseconds. */
 int lbm_autotune(const lbm_params *p, int32_t count, const double *const *gw_host,
                  const double *const *rho0_host, void *d_ws, size_t bytes, void *hip_stream,
                  int32_t steps, lbm_tune *best, double *best_ms);

@@ -194,12 +194,16 @@ static hipError_t launch_batch2_t(int geo, int eos, const InstDesc* inst, const 
     });
 }
 
-// Two steps per launch (schedule 2): tile 2 -> 64x16 output tiles, otherwise 64x8; the work-list
-// must have been built for that tile shape.
+// Two steps per launch (schedule 2) with the output tiles of the work-list's tile shape (0 64x4,
+// 1 64x8, 2 64x16, 3 128x4).
 hipError_t launch_batch_step2(int tile, int geo, int eos, const InstDesc* inst,
                               const int* tile_inst, int ntiles, int cur, hipStream_t s) {
-    if (tile == 2) return launch_batch2_t<64, 16>(geo, eos, inst, tile_inst, ntiles, cur, s);
-    return launch_batch2_t<64, 8>(geo, eos, inst, tile_inst, ntiles, cur, s);
+    switch (tile) {
+        case 1: return launch_batch2_t<64, 8>(geo, eos, inst, tile_inst, ntiles, cur, s);
+        case 2: return launch_batch2_t<64, 16>(geo, eos, inst, tile_inst, ntiles, cur, s);
+        case 3: return launch_batch2_t<128, 4>(geo, eos, inst, tile_inst, ntiles, cur, s);
+        default: return launch_batch2_t<64, 4>(geo, eos, inst, tile_inst, ntiles, cur, s);
+    }
 }
 
 hipError_t launch_batch_step(int tile, int geo, int eos, const InstDesc* inst,

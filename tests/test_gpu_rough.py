@@ -150,7 +150,8 @@ def test_mask_rejected_where_unsupported(orc, gpu):
         sim.adjoint_workspace(100, 10)
 
 
-@pytest.mark.parametrize("tile,schedule", [(0, 0), (1, 0), (2, 0), (3, 0), (1, 1), (1, 2), (2, 2)])
+@pytest.mark.parametrize("tile,schedule", [(0, 0), (1, 0), (2, 0), (3, 0), (1, 1), (0, 2), (1, 2),
+                                           (2, 2), (3, 2)])
 def test_masked_ensemble_bitwise_equals_lone_runs(orc, gpu, tile, schedule):
     """Pillared lattices of several sizes and forms as one ensemble: every instance carries the
     same bits as the lattice stepped alone, and the per-instance contact planes feed the fits."""
