@@ -28,6 +28,18 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS & %HBM peak per LB step; batched-sweep and adjoint speedup vs plain"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LU = 144  # algorithmic: read and write the 9 FP64 populations once
+# Algorithmic bytes per node and time step of a gradient run (checkpointed forward, then per
+# reverse step the segment's recomputed step and the two adjoint kernels): forward 144,
+# recompute 144, k_adj_local 264 (f^{n-1}, a in, c in, a out, q, p0, psi'), k_adj_gather 40.
+ADJ_BYTES_PER_NODE_STEP = 144 + 144 + 264 + 40
+
+
+def adjoint_roofline(node_steps: float, seconds: float) -> dict:
+    ach = ADJ_BYTES_PER_NODE_STEP * node_steps / seconds / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_node_step": ADJ_BYTES_PER_NODE_STEP,
+            "model": "forward 144 + recompute 144 + k_adj_local 264 + k_adj_gather 40"}
 KERNEL_SOURCES = ["paper_1410_2569_amd/csrc/lbm_device.h", "paper_1410_2569_amd/csrc/lbm_kernels.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step2_1024x512.json")
 
@@ -221,6 +233,7 @@ def adjoint_speedup(args) -> dict:
             "t_adjoint_s": round(t_adj, 4), "t_fd_512_runs_s": round(t_fd, 3),
             "fd_runs_timed": runs, "max_rel_err_vs_fd": float(err),
             "mlups_forward_ckpt_plus_backward": round(2 * fluid * N / t_adj / 1e6, 1),
+            "roofline": adjoint_roofline(fluid * N, t_adj),
             "workload": "256x128, R=40, modified form, smooth G_w, 4,000 steps, K=200"}
 
 
@@ -260,7 +273,7 @@ def c5_run(args) -> dict:
     del b
     torch.cuda.empty_cache()
 
-    grads, t_adj = [], 0.0
+    grads, t_adj, t_ckpt, t_back = [], 0.0, 0.0, 0.0
     sim = L.Sim(prm[0], gws[0], rhos[0])
     ws = sim.adjoint_workspace(NA, K)
     angles = []
@@ -272,13 +285,12 @@ def c5_run(args) -> dict:
             o = sim.observables(xc - 1.6 * r, xc + 1.6 * r, allow_nonfinite=True)
             angles.append(None if math.isnan(o["theta_deg"]) else round(o["theta_deg"], 2))
 
-        def adj():
-            sim.forward_ckpt(NA, K, ws)
-            sim.loss()
-            return sim.backward(NA, K, ws)
-
         holder = {}
-        t_adj += _timed(lambda: holder.setdefault("g", adj()))
+        t_f = _timed(lambda: sim.forward_ckpt(NA, K, ws))
+        t_b = _timed(lambda: holder.setdefault("g", (sim.loss(), sim.backward(NA, K, ws))[1]))
+        t_ckpt += t_f
+        t_back += t_b
+        t_adj += t_f + t_b
         grads.append(holder["g"].cpu().numpy())
         if i == 0:
             sim0_state = states[0]
@@ -312,6 +324,12 @@ def c5_run(args) -> dict:
                         "nonfinite_instances": sum(1 for o in obs if o["nonfinite"])},
             "adjoint": {"steps": NA, "K": K, "seconds": round(t_adj, 3),
                         "mlups_forward_ckpt_plus_backward": round(lu_adj / t_adj / 1e6, 1),
+                        "roofline": adjoint_roofline(fluid * NA, t_adj),
+                        "seconds_forward_ckpt": round(t_ckpt, 3),
+                        "seconds_loss_and_backward": round(t_back, 3),
+                        # recompute 144 + k_adj_local 264 + k_adj_gather 40 per node and step
+                        "backward_gbs": round((ADJ_BYTES_PER_NODE_STEP - 144) * fluid * NA
+                                              / t_back / 1e9, 1),
                         "fd_nodes": 16, "max_rel_err_vs_fd": float(max(errs))},
             "peak_device_bytes": int(peak), "droplet_angles_deg": angles, "dtype": "f64"}
 
