@@ -437,7 +437,9 @@ def rough_run(args) -> dict:
     fused tile shape or two-step output tile timed fastest on 400 steps) for --rough-steps
     steps. Reports the apparent
     angle against Cassie's law, Eq. (17), applied to the flat angle of the same G_w, the liquid
-    fraction of the gaps under the droplet, and Table II's densities."""
+    fraction of the gaps under the droplet, and Table II's densities. --rough-replicas R > 1
+    advances R copies of the four runs as one ensemble (the masked kernel on a filled chip; the
+    physics is that of the first copy)."""
     import paper_1410_2569_amd as L
     import synth
 
@@ -445,6 +447,7 @@ def rough_run(args) -> dict:
     fr = synth.ROUGH["width"] / (synth.ROUGH["width"] + synth.ROUGH["gap"])
     runs = [(form, g, h) for form, g in ROUGH_CASES for h in (0, synth.ROUGH["height"])]
     cs = [synth.rough_setup(form, g, height=h, gw_scale=1.0) for form, g, h in runs]
+    cs = cs * max(1, args.rough_replicas)
     args_b = ([c["params"] for c in cs], [c["gw"] for c in cs], [c["rho0"] for c in cs])
     best, best_t = None, math.inf
     for tune in [{"tile": t, "schedule": 0} for t in range(4)] + \
@@ -494,6 +497,7 @@ def rough_run(args) -> dict:
            "config": {"workload": "300x150, flat base or pillars 20 high, 6 wide, gaps 3; Eq. (15); "
                                   "droplet R=30; density-based and modified forms; the 4 runs as "
                                   "one masked ensemble", "runs": len(runs),
+                      "replicas": max(1, args.rough_replicas),
                       "tune": best},
            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
@@ -699,6 +703,8 @@ def main():
                          "spreading: dynamic wetting of Sec. III.B")
     ap.add_argument("--paper-steps", type=int, default=30_000)
     ap.add_argument("--rough-steps", type=int, default=100_000)
+    ap.add_argument("--rough-replicas", type=int, default=1,
+                    help="copies of the four rough-surface runs in the ensemble")
     ap.add_argument("--spread-steps", type=int, default=20_000)
     ap.add_argument("--spread-gamma", type=float, default=None,
                     help="surface tension to use instead of measuring it (Laplace stage skipped)")

@@ -40,7 +40,8 @@ __global__ __launch_bounds__(TX* TY) void k_batch_step(const InstDesc* __restric
 
 // Two steps per launch over the work-list (the tiles are the output tiles of step2_tile).
 template <int TX, int TY, int GEO, int EOS>
-__global__ __launch_bounds__(step2_threads(TX, TY, GEO)) void k_batch_step2(
+__global__
+__launch_bounds__(step2_threads(TX, TY, GEO), step2_waves(TX, TY, GEO)) void k_batch_step2(
     const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, int ntiles, int cur) {
     __shared__ Step2Lds<TX, TY, GEO == GEO_MASK> lds;
     const int t = xcd_tile(blockIdx.x, ntiles);

@@ -556,15 +556,19 @@ __device__ __forceinline__ void pull9_lds_mask(const double* g1, int plane, int 
     f[8] = (lk & 256u) ? g1[6 * plane + l] : g1[8 * plane + l + W - 1];
 }
 
-// Threads of a two-step workgroup. The LDS of a 64 x 8 tile allows two workgroups per CU; without
-// a solid mask it runs 768 threads (12 waves, 6 per SIMD with two workgroups) so that more waves
-// hide each other's latencies and its R2 (816 nodes) takes one pass on most of them (832 or more
-// threads leave room for one workgroup per CU only, and the mask variant needs too many
-// registers for 6 waves per SIMD). The 64 x 4 tile (three workgroups per CU) runs 512 threads,
-// so that its R2 (544 nodes) also takes one pass on all but one wave; the other tiles run one
-// thread per output node.
+// Threads of a two-step workgroup. The LDS of a 64 x 8 tile allows two workgroups per CU; it runs
+// 768 threads (12 waves, 6 per SIMD with two workgroups, which step2_waves asks the compiler to
+// leave registers for) so that more waves hide each other's latencies and its R2 (816 nodes)
+// takes one pass on all but one wave; 832 or more threads leave room for one workgroup per CU
+// only. The 64 x 4 tile (three workgroups per CU) runs 512 threads, so that its R2 (544 nodes)
+// also takes one pass on all but one wave; the other tiles run one thread per output node.
 __host__ __device__ constexpr int step2_threads(int TX, int TY, int GEO) {
-    return TX == 64 && TY == 8 && GEO != GEO_MASK ? 768 : (TX == 64 && TY == 4 ? 512 : TX * TY);
+    return TX == 64 && TY == 8 ? 768 : (TX == 64 && TY == 4 ? 512 : TX * TY);
+}
+// Waves per SIMD the two-step kernels must leave registers for (launch bounds): 6 for the tiles
+// whose LDS holds two (64 x 8, 12 waves each) or three (64 x 4, 8 waves each) workgroups per CU.
+__host__ __device__ constexpr int step2_waves(int TX, int TY, int GEO) {
+    return TX == 64 && (TY == 8 || TY == 4) ? 6 : 1;
 }
 
 // LDS of step2_tile; MK: a solid mask, whose link words of R2 are kept too.

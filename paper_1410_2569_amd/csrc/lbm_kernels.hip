@@ -85,7 +85,8 @@ __global__ __launch_bounds__(64 * (TYI + 2)) void k_step_ov(KParams P,
 
 // Two steps per launch over TX x TY output tiles (step2_tile).
 template <int TX, int TY, int GEO, int EOS>
-__global__ __launch_bounds__(step2_threads(TX, TY, GEO)) void k_step2(
+__global__
+__launch_bounds__(step2_threads(TX, TY, GEO), step2_waves(TX, TY, GEO)) void k_step2(
     KParams P, const double* __restrict__ gin, double* __restrict__ gout,
     const double* __restrict__ gw) {
     __shared__ Step2Lds<TX, TY, GEO == GEO_MASK> lds;
