@@ -95,3 +95,31 @@ def test_autotune_picks_a_valid_schedule(orc, gpu):
     ref = plain_states(gpu, cases, 7)
     for i in range(len(cases)):
         assert np.array_equal(b.f(i), ref[i])
+
+
+def test_c3_full_size_sampled(orc, gpu):
+    """The 96-lattice ensemble (128 x 64 ... 512 x 256, three forms, viscosity ratios 1, 5, 15) in
+    the benchmark's launch configuration (two steps per launch, 64 x 8 output tiles): after 31
+    steps, the populations of the largest and the smallest lattice and of one of each form against
+    the oracle, element by element."""
+    ens = synth.c3_ensemble()
+    prm, gws, rhos, qs = [], [], [], []
+    for e in ens:
+        q = orc.make_params(e["params"])
+        prm.append(dict(e["params"], rho_l=q.rho_l, rho_v=q.rho_v))
+        gws.append(e["gw"])
+        rhos.append(synth.droplet_rho(q.nx, q.ny, q.rho_l, q.rho_v, e["centres"], e["radii"],
+                                      seed=e["seed"]))
+        qs.append(q)
+    b = gpu.Batch(prm, gws, rhos, tune={"tile": 1, "schedule": 2})
+    steps = 31
+    b.step(steps)
+    sizes = [p["nx"] * p["ny"] for p in prm]
+    pick = {int(np.argmax(sizes)), int(np.argmin(sizes)), 0, 1, 2}
+    for i in sorted(pick):
+        q = qs[i]
+        f = orc.run(q, gws[i], orc.init_rest(q, rhos[i]), steps)
+        fl = orc.fluid_mask(q)
+        rel = float((np.abs(b.f(i) - f).max(0)[fl] / f.sum(0)[fl]).max())
+        print(f"C3 instance {i} ({q.nx}x{q.ny}): {rel:.3e}", flush=True)
+        assert rel <= 1e-9
