@@ -258,22 +258,31 @@ __global__ __launch_bounds__(256) void k_obs(KParams P, const double* __restrict
     }
 }
 
-// One block of 256 threads: thread t combines partials t, t+256, ... in order, then a fixed tree.
+// One block of 256 threads: for every quantity, thread t combines partials t, t+256, ... in
+// order, then a fixed tree; all quantities advance together (one pass over the partial rows).
 __global__ __launch_bounds__(256) void k_obs_final(const double* __restrict__ part, int nblk,
                                                    double* __restrict__ out) {
-    __shared__ double sh[256];
-    for (int q = 0; q < O_NQ; ++q) {
-        double s = op_identity(q);
-        for (int b = threadIdx.x; b < nblk; b += 256) s = op_combine(q, s, part[(long long)b * O_NQ + q]);
-        sh[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) sh[threadIdx.x] = op_combine(q, sh[threadIdx.x], sh[threadIdx.x + w]);
-            __syncthreads();
+    __shared__ double sh[O_NQ][256];
+    double s[O_NQ];
+#pragma unroll
+    for (int q = 0; q < O_NQ; ++q) s[q] = op_identity(q);
+    for (int b = threadIdx.x; b < nblk; b += 256) {
+        const double* r = part + (long long)b * O_NQ;
+#pragma unroll
+        for (int q = 0; q < O_NQ; ++q) s[q] = op_combine(q, s[q], r[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < O_NQ; ++q) sh[q][threadIdx.x] = s[q];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int q = 0; q < O_NQ; ++q)
+                sh[q][threadIdx.x] = op_combine(q, sh[q][threadIdx.x], sh[q][threadIdx.x + w]);
         }
-        if (threadIdx.x == 0) out[q] = sh[0];
         __syncthreads();
     }
+    if ((int)threadIdx.x < O_NQ) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
 // Contact line of one lattice (contact_line_block).
