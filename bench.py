@@ -264,6 +264,7 @@ def c5_run(args) -> dict:
     torch.cuda.reset_peak_memory_stats()
     b = L.Batch(prm, gws, rhos, tune=best)
     log(f"c5: {len(prm)} x {prm[0]['nx']}x{prm[0]['ny']}, tune {b.tune()}")
+    NA = max(0, min(NA, N))
     t_fwd1 = _timed(lambda: b.step(N - NA), b.stream)
     states = [b.save_state(i) for i in range(len(prm))]
     t_fwd2 = _timed(lambda: b.step(NA), b.stream)
@@ -272,6 +273,15 @@ def c5_run(args) -> dict:
     log(f"c5: forward {N} steps in {t_fwd:.2f} s")
     del b
     torch.cuda.empty_cache()
+    forward = {"steps": N, "seconds": round(t_fwd, 3), "mlups": round(fluid * N / t_fwd / 1e6, 1),
+               "tune": {k: best[k] for k in ("tile", "schedule", "waves_per_cu")},
+               "hbm_frac_effective": round(BYTES_PER_LU * fluid * N / t_fwd
+                                           / (HBM_PEAK_GBS * 1e9), 4),
+               "nonfinite_instances": sum(1 for o in obs if o["nonfinite"])}
+    if NA == 0:  # forward only (--c5-adj-steps 0)
+        return {"metric": "c5 large batched", "workload": "8 x 2048x1024, 6 droplets each, "
+                "striped G_w (-0.1/+0.2, width 64), modified form", "forward": forward,
+                "dtype": "f64"}
 
     grads, t_adj, t_ckpt, t_back = [], 0.0, 0.0, 0.0
     sim = L.Sim(prm[0], gws[0], rhos[0])
@@ -316,12 +326,7 @@ def c5_run(args) -> dict:
     lu_adj = 2 * fluid * NA  # forward_ckpt + backward, every instance
     return {"metric": "c5 large batched + adjoint", "workload": "8 x 2048x1024, 6 droplets "
             "each, striped G_w (-0.1/+0.2, width 64), modified form",
-            "forward": {"steps": N, "seconds": round(t_fwd, 3),
-                        "mlups": round(fluid * N / t_fwd / 1e6, 1),
-                        "tune": {k: best[k] for k in ("tile", "schedule", "waves_per_cu")},
-                        "hbm_frac_effective": round(BYTES_PER_LU * fluid * N / t_fwd
-                                                    / (HBM_PEAK_GBS * 1e9), 4),
-                        "nonfinite_instances": sum(1 for o in obs if o["nonfinite"])},
+            "forward": forward,
             "adjoint": {"steps": NA, "K": K, "seconds": round(t_adj, 3),
                         "mlups_forward_ckpt_plus_backward": round(lu_adj / t_adj / 1e6, 1),
                         "roofline": adjoint_roofline(fluid * NA, t_adj),
