@@ -317,16 +317,19 @@ __device__ __forceinline__ void collide(const KParams& P, double f[9], double rh
     // moments m = M f (rows rho, e, epsilon, jx, qx, jy, qy, pxx, pxy)
     const double ax = f[1] + f[3], ay = f[2] + f[4];
     const double sa = ax + ay;                       // axial sum
-    const double sd = (f[5] + f[7]) + (f[6] + f[8]); // diagonal sum
-    const double m1 = -4.0 * f[0] - sa + 2.0 * sd;
-    const double m2 = 4.0 * f[0] - 2.0 * sa + sd;
+    const double s57 = f[5] + f[7], s68 = f[6] + f[8];
+    const double sd = s57 + s68;                     // diagonal sum
+    const double f04 = 4.0 * f[0];
+    const double m1 = fma(2.0, sd, -(f04 + sa));
+    const double m2 = fma(-2.0, sa, f04 + sd);
+    const double d13 = f[1] - f[3], d24 = f[2] - f[4];
     const double d58 = f[5] - f[7], d68 = f[6] - f[8];
-    const double jx = (f[1] - f[3]) + d58 - d68;
-    const double jy = (f[2] - f[4]) + d58 + d68;
-    const double m4 = -2.0 * (f[1] - f[3]) + d58 - d68;
-    const double m6 = -2.0 * (f[2] - f[4]) + d58 + d68;
+    const double ex = d58 - d68, ey = d58 + d68;
+    const double jx = d13 + ex, jy = d24 + ey;
+    const double m4 = fma(-2.0, d13, ex);
+    const double m6 = fma(-2.0, d24, ey);
     const double m7 = ax - ay;
-    const double m8 = (f[5] + f[7]) - (f[6] + f[8]);
+    const double m8 = s57 - s68;
 
     // Eq. (6): velocity with half the force
     const double ir = 1.0 / rho;
@@ -367,17 +370,21 @@ __device__ __forceinline__ void collide(const KParams& P, double f[9], double rh
     const double a3 = ms3 * (1.0 / 6.0), a4 = ms4 * (1.0 / 12.0);
     const double a5 = ms5 * (1.0 / 6.0), a6 = ms6 * (1.0 / 12.0);
     const double a7 = ms7 * 0.25, a8 = ms8 * 0.25;
-    const double ba = a0 - a1 - 2.0 * a2, bd = a0 + 2.0 * a1 + a2;
+    const double ba = fma(-2.0, a2, a0 - a1), bd = fma(2.0, a1, a0 + a2);
+    f[0] = fma(4.0, a2 - a1, a0);
+    const double tx = ba + a7, ux = fma(-2.0, a4, a3);  // axial x: ba + a7 +- (a3 - 2 a4)
+    const double ty = ba - a7, uy = fma(-2.0, a6, a5);  // axial y: ba - a7 +- (a5 - 2 a6)
+    f[1] = tx + ux;
+    f[3] = tx - ux;
+    f[2] = ty + uy;
+    f[4] = ty - uy;
     const double X = a3 + a4, Y = a5 + a6;
-    f[0] = a0 - 4.0 * a1 + 4.0 * a2;
-    f[1] = ba + a3 - 2.0 * a4 + a7;
-    f[3] = ba - a3 + 2.0 * a4 + a7;
-    f[2] = ba + a5 - 2.0 * a6 - a7;
-    f[4] = ba - a5 + 2.0 * a6 - a7;
-    f[5] = bd + X + Y + a8;
-    f[6] = bd - X + Y - a8;
-    f[7] = bd - X - Y + a8;
-    f[8] = bd + X - Y - a8;
+    const double sp = X + Y, sm = Y - X;  // diagonals: bd +- a8 +- (X + Y) or (Y - X)
+    const double bp = bd + a8, bm = bd - a8;
+    f[5] = bp + sp;
+    f[7] = bp - sp;
+    f[6] = bm + sm;
+    f[8] = bm - sm;
 }
 
 // Macroscopic velocity of a node (Eq. 6) with the same force as collide().
