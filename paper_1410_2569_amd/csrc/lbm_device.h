@@ -333,7 +333,7 @@ __device__ __forceinline__ void collide(const KParams& P, double f[9], double rh
 
     // Eq. (6): velocity with half the force
     const double ir = 1.0 / rho;
-    const double vx = (jx + 0.5 * Fx) * ir, vy = (jy + 0.5 * Fy) * ir;
+    const double vx = fma(0.5, Fx, jx) * ir, vy = fma(0.5, Fy, jy) * ir;
     const double v2 = fma(vx, vx, vy * vy);
 
     // shear relaxation rate from the phase-interpolated viscosity
@@ -358,9 +358,10 @@ __device__ __forceinline__ void collide(const KParams& P, double f[9], double rh
     // Eq. (4) with Eq. (3) equilibria; m*_0 = rho
     const double ms1 = fma(P.h_e, S1, fma(-P.s_e, m1 - rho * fma(3.0, v2, -2.0), m1));
     const double ms2 = fma(P.h_z, S2, fma(-P.s_z, m2 - rho * fma(-3.0, v2, 1.0), m2));
-    const double ms3 = fma(P.h_j, Fx, fma(-P.s_j, fma(-rho, vx, jx), jx));
+    // momentum rows: j - s_j (j - rho v) + (1 - s_j/2) F with rho v = j + F/2 is j + F
+    const double ms3 = jx + Fx;
     const double ms4 = fma(-P.h_q, Fx, fma(-P.s_q, fma(rho, vx, m4), m4));
-    const double ms5 = fma(P.h_j, Fy, fma(-P.s_j, fma(-rho, vy, jy), jy));
+    const double ms5 = jy + Fy;
     const double ms6 = fma(-P.h_q, Fy, fma(-P.s_q, fma(rho, vy, m6), m6));
     const double ms7 = fma(hnu, S7, fma(-snu, fma(-rho, fma(vx, vx, -(vy * vy)), m7), m7));
     const double ms8 = fma(hnu, S8, fma(-snu, fma(-rho, vx * vy, m8), m8));
@@ -398,8 +399,8 @@ __device__ __forceinline__ void velocity(const KParams& P, const double f[9], do
     const double jx = (f[1] - f[3]) + d58 - d68;
     const double jy = (f[2] - f[4]) + d58 + d68;
     const double ir = 1.0 / rho;
-    vx = (jx + 0.5 * Fx) * ir;
-    vy = (jy + 0.5 * Fy) * ir;
+    vx = fma(0.5, Fx, jx) * ir;
+    vy = fma(0.5, Fy, jy) * ir;
 }
 
 // XCD-aware tile order: workgroup i runs on XCD i mod 8; give each XCD a contiguous range of
