@@ -702,7 +702,7 @@ def main():
     ap.add_argument("--workload", default="sweep",
                     choices=["sweep", "c5", "paper", "rough", "spreading"],
                     help="sweep: the 1024x512 sweep (default); c5: 8 x 2048x1024 ensemble with "
-                         "six droplets each, forward in one persistent launch, adjoint over "
+                         "six droplets each, forward with the autotuned schedule, adjoint over "
                          "the last 2,000 steps; paper: the printed points of Figs. 2-4 in the "
                          "paper's own setup; rough: flat and pillared surfaces of Sec. III.B; "
                          "spreading: dynamic wetting of Sec. III.B")
@@ -714,7 +714,8 @@ def main():
     ap.add_argument("--spread-gamma", type=float, default=None,
                     help="surface tension to use instead of measuring it (Laplace stage skipped)")
     ap.add_argument("--c5-steps", type=int, default=30_000)
-    ap.add_argument("--c5-adj-steps", type=int, default=2_000)
+    ap.add_argument("--c5-adj-steps", type=int, default=2_000,
+                    help="steps of the c5 gradient run (0: forward only)")
     ap.add_argument("--c5-K", type=int, default=45)
     ap.add_argument("--profile-probe", action="store_true",
                     help="for counter runs: a device copy of known size, then 20 step launches "
