@@ -69,6 +69,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def device_info() -> dict:
+    """The device the run used, as the runtime reports it."""
+    import torch
+
+    p = torch.cuda.get_device_properties(0)
+    return {"arch": p.gcnArchName, "compute_units": p.multi_processor_count,
+            "memory_bytes": p.total_memory, "l2_bytes": getattr(p, "L2_cache_size", None),
+            "lds_bytes_per_block": getattr(p, "shared_memory_per_block", None)}
+
+
 def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> dict:
     """A plain device copy of nbytes (above the 256 MB last-level cache), timed with events: the
     bandwidth the chip delivers to a streaming kernel, beside the 8 TB/s of the data sheet."""
@@ -846,6 +856,7 @@ def main():
            "hbm_frac_measured": (round(tr / avg_kernel_s / (HBM_PEAK_GBS * 1e9), 4) if tr
                                  else None),
            "copy_bandwidth": copy_bandwidth(),
+           "device": device_info(),
            "nonfinite_runs": bad,
            "roofline": roof}
     if not args.no_extras:
