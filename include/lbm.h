@@ -297,6 +297,8 @@ int lbm_batch_save_state(lbm_batch *b, int32_t index, void *host, size_t bytes);
 int64_t lbm_batch_current_step(const lbm_batch *b);
 /* The tune in use and the persistent grid size (workgroups). */
 int lbm_batch_get_tune(const lbm_batch *b, lbm_tune *t, int32_t *grid);
+/* Release an ensemble: waits for its queued work (graph replays included), then frees the
+ * captured graphs and the host handle; the workspace may be freed once it returns. */
 int lbm_batch_destroy(lbm_batch *b);
 const char *lbm_batch_last_error(const lbm_batch *b);
 /* Autotuner: times every tile shape x schedule (per-step launches, persistent at full and half
@@ -308,6 +310,9 @@ int lbm_autotune(const lbm_params *p, int32_t count, const double *const *gw_hos
                  int32_t steps, lbm_tune *best, double *best_ms);
 
 int64_t lbm_current_step(const lbm_ctx *c);
+/* Release a context (host memory only). Waits for the work queued on its stream first, so the
+ * caller may free the workspace as soon as it returns; LBM_E_HIP if that wait failed (the
+ * context is released all the same). */
 int lbm_destroy(lbm_ctx *c);
 const char *lbm_strerror(int code);
 const char *lbm_last_error(const lbm_ctx *c);

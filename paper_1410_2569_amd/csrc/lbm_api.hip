@@ -1367,11 +1367,14 @@ int lbm_batch_get_tune(const lbm_batch* b, lbm_tune* t, int32_t* grid) {
 
 int lbm_batch_destroy(lbm_batch* b) {
     if (!b) return LBM_E_INVAL;
+    // queued launches (graph replays among them) still read and write the workspace: let them
+    // finish before the graphs go and the caller may release the workspace
+    const hipError_t e = hipStreamSynchronize(b->stream);
     for (auto& g : b->graph)
         if (g) (void)hipGraphExecDestroy(g);
     if (b->pgraph) (void)hipGraphExecDestroy(b->pgraph);
     delete b;
-    return LBM_OK;
+    return e == hipSuccess ? LBM_OK : LBM_E_HIP;
 }
 
 const char* lbm_batch_last_error(const lbm_batch* b) { return b ? b->err.c_str() : g_create_err.c_str(); }
@@ -1437,8 +1440,10 @@ int lbm_autotune(const lbm_params* p, int32_t count, const double* const* gw_hos
 
 int lbm_destroy(lbm_ctx* c) {
     if (!c) return LBM_E_INVAL;
+    // queued launches still use the workspace: the caller may release it once this returns
+    const hipError_t e = hipStreamSynchronize(c->stream);
     delete c;
-    return LBM_OK;
+    return e == hipSuccess ? LBM_OK : LBM_E_HIP;
 }
 
 }  // extern "C"

@@ -217,6 +217,20 @@ def make_params(p: dict) -> Params:
     return q
 
 
+def _use_on(t, stream):
+    """Make a freshly allocated tensor t safe to use on `stream`: torch's caching allocator hands
+    out a block that is free only with respect to the current stream, so `stream` first waits for
+    the current stream; record_stream keeps the block from being reused until the work queued on
+    `stream` has finished."""
+    import torch
+
+    cur = torch.cuda.current_stream(t.device)
+    if stream.cuda_stream != cur.cuda_stream:
+        stream.wait_stream(cur)
+        t.record_stream(stream)
+    return t
+
+
 def workspace_size(q: Params) -> int:
     n = C.c_size_t()
     check(lib().lbm_workspace_size(C.byref(q), C.byref(n)))
@@ -240,6 +254,7 @@ class Sim:
         # 256-byte aligned: torch's caching allocator hands out 512-byte aligned blocks
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
+        _use_on(self.ws, self.stream)
         gshape = (self.ny, self.nx) if self.masked else (2, self.nx)
         g = np.ascontiguousarray(gw if gw is not None else np.zeros(gshape), dtype=np.float64)
         r = np.ascontiguousarray(rho0, dtype=np.float64)
@@ -296,7 +311,8 @@ class Sim:
         import torch
         k = n // every + 1
         if out is None:
-            out = torch.empty((k, 2), dtype=torch.float64, device=self.ws.device)
+            out = _use_on(torch.empty((k, 2), dtype=torch.float64, device=self.ws.device),
+                          self.stream)
         assert out.is_contiguous() and out.dtype == torch.float64
         self._chk(lib().lbm_record_contact_line(self.h, int(n), int(every), int(row),
                                                 C.c_void_p(out.data_ptr()), out.numel()))
@@ -333,7 +349,8 @@ class Sim:
         import torch
         n = C.c_size_t()
         check(lib().lbm_adjoint_workspace_size(C.byref(self.q), int(nsteps), int(K), C.byref(n)))
-        return torch.empty(n.value, dtype=torch.uint8, device=self.ws.device)
+        return _use_on(torch.empty(n.value, dtype=torch.uint8, device=self.ws.device),
+                       self.stream)
 
     def forward_ckpt(self, nsteps: int, K: int, ws):
         self._chk(lib().lbm_forward_ckpt(self.h, int(nsteps), int(K), C.c_void_p(ws.data_ptr()),
@@ -347,7 +364,8 @@ class Sim:
     def backward(self, nsteps: int, K: int, ws, w_centroid: float = 1.0, w_wet: float = 1.0):
         """dL/dG_w as a (2, nx) float64 device tensor (row 0 bottom wall, row 1 top wall)."""
         import torch
-        g = torch.empty((2, self.nx), dtype=torch.float64, device=self.ws.device)
+        g = _use_on(torch.empty((2, self.nx), dtype=torch.float64, device=self.ws.device),
+                    self.stream)
         self._chk(lib().lbm_backward(self.h, int(nsteps), int(K), C.c_void_p(ws.data_ptr()),
                                      ws.numel(), w_centroid, w_wet, C.c_void_p(g.data_ptr())))
         return g
@@ -394,7 +412,7 @@ class Batch:
         # a stream of its own (default priority): the legacy default stream cannot be captured
         # into the hipGraphs the ensemble replays
         self.stream = stream if stream is not None else torch.cuda.Stream(self.ws.device)
-        torch.cuda.current_stream(self.ws.device).synchronize()
+        _use_on(self.ws, self.stream)
         h = C.c_void_p()
         ws, st = C.c_void_p(self.ws.data_ptr()), C.c_void_p(self.stream.cuda_stream)
         if self.masked:
@@ -448,7 +466,8 @@ class Batch:
         import torch
         k = n // every + 1
         if out is None:
-            out = torch.empty((k, self.n, 2), dtype=torch.float64, device=self.ws.device)
+            out = _use_on(torch.empty((k, self.n, 2), dtype=torch.float64, device=self.ws.device),
+                          self.stream)
         assert out.is_contiguous() and out.dtype == torch.float64
         rw = (C.c_int32 * self.n)(*[int(r) for r in rows])
         self._chk(lib().lbm_batch_record_contact_line(self.h, int(n), int(every), rw,
@@ -491,7 +510,7 @@ def autotune(params_list, gw_list, rho0_list, steps=200, device="cuda"):
     ws = torch.empty(need, dtype=torch.uint8, device=device)
     best, ms = Tune(), C.c_double()
     stream = torch.cuda.Stream(ws.device)  # capturable (see Batch)
-    torch.cuda.current_stream(ws.device).synchronize()
+    _use_on(ws, stream)
     check(lib().lbm_autotune(arr, n, gwp, rp, C.c_void_p(ws.data_ptr()), need,
                              C.c_void_p(stream.cuda_stream), int(steps), C.byref(best),
                              C.byref(ms)))
