@@ -6,14 +6,6 @@
 
 namespace lbm {
 
-// Arguments of the observables kernel: contour level, fit window and centring of the sums.
-struct ObsArgs {
-    double rho_mid;     // (rho_l + rho_v) / 2
-    double y_min;       // interface points below this height are not fitted
-    double x_lo, x_hi;  // fit window
-    double cx, cy;      // coordinates are accumulated relative to this point
-};
-
 enum { OBS_NQ = 15 };
 
 // One instance of an ensemble, as the batch kernels see it (device memory).

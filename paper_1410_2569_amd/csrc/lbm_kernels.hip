@@ -104,21 +104,7 @@ __global__ __launch_bounds__(256) void k_psi(KParams P, const double* __restrict
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = P.y_lo + blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= P.nx || y > P.y_hi) return;
-    if (is_solid_node(P, x, y)) {  // solid mask: psi = 0, density reported as 0
-        psi_g[(long long)y * P.pitch + x] = 0.0;
-        if (rho_out) rho_out[(long long)y * P.pitch + x] = 0.0;
-        return;
-    }
-    double f[9];
-    pull9_any(P, gin, x, y, f);
-    const double rho = sum9(f);
-    const double ps = psi_of_rho(P, rho);
-    psi_g[(long long)y * P.pitch + x] = ps;
-    if (rho_out) rho_out[(long long)y * P.pitch + x] = rho;
-    if (P.walls && !P.mask && P.ghost) {
-        if (y == 1) psi_g[x] = ps;
-        if (y == P.ny - 2) psi_g[(long long)(P.ny - 1) * P.pitch + x] = ps;
-    }
+    psi_node(P, gin, psi_g, rho_out, x, y);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -166,28 +152,6 @@ __global__ __launch_bounds__(256) void k_pull(KParams P, const double* __restric
 // Observables: per-block partials (wave-level shuffles, then LDS across waves), fixed-order final
 // reduction. No floating-point atomics, so results are bitwise reproducible.
 // ------------------------------------------------------------------------------------------------
-enum { O_MIN = 0, O_MAX, O_U, O_UL, O_MASS, O_BAD, O_N, O_SX, O_SY, O_SXX, O_SYY, O_SXY, O_SXR,
-       O_SYR, O_SR, O_NQ };
-
-__device__ __forceinline__ double op_combine(int q, double a, double b) {
-    if (q == O_MIN) return fmin(a, b);
-    if (q == O_MAX || q == O_U || q == O_UL) return fmax(a, b);
-    return a + b;
-}
-
-__device__ __forceinline__ double op_identity(int q) {
-    if (q == O_MIN) return __builtin_huge_val();
-    if (q == O_MAX || q == O_U || q == O_UL) return -__builtin_huge_val();
-    return 0.0;
-}
-
-__device__ __forceinline__ void add_point(double v[O_NQ], double px, double py, double cx,
-                                          double cy) {
-    const double X = px - cx, Y = py - cy, r2 = X * X + Y * Y;
-    v[O_N] += 1.0; v[O_SX] += X; v[O_SY] += Y; v[O_SXX] += X * X; v[O_SYY] += Y * Y;
-    v[O_SXY] += X * Y; v[O_SXR] += X * r2; v[O_SYR] += Y * r2; v[O_SR] += r2;
-}
-
 // Block of 256 threads over a 64 x 4 patch. rho_f: rho of every fluid node (from k_psi);
 // psi_g: psi with ghost rows. Writes O_NQ partials per block.
 __global__ __launch_bounds__(256) void k_obs(KParams P, const double* __restrict__ gin,
@@ -199,48 +163,7 @@ __global__ __launch_bounds__(256) void k_obs(KParams P, const double* __restrict
     const int y = P.y_lo + blockIdx.y * 4 + (threadIdx.x >> 6);
     double v[O_NQ];
     for (int q = 0; q < O_NQ; ++q) v[q] = op_identity(q);
-    if (x < P.nx && y <= P.y_hi && !is_solid_node(P, x, y)) {
-        const long long i = (long long)y * P.pitch + x;
-        double f[9];
-        pull9_any(P, gin, x, y, f);
-        const double rho = rho_f[i], pc = psi_g[i];
-        const int xm = x == 0 ? P.nx - 1 : x - 1, xp = x == P.nx - 1 ? 0 : x + 1;
-        int ym = y - 1, yp = y + 1;
-        if (!P.walls || P.mask) { ym = wrapx(ym, P.ny); yp = wrapx(yp, P.ny); }
-        const double* rm = psi_g + (long long)ym * P.pitch;
-        const double* r0 = psi_g + (long long)y * P.pitch;
-        const double* rp = psi_g + (long long)yp * P.pitch;
-        double sx, sy, Ax = 0.0, Ay = 0.0, vx, vy;
-        cohesion_sum(rm[xm], rm[x], rm[xp], r0[xm], r0[xp], rp[xm], rp[x], rp[xp], sx, sy);
-        if (P.mask) adhesion_mask(P, x, y, P.links[(unsigned)i], Ax, Ay);
-        else adhesion_sum(P, gw, x, y, Ax, Ay);
-        velocity(P, f, rho, pc, sx, sy, Ax, Ay, vx, vy);
-        const double u = sqrt(vx * vx + vy * vy);
-        const bool ok = isfinite(rho) && isfinite(pc) && isfinite(u);
-        v[O_BAD] = ok ? 0.0 : 1.0;
-        if (ok) {
-            v[O_MIN] = rho; v[O_MAX] = rho; v[O_U] = u; v[O_MASS] = rho;
-            if (rho >= A.rho_mid) v[O_UL] = u;
-        }
-        // interface crossings on the edges to the right and upper neighbours
-        const bool la = rho >= A.rho_mid;
-        if (x + 1 < P.nx && !is_solid_node(P, x + 1, y)) {
-            const double rb = rho_f[i + 1];
-            if ((rb >= A.rho_mid) != la) {
-                const double t = (A.rho_mid - rho) / (rb - rho);
-                const double px = x + t, py = (double)y;
-                if (py >= A.y_min && px >= A.x_lo && px < A.x_hi) add_point(v, px, py, A.cx, A.cy);
-            }
-        }
-        if (y + 1 <= P.y_hi && !is_solid_node(P, x, y + 1)) {
-            const double rb = rho_f[i + P.pitch];
-            if ((rb >= A.rho_mid) != la) {
-                const double t = (A.rho_mid - rho) / (rb - rho);
-                const double px = (double)x, py = y + t;
-                if (py >= A.y_min && px >= A.x_lo && px < A.x_hi) add_point(v, px, py, A.cx, A.cy);
-            }
-        }
-    }
+    if (x < P.nx && y <= P.y_hi) obs_node(P, gin, rho_f, psi_g, gw, A, x, y, v);
     // wave-level tree (xor shuffles), then across the 4 waves of the block
     __shared__ double red[4][O_NQ];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
