@@ -29,17 +29,19 @@ METRIC = "MLUPS & %HBM peak per LB step; batched-sweep and adjoint speedup vs pl
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LU = 144  # algorithmic: read and write the 9 FP64 populations once
 # Algorithmic bytes per node and time step of a gradient run (checkpointed forward, then per
-# reverse step the segment's recomputed step and the two adjoint kernels): forward 144,
-# recompute 144, k_adj_local 264 (f^{n-1}, a in, c in, a out, q, p0, psi'), k_adj_gather 40.
-ADJ_BYTES_PER_NODE_STEP = 144 + 144 + 264 + 40
+# reverse step the segment's recomputed step and the fused adjoint kernel): forward 144,
+# recompute 144, k_adj 280 (reads f^{n-1} 72, a 72, q 16, p0 8, psi' 8; writes a, q, p0, psi').
+ADJ_BYTES_PER_NODE_STEP = 144 + 144 + 280
+ADJ_MODEL = "forward 144 + recompute 144 + k_adj 280"
 
 
 def adjoint_roofline(node_steps: float, seconds: float) -> dict:
     ach = ADJ_BYTES_PER_NODE_STEP * node_steps / seconds / 1e9
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-            "bytes_per_node_step": ADJ_BYTES_PER_NODE_STEP,
-            "model": "forward 144 + recompute 144 + k_adj_local 264 + k_adj_gather 40"}
+            "bytes_per_node_step": ADJ_BYTES_PER_NODE_STEP, "model": ADJ_MODEL}
+
+
 KERNEL_SOURCES = ["paper_1410_2569_amd/csrc/lbm_device.h", "paper_1410_2569_amd/csrc/lbm_kernels.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step2_1024x512.json")
 
@@ -138,6 +140,39 @@ def _timed(fn, stream=None):
     return e0.elapsed_time(e1) / 1e3
 
 
+def schedule_table(prm, gws, rhos, steps: int) -> dict:
+    """Milliseconds per step of every tile shape x schedule on the ensemble (the persistent one at
+    full and, where it allows two or more, half occupancy): the autotuner's candidates, each the
+    faster of two timed runs after a warm-up that captures its graph. Also the best persistent
+    time over the best graph-replayed one."""
+    import torch
+
+    import paper_1410_2569_amd as L
+    names = {0: "per-step", 1: "persistent", 2: "two-step"}
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    rows = []
+    for tile in range(4):
+        for sched in (0, 2, 1):
+            tunes = [{"tile": tile, "schedule": sched, "waves_per_cu": 0}]
+            for t in tunes:
+                b = L.Batch(prm, gws, rhos, tune=t)
+                grid = b.tune()["grid"]
+                if sched == 1 and t["waves_per_cu"] == 0 and grid // cus >= 2:
+                    tunes.append(dict(t, waves_per_cu=grid // cus // 2))
+                b.step(2)
+                b.step(steps)
+                ms = min(_timed(lambda: b.step(steps), b.stream) for _ in range(2)) * 1e3 / steps
+                rows.append({"tile": tile, "schedule": names[sched],
+                             "waves_per_cu": t["waves_per_cu"], "grid": grid,
+                             "ms_per_step": round(ms, 4)})
+                del b
+                torch.cuda.empty_cache()
+    best_p = min(r["ms_per_step"] for r in rows if r["schedule"] == "persistent")
+    best_g = min(r["ms_per_step"] for r in rows if r["schedule"] != "persistent")
+    return {"steps": steps, "candidates": rows,
+            "persistent_over_graph": round(best_p / best_g, 3)}
+
+
 def batched_speedup(args) -> dict:
     """96-instance uneven ensemble: one lbm_batch_step(n) (autotuned tile and schedule) against
     the plain loop that advances each instance alone with lbm_step(n)."""
@@ -181,6 +216,7 @@ def batched_speedup(args) -> dict:
             "instances": len(prm), "fluid_nodes": fluid, "steps": n,
             "tune": {k: best[k] for k in ("tile", "schedule", "waves_per_cu")},
             "bitwise_equal_to_plain": bool(same), "nonfinite_instances": bad,
+            "schedules": schedule_table(prm, gws, rhos, 40),
             "workload": "96 uneven lattices 128x64..512x256, 3 forms x G_w sweep x viscosity "
                         "ratios {1,5,15}"}
 
@@ -250,9 +286,10 @@ def adjoint_speedup(args) -> dict:
 def c5_run(args) -> dict:
     """8 x 2048x1024 lattices, six droplets each on a striped wall (G_w -0.1 / +0.2, width 64),
     modified form. Forward: the ensemble with the autotuned schedule (graph-replayed launches or
-    one persistent launch). Adjoint: for every instance,
-    dL/dG_w over the last `c5_adj_steps` steps (checkpoint every K) from its exported state;
-    finite differences on 16 seeded nodes of instance 0."""
+    one persistent launch). Adjoint: dL/dG_w of all eight instances over the last `c5_adj_steps`
+    steps in one ensemble sweep (checkpointed forward with the same schedule, then reverse steps
+    over the tile work-list of every instance, checkpoint every K); finite differences on 16
+    seeded nodes of instance 0."""
     import numpy as np
     import torch
 
@@ -271,80 +308,90 @@ def c5_run(args) -> dict:
     fluid = sum(p["nx"] * (p["ny"] - 2) for p in prm)
     from paper_1410_2569_amd import tune as T
     best = T.tuned(prm, gws, rhos, steps=40)
+    schedules = schedule_table(prm, gws, rhos, 20)
     torch.cuda.reset_peak_memory_stats()
     b = L.Batch(prm, gws, rhos, tune=best)
     log(f"c5: {len(prm)} x {prm[0]['nx']}x{prm[0]['ny']}, tune {b.tune()}")
     NA = max(0, min(NA, N))
+    tune = {k: best[k] for k in ("tile", "schedule", "waves_per_cu")}
+    workload = ("8 x 2048x1024, 6 droplets each, striped G_w (-0.1/+0.2, width 64), "
+                "modified form")
     t_fwd1 = _timed(lambda: b.step(N - NA), b.stream)
+    if NA == 0:  # forward only (--c5-adj-steps 0)
+        obs = b.observables(allow_nonfinite=True)
+        return {"metric": "c5 large batched", "workload": workload, "dtype": "f64",
+                "schedules": schedules,
+                "forward": {"steps": N, "seconds": round(t_fwd1, 3),
+                            "mlups": round(fluid * N / t_fwd1 / 1e6, 1), "tune": tune,
+                            "hbm_frac_effective": round(BYTES_PER_LU * fluid * N / t_fwd1
+                                                        / (HBM_PEAK_GBS * 1e9), 4),
+                            "nonfinite_instances": sum(1 for o in obs if o["nonfinite"])}}
     states = [b.save_state(i) for i in range(len(prm))]
-    t_fwd2 = _timed(lambda: b.step(NA), b.stream)
-    t_fwd = t_fwd1 + t_fwd2
+    ws = b.adjoint_workspace(NA, K)
+    log(f"c5: ensemble adjoint workspace {ws.numel() / 2**30:.1f} GiB")
+    t_ckpt = _timed(lambda: b.forward_ckpt(NA, K, ws), b.stream)
+    holder = {}
+    t_back = _timed(lambda: holder.update(L=b.loss(), g=b.backward(NA, K, ws)), b.stream)
+    grads = [g.cpu().numpy() for g in holder["g"]]
     obs = b.observables(allow_nonfinite=True)
-    log(f"c5: forward {N} steps in {t_fwd:.2f} s")
-    del b
+    t_fwd = t_fwd1 + t_ckpt
+    log(f"c5: forward {N} steps in {t_fwd:.2f} s, ensemble adjoint {NA} steps: "
+        f"checkpointed forward {t_ckpt:.2f} s, loss + backward {t_back:.2f} s")
+    del b, ws
     torch.cuda.empty_cache()
     forward = {"steps": N, "seconds": round(t_fwd, 3), "mlups": round(fluid * N / t_fwd / 1e6, 1),
-               "tune": {k: best[k] for k in ("tile", "schedule", "waves_per_cu")},
+               "tune": tune, "includes_checkpoint_copies": True,
                "hbm_frac_effective": round(BYTES_PER_LU * fluid * N / t_fwd
                                            / (HBM_PEAK_GBS * 1e9), 4),
                "nonfinite_instances": sum(1 for o in obs if o["nonfinite"])}
-    if NA == 0:  # forward only (--c5-adj-steps 0)
-        return {"metric": "c5 large batched", "workload": "8 x 2048x1024, 6 droplets each, "
-                "striped G_w (-0.1/+0.2, width 64), modified form", "forward": forward,
-                "dtype": "f64"}
 
-    grads, t_adj, t_ckpt, t_back = [], 0.0, 0.0, 0.0
-    sim = L.Sim(prm[0], gws[0], rhos[0])
-    ws = sim.adjoint_workspace(NA, K)
+    # droplet angles at the start of the adjoint window, and finite differences of instance 0
     angles = []
+    sim = None
     for i in range(len(prm)):
-        if i:
-            sim = L.Sim(prm[i], gws[i], rhos[i])
+        sim = L.Sim(prm[i], gws[i], rhos[i])
         sim.load_state(states[i])
         for (xc, _), r in zip(insts[i]["centres"], insts[i]["radii"]):
             o = sim.observables(xc - 1.6 * r, xc + 1.6 * r, allow_nonfinite=True)
             angles.append(None if math.isnan(o["theta_deg"]) else round(o["theta_deg"], 2))
-
-        holder = {}
-        t_f = _timed(lambda: sim.forward_ckpt(NA, K, ws))
-        t_b = _timed(lambda: holder.setdefault("g", (sim.loss(), sim.backward(NA, K, ws))[1]))
-        t_ckpt += t_f
-        t_back += t_b
-        t_adj += t_f + t_b
-        grads.append(holder["g"].cpu().numpy())
-        if i == 0:
-            sim0_state = states[0]
-            # finite differences on 16 seeded bottom-wall nodes of instance 0
-            d = synth.Draws(99)
-            nodes = sorted({int(d.u01() * prm[0]["nx"]) for _ in range(40)})[:16]
-            h = 1e-5
-            errs = []
-            scale = np.abs(grads[0][0]).max()
-            for x in nodes:
-                vals = []
-                for sgn in (1, -1):
-                    gg = gws[0].copy()
-                    gg[0, x] += sgn * h
-                    sim.load_state(sim0_state)
-                    sim.set_gw(gg)
-                    sim.step(NA)
-                    vals.append(sim.loss())
-                errs.append(abs(grads[0][0, x] - (vals[0] - vals[1]) / (2 * h)) / scale)
-            sim.set_gw(gws[0])
-            log(f"c5: FD check on {len(nodes)} nodes, max rel err {max(errs):.2e}")
+        if i < len(prm) - 1:
+            del sim
+    sim = L.Sim(prm[0], gws[0], rhos[0])
+    d = synth.Draws(99)
+    nodes = sorted({int(d.u01() * prm[0]["nx"]) for _ in range(40)})[:16]
+    h = 1e-5
+    errs = []
+    scale = np.abs(grads[0][0]).max()
+    for x in nodes:
+        vals = []
+        for sgn in (1, -1):
+            gg = gws[0].copy()
+            gg[0, x] += sgn * h
+            sim.load_state(states[0])
+            sim.set_gw(gg)
+            sim.step(NA)
+            vals.append(sim.loss())
+        errs.append(abs(grads[0][0, x] - (vals[0] - vals[1]) / (2 * h)) / scale)
+    log(f"c5: FD check on {len(nodes)} nodes of instance 0, max rel err {max(errs):.2e}")
     peak = torch.cuda.max_memory_allocated()
-    lu_adj = 2 * fluid * NA  # forward_ckpt + backward, every instance
-    return {"metric": "c5 large batched + adjoint", "workload": "8 x 2048x1024, 6 droplets "
-            "each, striped G_w (-0.1/+0.2, width 64), modified form",
-            "forward": forward,
-            "adjoint": {"steps": NA, "K": K, "seconds": round(t_adj, 3),
-                        "mlups_forward_ckpt_plus_backward": round(lu_adj / t_adj / 1e6, 1),
+    t_adj = t_ckpt + t_back
+    back_bytes = (ADJ_BYTES_PER_NODE_STEP - 144) * fluid * NA  # recompute + k_adj
+    back = {"bound": "hbm", "achieved": round(back_bytes / t_back / 1e9, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(back_bytes / t_back / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_node_step": ADJ_BYTES_PER_NODE_STEP - 144,
+            "model": "recompute 144 + k_adj 280"}
+    return {"metric": "c5 large batched + adjoint", "workload": workload,
+            "forward": forward, "schedules": schedules,
+            "adjoint": {"steps": NA, "K": K, "batched": True, "instances": len(prm),
+                        "seconds": round(t_adj, 3),
+                        "mlups_forward_ckpt_plus_backward": round(2 * fluid * NA / t_adj / 1e6, 1),
                         "roofline": adjoint_roofline(fluid * NA, t_adj),
                         "seconds_forward_ckpt": round(t_ckpt, 3),
                         "seconds_loss_and_backward": round(t_back, 3),
-                        # recompute 144 + k_adj_local 264 + k_adj_gather 40 per node and step
-                        "backward_gbs": round((ADJ_BYTES_PER_NODE_STEP - 144) * fluid * NA
-                                              / t_back / 1e9, 1),
+                        "backward_mlups": round(fluid * NA / t_back / 1e6, 1),
+                        "backward_roofline": back,
+                        "losses": [round(v, 6) for v in holder["L"]],
                         "fd_nodes": 16, "max_rel_err_vs_fd": float(max(errs))},
             "peak_device_bytes": int(peak), "droplet_angles_deg": angles, "dtype": "f64"}
 

@@ -174,6 +174,7 @@ int lbm_observables_window(lbm_ctx *c, double x_lo, double x_hi, lbm_obs *out);
  * default plane is y = 0.5 (bounce-back and masked geometries) or 1 (wet-node walls). */
 int lbm_observables_plane(lbm_ctx *c, double x_lo, double x_hi, double y_wall, lbm_obs *out);
 
+
 /* Dynamic wetting (Sec. III.B, Fig. 7): advance n steps (a multiple of `every`) and record the
  * contact line on fluid row `row` at steps 0, every, 2 every, ..., n of this call, without any
  * host synchronisation. Sample k is written to d_series[2k] (leftmost rho_mid crossing where rho
@@ -231,7 +232,7 @@ int lbm_set_schedule(lbm_ctx *c, int32_t schedule);
  *     K steps from its checkpoint, runs the adjoint steps in reverse and writes dL/dG_w into the
  *     device array d_grad [2][nx] (row 0 bottom wall, row 1 top wall). Asynchronous on the
  *     context stream; the context's own state is left at step N.
- * Memory: ceil(N/K) + K states of 9 * ny * round_up(nx, 32) doubles, plus about 24 planes.
+ * Memory: ceil(N/K) + K states of 9 * ny * round_up(nx, 32) doubles, plus 26 planes.
  */
 int lbm_adjoint_workspace_size(const lbm_params *p, int64_t nsteps, int32_t K, size_t *bytes);
 int lbm_forward_ckpt(lbm_ctx *c, int64_t nsteps, int32_t K, void *d_ws, size_t bytes);
@@ -242,11 +243,13 @@ int lbm_backward(lbm_ctx *c, int64_t nsteps, int32_t K, void *d_ws, size_t bytes
 /* ---- Ensembles of uneven lattices -------------------------------------------------------- */
 /*
  * `count` independent instances (each with its own lbm_params: lattice size, wall force, G_w,
- * viscosities ...) advanced together. All instances' tiles form one work-list, executed either
- * one launch per time step (schedule 0, replayed from a captured hipGraph) or by one persistent
- * launch for n steps (schedule 1: an occupancy-sized grid with a grid barrier between steps;
- * lbm_batch_step is then a single hipGraphLaunch). Both run the same per-tile arithmetic as
- * lbm_step, so every instance evolves bit-for-bit as it would alone.
+ * viscosities ...) advanced together. All instances' tiles form one work-list, executed by one
+ * launch per time step (schedule 0) or per two steps (schedule 2), replayed from captured
+ * hipGraphs, or by one persistent launch for n steps (schedule 1: an occupancy-sized grid that
+ * advances its tiles two steps at a time, with a grid barrier between the two-step passes, and a
+ * per-step launch for an odd last step; lbm_batch_step is then a single hipGraphLaunch). All run
+ * the same per-tile arithmetic as lbm_step, so every instance evolves bit-for-bit as it would
+ * alone.
  */
 typedef struct {
     int32_t tile;         /* tile shape 0..3: 64x4, 64x8, 64x16, 128x4 */
@@ -289,6 +292,27 @@ int lbm_batch_observables_plane(lbm_batch *b, const double *y_wall, lbm_obs *out
  * filled asynchronously on the ensemble's stream. */
 int lbm_batch_record_contact_line(lbm_batch *b, int64_t n, int32_t every, const int32_t *rows,
                                   double *d_series, size_t count);
+/* Gradients for a whole ensemble (every instance with walls = 1): the objective and the adjoint
+ * of the single-lattice entry points above (lbm_loss, lbm_forward_ckpt, lbm_backward) for every
+ * instance at once. The forward part advances the ensemble by nsteps with its own schedule and
+ * stores every instance's state every K steps; the backward part recomputes each segment of all
+ * instances with two-step launches over one work-list of 64 x 4 tiles and runs each reverse step
+ * of all instances as one launch over the same work-list. Every instance's gradient is bit for bit
+ * the one its lattice alone gets from lbm_backward.
+ *   lbm_batch_adjoint_workspace_size: device bytes for (nsteps, K): per instance ceil(N/K) + K
+ *     states and the adjoint buffers of lbm_adjoint_workspace_size, plus the tables;
+ *   lbm_batch_forward_ckpt: d_ws caller-owned, 256-byte aligned, >= that size;
+ *   lbm_batch_loss: L[count] host array (synchronises);
+ *   lbm_batch_backward: must follow the matching lbm_batch_forward_ckpt (LBM_E_STATE otherwise);
+ *     writes dL/dG_w of instance i ([2][nx_i], bottom then top wall) to the device array d_grad
+ *     at offset sum_{j<i} 2 nx_j; asynchronous on the ensemble's stream.
+ * LBM_E_INVAL when an instance has another geometry. */
+int lbm_batch_adjoint_workspace_size(const lbm_batch *b, int64_t nsteps, int32_t K,
+                                     size_t *bytes);
+int lbm_batch_forward_ckpt(lbm_batch *b, int64_t nsteps, int32_t K, void *d_ws, size_t bytes);
+int lbm_batch_loss(lbm_batch *b, double w_centroid, double w_wet, double *L);
+int lbm_batch_backward(lbm_batch *b, int64_t nsteps, int32_t K, void *d_ws, size_t bytes,
+                       double w_centroid, double w_wet, double *d_grad);
 /* Pre-collision populations f^n of instance `index` ([9][ny][nx] host array). */
 int lbm_batch_read_f(lbm_batch *b, int32_t index, double *host, size_t count);
 /* State of instance `index` as a checkpoint blob (the format of lbm_save_state, loadable into

@@ -2,139 +2,34 @@
 // objective, for gradients with respect to the per-wall-node wettability G_w.
 //
 // Per time step n (forward: g^n = C(pull(g^{n-1}))), with lambda^n = dL/df^n stored as
-// lambda = a + c 1 (a: 9 planes, c: one scalar plane):
-//   pass A  (k_adj_local, one thread per fluid node y, tile + halo like the fused forward step):
-//           nu = dL/dg^n(y) gathered from (a, c)^{n+1} (transpose of pull streaming and
-//           bounce-back), the forward node recomputed from g^{n-1}, then reverse mode through the
-//           MRT collision: a^n(y) = dL/df^n(y) along every path except psi, p0 = dL/dpsi(y) as the
-//           node's own pre-factor, q = dL/ds for the cohesion sum s = sum w_a psi(y+e_a) e_a,
-//           psi'(rho(y)), and r = dL/dA on wall rows.
-//   pass B  (k_adj_gather): xi(x) = p0(x) + sum_a w_a e_a . q(x - e_a) (+ the mirrored ghost
-//           rows), c^n(x) = psi'(x) xi(x); dL/dG_w(s) += sum_a omega_a e_a . r(s - e_a) on the
-//           solid nodes s of both walls.
+// lambda = a + c 1 (a: 9 planes, c: one scalar plane), one launch of k_adj per reverse step
+// (adj_tile in lbm_device.h): c of the later step is formed on the tile and one ring from its q,
+// p0 and psi' (the transpose of the cohesion stencil), then lambda is gathered through the
+// transposed pull streaming and bounce-back and the forward node is recomputed from g^{n-1} for
+// the reverse mode of the MRT collision (a^{n-1}, q = dL/ds, p0 = dL/dpsi as the node's own
+// pre-factor, psi', and r = dL/dA on the wall rows). dL/dG_w accumulates on the solid nodes of
+// both walls from each step's r, the last step's by k_adj_gw.
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
 namespace lbm {
 
 template <int TX, int TY>
-__global__ __launch_bounds__(TX* TY) void k_adj_local(KParams P, const double* __restrict__ gprev,
-                                                      const double* __restrict__ a_in,
-                                                      const double* __restrict__ c_in,
-                                                      const double* __restrict__ gw,
-                                                      double* __restrict__ a_out,
-                                                      double* __restrict__ qbuf,
-                                                      double* __restrict__ p0buf,
-                                                      double* __restrict__ dpsibuf,
-                                                      double* __restrict__ rvec) {
-    constexpr int NT = TX * TY;
-    constexpr int LW = TX + 2;
-    constexpr int NH = 2 * LW + 2 * TY;
-    __shared__ double sp[(TY + 2) * LW];
-
+__global__ __launch_bounds__(TX* TY) void k_adj(KParams P, AdjPtrs A) {
+    __shared__ AdjLds<TX, TY> lds;
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
     const int tile = xcd_tile(blockIdx.x, ntx * nty);
-    const int x0 = (tile % ntx) * TX;
-    const int y0 = P.y_lo + (tile / ntx) * TY;
-    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-    const int x = x0 + tx, y = y0 + ty;
-    const bool active = x < P.nx && y <= P.y_hi;
-
-    double f[9];
-    double rho = 1.0, psi_c = 0.0;
-    if (active) {
-        pull9<GEO_ROWS>(P, gprev, x, y, f);
-        rho = sum9(f);
-        psi_c = psi_of_rho(P, rho);
-    }
-    sp[(ty + 1) * LW + tx + 1] = active ? psi_c : psi_at<GEO_ROWS>(P, gprev, x, y);
-    for (int h = threadIdx.x; h < NH; h += NT) {
-        int hx, hy;
-        if (h < LW) { hx = h - 1; hy = -1; }
-        else if (h < 2 * LW) { hx = h - LW - 1; hy = TY; }
-        else if (h < 2 * LW + TY) { hx = -1; hy = h - 2 * LW; }
-        else { hx = TX; hy = h - 2 * LW - TY; }
-        sp[(hy + 1) * LW + hx + 1] = psi_at<GEO_ROWS>(P, gprev, x0 + hx, y0 + hy);
-    }
-    __syncthreads();
-    if (!active) return;
-
-    const double* cc = sp + (ty + 1) * LW + tx + 1;
-    double sx, sy;
-    cohesion_sum(cc[-LW - 1], cc[-LW], cc[-LW + 1], cc[-1], cc[1], cc[LW - 1], cc[LW],
-                 cc[LW + 1], sx, sy);
-    double Ax = 0.0, Ay = 0.0;
-    const bool wall_row = P.walls && (y == 1 || y == P.ny - 2);
-    if (wall_row) adhesion_sum(P, gw, x, y, Ax, Ay);
-
-    double nu[9], fb[9], pb, qx, qy, rx, ry;
-    push_gather(P, a_in, c_in, x, y, nu);
-    collide_adj(P, f, rho, psi_c, sx, sy, Ax, Ay, nu, fb, pb, qx, qy, rx, ry);
-
-    const unsigned i = (unsigned)y * P.pitch + x;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) (a_out + k * P.plane)[i] = fb[k];
-    qbuf[i] = qx;
-    (qbuf + P.plane)[i] = qy;
-    p0buf[i] = pb;
-    dpsibuf[i] = dpsi_drho(P, rho, psi_c);
-    if (wall_row) {
-        if (y == 1) { rvec[x] = rx; rvec[P.pitch + x] = ry; }
-        if (y == P.ny - 2) { rvec[2 * P.pitch + x] = rx; rvec[3 * P.pitch + x] = ry; }
-    }
+    adj_tile<TX, TY>(P, A, (tile % ntx) * TX, P.y_lo + (tile / ntx) * TY, lds);
 }
 
-__global__ __launch_bounds__(256) void k_adj_gather(KParams P, const double* __restrict__ qbuf,
-                                                    const double* __restrict__ p0buf,
-                                                    const double* __restrict__ dpsibuf,
-                                                    const double* __restrict__ rvec,
-                                                    double* __restrict__ c_out,
-                                                    double* __restrict__ gwgrad) {
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = P.y_lo + blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (x >= P.nx || y > P.y_hi) return;
-    const unsigned pitch = P.pitch;
-    const unsigned ux = x;
-    const unsigned xm = ux == 0 ? P.nx - 1 : ux - 1;
-    const unsigned xp = ux == (unsigned)P.nx - 1 ? 0 : ux + 1;
-    unsigned ym, yp;
-    if (P.walls) { ym = y - 1; yp = y + 1; }  // solid rows of q hold 0
-    else { ym = y == 0 ? P.ny - 1 : y - 1; yp = y == P.ny - 1 ? 0 : y + 1; }
-    const double* qx = qbuf;
-    const double* qy = qbuf + P.plane;
-    const unsigned r0 = (unsigned)y * pitch, rm = ym * pitch, rp = yp * pitch;
-    // sum over a of w_a e_a . q(x - e_a)
-    double xi = (qx[r0 + xm] - qx[r0 + xp] + qy[rm + ux] - qy[rp + ux]) * (1.0 / 3.0) +
-                ((qx[rm + xm] + qy[rm + xm]) + (qy[rm + xp] - qx[rm + xp]) -
-                 (qx[rp + xp] + qy[rp + xp]) + (qx[rp + xm] - qy[rp + xm])) * (1.0 / 12.0);
-    if (P.walls && P.ghost) {
-        // the solid row next to the wall carries this row's psi (mirror ghost)
-        if (y == 1)
-            xi += -qy[r0 + ux] * (1.0 / 3.0) +
-                  ((-qx[r0 + xp] - qy[r0 + xp]) + (qx[r0 + xm] - qy[r0 + xm])) * (1.0 / 12.0);
-        if (y == P.ny - 2)
-            xi += qy[r0 + ux] * (1.0 / 3.0) +
-                  ((qx[r0 + xm] + qy[r0 + xm]) + (qy[r0 + xp] - qx[r0 + xp])) * (1.0 / 12.0);
-    }
-    xi += p0buf[r0 + ux];
-    c_out[r0 + ux] = dpsibuf[r0 + ux] * xi;
-
-    if (P.walls) {
-        // dL/dG_w of the solid node beside this fluid node (omega = w/3: 1/9 axial, 1/36 diagonal)
-        if (y == 1) {
-            const double* rX = rvec;
-            const double* rY = rvec + pitch;
-            gwgrad[ux] += -rY[ux] * (1.0 / 9.0) +
-                          ((-rX[xp] - rY[xp]) + (rX[xm] - rY[xm])) * (1.0 / 36.0);
-        }
-        if (y == P.ny - 2) {
-            const double* rX = rvec + 2 * pitch;
-            const double* rY = rvec + 3 * pitch;
-            gwgrad[pitch + ux] += rY[ux] * (1.0 / 9.0) +
-                                  ((rX[xm] + rY[xm]) + (rY[xp] - rX[xp])) * (1.0 / 36.0);
-        }
-    }
+// dL/dG_w of the wall vectors of the last reverse step.
+__global__ __launch_bounds__(256) void k_adj_gw(KParams P, const double* __restrict__ rv,
+                                                double* __restrict__ gwgrad) {
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= P.nx || !P.walls) return;
+    adj_gw_node(P, rv, gwgrad, x, 1);
+    adj_gw_node(P, rv, gwgrad, x, P.ny - 2);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -188,14 +83,17 @@ __global__ __launch_bounds__(256) void k_sum_final(const double* __restrict__ pa
     }
 }
 
-// dL/drho^N on every fluid node: the seed of the adjoint (stored as the scalar plane c).
+// dL/drho^N on every fluid node, the seed of the adjoint: written as the later step's p0 with
+// psi' = 1 (and q = 0), so that the first reverse step forms c = 1 * (0 + seed) = seed exactly.
 __global__ __launch_bounds__(256) void k_loss_seed(KParams P, double w_c, double w_w, double yc,
-                                                   double sum_phi, double* __restrict__ c) {
+                                                   double sum_phi, double* __restrict__ p0,
+                                                   double* __restrict__ dpsi) {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = P.y_lo + blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= P.nx || y > P.y_hi) return;
     const double d = w_c * ((y - 0.5) - yc) / sum_phi + (y == 1 ? w_w : 0.0);
-    c[(unsigned)y * P.pitch + x] = P.inv_drho * d;
+    p0[(unsigned)y * P.pitch + x] = P.inv_drho * d;
+    dpsi[(unsigned)y * P.pitch + x] = 1.0;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -203,19 +101,24 @@ static dim3 node_grid_adj(const KParams& P) {
     return dim3((P.nx + 63) / 64, (P.y_hi - P.y_lo + 4) / 4);
 }
 
-hipError_t launch_adj_step(const KParams& P, const double* gprev, const double* a_in,
-                           const double* c_in, const double* gw, double* a_out, double* qbuf,
-                           double* p0buf, double* dpsibuf, double* rvec, double* c_out,
-                           double* gwgrad, hipStream_t s) {
-    constexpr int TX = 64, TY = 4;
+template <int TX, int TY>
+static hipError_t launch_adj_t(const KParams& P, const AdjPtrs& A, hipStream_t s) {
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
-    hipLaunchKernelGGL((k_adj_local<TX, TY>), dim3(ntx * nty), dim3(TX * TY), 0, s, P, gprev,
-                       a_in, c_in, gw, a_out, qbuf, p0buf, dpsibuf, rvec);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_gather, node_grid_adj(P), dim3(256), 0, s, P, qbuf, p0buf, dpsibuf,
-                       rvec, c_out, gwgrad);
+    hipLaunchKernelGGL((k_adj<TX, TY>), dim3(ntx * nty), dim3(TX * TY), 0, s, P, A);
+    return hipGetLastError();
+}
+
+// One reverse step. Tiles of 64 x 4 nodes, or 32 x 4 on lattices that would give fewer than 512
+// workgroups with those (more workgroups on the 256 compute units).
+hipError_t launch_adj(const KParams& P, const AdjPtrs& A, hipStream_t s) {
+    const int tiles64 = ((P.nx + 63) / 64) * ((P.y_hi - P.y_lo + 4) / 4);
+    if (tiles64 < 512) return launch_adj_t<32, 4>(P, A, s);
+    return launch_adj_t<64, 4>(P, A, s);
+}
+
+hipError_t launch_adj_gw(const KParams& P, const double* rv, double* gwgrad, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_gw, dim3((P.nx + 255) / 256), dim3(256), 0, s, P, rv, gwgrad);
     return hipGetLastError();
 }
 
@@ -235,9 +138,9 @@ hipError_t launch_loss(const KParams& P, const double* g, double* part, double* 
 }
 
 hipError_t launch_loss_seed(const KParams& P, double w_c, double w_w, double yc, double sum_phi,
-                            double* c, hipStream_t s) {
+                            double* p0, double* dpsi, hipStream_t s) {
     hipLaunchKernelGGL(k_loss_seed, node_grid_adj(P), dim3(256), 0, s, P, w_c, w_w, yc, sum_phi,
-                       c);
+                       p0, dpsi);
     return hipGetLastError();
 }
 

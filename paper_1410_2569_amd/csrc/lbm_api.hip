@@ -55,6 +55,39 @@ int create_fail(int code, const char* what, hipError_t e) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Every copy between host and device memory is one contiguous synchronous transfer made after
+// the stream's queued work has completed: pitched fields are packed or unpacked on the device
+// (k_repack) next to a dense staging copy. The host buffers of this API are ordinary pageable
+// memory; a synchronous copy is complete when it returns, and the preceding synchronisation
+// orders it after the stream's kernels (every kernel enqueued later sees it). No strided (2D)
+// copy is used: with a kernel tracer attached those have been observed not to deliver their data.
+hipError_t host_copy(hipStream_t s, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    return hipMemcpy(dst, src, bytes, kind);
+}
+
+// Dense host array [planes][rows][nx] -> device field with rows `pitch` and planes `plane`
+// doubles apart, through `stage` (device memory of planes * rows * nx doubles, free here).
+hipError_t upload_field(hipStream_t s, const double* host, int planes, int rows, int nx,
+                        double* stage, double* dst, long long plane, int pitch) {
+    hipError_t e = host_copy(s, stage, host, sizeof(double) * planes * rows * nx,
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    return lbm::launch_repack(stage, (long long)rows * nx, nx, dst, plane, pitch, nx, rows, planes,
+                              s);
+}
+
+// Device field (rows `pitch`, planes `plane` apart) -> dense host array [planes][rows][nx],
+// through `stage` (device memory of planes * rows * nx doubles, free here).
+hipError_t download_field(hipStream_t s, const double* src, long long plane, int pitch,
+                          int planes, int rows, int nx, double* stage, double* host) {
+    hipError_t e = lbm::launch_repack(src, plane, pitch, stage, (long long)rows * nx, nx, nx, rows,
+                                      planes, s);
+    if (e != hipSuccess) return e;
+    return host_copy(s, host, stage, sizeof(double) * planes * rows * nx, hipMemcpyDeviceToHost);
+}
+
 struct Layout {
     int pitch;
     long long plane;  // doubles
@@ -239,29 +272,32 @@ int maxwell_cs_impl(double a, double b, double R, double T, double* rv, double* 
 
 struct AdjLayout {
     int64_t nck;
-    size_t fbytes, pbytes;
-    size_t off_ck, off_seg, off_a, off_c, off_q, off_p0, off_dpsi, off_rv, off_gg, off_part,
-        off_fin, total;
+    size_t fbytes, pbytes, rbytes;
+    size_t off_ck, off_seg, off_a, off_q, off_p0, off_dpsi, off_rv, off_gg, off_part, off_fin,
+        total;
 };
 
+// Adjoint workspace: the checkpoints, one segment of states, then the adjoint quantities of two
+// consecutive reverse steps (a: 9 planes, q: 2 planes, p0, psi', r: 4 rows, each twice) and the
+// G_w gradient; the adjoint part is cleared at the start of every backward pass.
 AdjLayout adj_layout_of(const lbm_params* p, int64_t nsteps, int32_t K) {
     AdjLayout A;
     Layout L = layout_of(p);
     A.nck = (nsteps + K - 1) / K;
     A.fbytes = align_up((size_t)(9 * L.plane) * sizeof(double), kAlign);
     A.pbytes = align_up((size_t)L.plane * sizeof(double), kAlign);
+    A.rbytes = align_up((size_t)4 * L.pitch * sizeof(double), kAlign);
     KParams tmp{};
     tmp.nx = p->nx; tmp.ny = p->ny;
     tmp.y_lo = p->walls ? 1 : 0; tmp.y_hi = p->walls ? p->ny - 2 : p->ny - 1;
     size_t o = 0;
     A.off_ck = o; o += (size_t)A.nck * A.fbytes;
     A.off_seg = o; o += (size_t)K * A.fbytes;
-    A.off_a = o; o += 2 * A.fbytes;   // a ping-pong
-    A.off_c = o; o += 2 * A.pbytes;   // c ping-pong
-    A.off_q = o; o += 2 * A.pbytes;   // q_x, q_y
-    A.off_p0 = o; o += A.pbytes;
-    A.off_dpsi = o; o += A.pbytes;
-    A.off_rv = o; o += align_up((size_t)4 * L.pitch * sizeof(double), kAlign);
+    A.off_a = o; o += 2 * A.fbytes;
+    A.off_q = o; o += 4 * A.pbytes;
+    A.off_p0 = o; o += 2 * A.pbytes;
+    A.off_dpsi = o; o += 2 * A.pbytes;
+    A.off_rv = o; o += 2 * A.rbytes;
     A.off_gg = o; o += align_up((size_t)2 * L.pitch * sizeof(double), kAlign);
     A.off_part = o; o += align_up((size_t)lbm::loss_blocks(tmp) * 3 * sizeof(double), kAlign);
     A.off_fin = o; o += kAlign;
@@ -458,26 +494,25 @@ static int create_impl(const lbm_params* p, const uint8_t* solid, const double* 
     hipStream_t s = c->stream;
     hipError_t e;
     if ((e = lbm::launch_zero(c->ws, L.total, s)) != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create: workspace clear", e); }
+    // host arrays are staged in the second population buffer, which the first step overwrites
     if (gw_host) {
-        e = hipMemcpy2DAsync(c->gw, L.pitch * sizeof(double), gw_host, p->nx * sizeof(double),
-                             p->nx * sizeof(double), gw_rows, hipMemcpyHostToDevice, s);
+        e = upload_field(s, gw_host, 1, gw_rows, p->nx, c->g[1], c->gw, 0, L.pitch);
         if (e != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create: G_w copy", e); }
     }
     if (solid) {
         std::vector<unsigned short> lk = mask_links(p, solid, L.pitch);
         unsigned short* d_links = (unsigned short*)(c->ws + L.off_links);
-        e = hipMemcpyAsync(d_links, lk.data(), lk.size() * sizeof(unsigned short),
-                           hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);  // lk is a host temporary
+        e = host_copy(s, d_links, lk.data(), lk.size() * sizeof(unsigned short),
+                      hipMemcpyHostToDevice);
         if (e != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create: links copy", e); }
         c->kp.links = d_links;
         c->kp.gwn = c->gw;
     }
-    // stage rho0 in the second population buffer, then build the first from it
-    e = hipMemcpy2DAsync(c->g[1], L.pitch * sizeof(double), rho0_host, p->nx * sizeof(double),
-                         p->nx * sizeof(double), p->ny, hipMemcpyHostToDevice, s);
+    // rho0 into plane 1 of the second population buffer, then the first buffer built from it
+    double* rho0 = c->g[1] + L.plane;
+    e = upload_field(s, rho0_host, 1, p->ny, p->nx, c->g[1], rho0, 0, L.pitch);
     if (e != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create: rho0 copy", e); }
-    if ((e = lbm::launch_init(c->kp, c->g[1], c->g[0], s)) != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create launch_init", e); }
+    if ((e = lbm::launch_init(c->kp, rho0, c->g[0], s)) != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create launch_init", e); }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create hipStreamSynchronize", e); }
     *out = c;
     return LBM_OK;
@@ -624,9 +659,8 @@ int lbm_observables_plane(lbm_ctx* c, double x_lo, double x_hi, double y_wall, l
     e = lbm::launch_obs(P, c->g[c->cur], rho, c->psi, c->gw, A, c->part, c->fin, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "observables");
     double q[32];
-    e = hipMemcpyAsync(q, c->fin, lbm::OBS_NQ * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    e = host_copy(c->stream, q, c->fin, lbm::OBS_NQ * sizeof(double), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(c, e, "observables copy");
-    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "observables sync");
 
     obs_from_sums(q, A, c->step, out);
     return out->nonfinite ? LBM_E_NONFINITE : LBM_OK;
@@ -664,40 +698,34 @@ int lbm_observables(lbm_ctx* c, lbm_obs* out) {
     return lbm_observables_window(c, -INFINITY, INFINITY, out);
 }
 
-static int copy_field_out(lbm_ctx* c, const double* dev, int planes, double* host) {
-    const KParams& P = c->kp;
-    for (int a = 0; a < planes; ++a) {
-        hipError_t e = hipMemcpy2DAsync(host + (size_t)a * P.nx * P.ny, P.nx * sizeof(double),
-                                        dev + a * P.plane, P.pitch * sizeof(double),
-                                        P.nx * sizeof(double), P.ny, hipMemcpyDeviceToHost,
-                                        c->stream);
-        if (e != hipSuccess) return hip_fail(c, e, "copy out");
-    }
-    hipError_t e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "copy out sync");
-    return LBM_OK;
-}
-
+// Read-outs use the idle population buffer as scratch: the next step overwrites it.
 int lbm_read_rho(lbm_ctx* c, double* host, size_t count) {
     if (!c || !host) return LBM_E_INVAL;
     if (count < (size_t)c->p.nx * c->p.ny) return LBM_E_SIZE;
+    const KParams& P = c->kp;
     double* scratch = c->g[c->cur ^ 1];
-    hipError_t e = lbm::launch_zero(scratch, (size_t)c->kp.plane * sizeof(double), c->stream);
+    hipError_t e = lbm::launch_zero(scratch, (size_t)P.plane * sizeof(double), c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "read_rho memset");
-    e = lbm::launch_rho_psi(c->kp, c->g[c->cur], c->psi, scratch, c->stream);
+    e = lbm::launch_rho_psi(P, c->g[c->cur], c->psi, scratch, c->stream);
+    if (e == hipSuccess)
+        e = download_field(c->stream, scratch, P.plane, P.pitch, 1, P.ny, P.nx, scratch + P.plane,
+                           host);
     if (e != hipSuccess) return hip_fail(c, e, "read_rho");
-    return copy_field_out(c, scratch, 1, host);
+    return LBM_OK;
 }
 
 int lbm_read_f(lbm_ctx* c, double* host, size_t count) {
     if (!c || !host) return LBM_E_INVAL;
     if (count < (size_t)9 * c->p.nx * c->p.ny) return LBM_E_SIZE;
+    const KParams& P = c->kp;
     double* scratch = c->g[c->cur ^ 1];
-    hipError_t e = lbm::launch_zero(scratch, (size_t)9 * c->kp.plane * sizeof(double), c->stream);
+    const size_t n = (size_t)9 * P.nx * P.ny;
+    hipError_t e = lbm::launch_zero(scratch, n * sizeof(double), c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "read_f memset");
-    e = lbm::launch_pull(c->kp, c->g[c->cur], scratch, c->stream);
+    e = lbm::launch_pull(P, c->g[c->cur], scratch, c->stream, true);
+    if (e == hipSuccess) e = host_copy(c->stream, host, scratch, n * sizeof(double), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(c, e, "read_f");
-    return copy_field_out(c, scratch, 9, host);
+    return LBM_OK;
 }
 
 struct StateHeader {
@@ -721,7 +749,11 @@ int lbm_save_state(lbm_ctx* c, void* host, size_t bytes) {
     if (bytes < need) return LBM_E_SIZE;
     StateHeader h{kMagic, c->step, c->p.nx, c->p.ny, c->p.walls, 0};
     std::memcpy(host, &h, sizeof h);
-    return copy_field_out(c, c->g[c->cur], 9, (double*)((char*)host + sizeof h));
+    const KParams& P = c->kp;
+    hipError_t e = download_field(c->stream, c->g[c->cur], P.plane, P.pitch, 9, P.ny, P.nx,
+                                  c->g[c->cur ^ 1], (double*)((char*)host + sizeof h));
+    if (e != hipSuccess) return hip_fail(c, e, "save_state");
+    return LBM_OK;
 }
 
 int lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
@@ -735,15 +767,10 @@ int lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
         return fail(c, LBM_E_STATE, "state blob does not match this context");
     const KParams& P = c->kp;
     const double* src = (const double*)((const char*)host + sizeof h);
-    for (int a = 0; a < 9; ++a) {
-        hipError_t e = hipMemcpy2DAsync(c->g[c->cur] + a * P.plane, P.pitch * sizeof(double),
-                                        src + (size_t)a * P.nx * P.ny, P.nx * sizeof(double),
-                                        P.nx * sizeof(double), P.ny, hipMemcpyHostToDevice,
-                                        c->stream);
-        if (e != hipSuccess) return hip_fail(c, e, "load_state");
-    }
-    hipError_t e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "load_state sync");
+    hipError_t e = upload_field(c->stream, src, 9, P.ny, P.nx, c->g[c->cur ^ 1], c->g[c->cur],
+                                P.plane, P.pitch);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "load_state");
     c->step = h.step;
     return LBM_OK;
 }
@@ -753,11 +780,10 @@ int lbm_set_gw(lbm_ctx* c, const double* gw_host) {
     const int rows = c->kp.mask ? c->p.ny : 2;
     for (long long i = 0; i < (long long)rows * c->p.nx; ++i)
         if (!std::isfinite(gw_host[i])) return fail(c, LBM_E_INVAL, "non-finite G_w");
-    hipError_t e = hipMemcpy2DAsync(c->gw, c->kp.pitch * sizeof(double), gw_host,
-                                    c->p.nx * sizeof(double), c->p.nx * sizeof(double), rows,
-                                    hipMemcpyHostToDevice, c->stream);
+    hipError_t e = upload_field(c->stream, gw_host, 1, rows, c->p.nx, c->g[c->cur ^ 1], c->gw, 0,
+                                c->kp.pitch);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "set_gw");
-    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "set_gw sync");
     return LBM_OK;
 }
 
@@ -776,9 +802,8 @@ int lbm_adjoint_workspace_size(const lbm_params* p, int64_t nsteps, int32_t K, s
 static int run_loss(lbm_ctx* c, double* sums) {
     hipError_t e = lbm::launch_loss(c->kp, c->g[c->cur], c->part, c->fin, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "loss");
-    e = hipMemcpyAsync(sums, c->fin, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    e = host_copy(c->stream, sums, c->fin, 3 * sizeof(double), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(c, e, "loss copy");
-    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "loss sync");
     return LBM_OK;
 }
 
@@ -836,46 +861,39 @@ int lbm_backward(lbm_ctx* c, int64_t nsteps, int32_t K, void* d_adj, size_t byte
     const double yc = sums[1] / sums[0];
     if (!std::isfinite(yc)) return fail(c, LBM_E_NONFINITE, "non-finite loss");
     double* a_buf[2] = {(double*)(w + A.off_a), (double*)(w + A.off_a + A.fbytes)};
-    double* c_buf[2] = {(double*)(w + A.off_c), (double*)(w + A.off_c + A.pbytes)};
-    double* q = (double*)(w + A.off_q);
-    double* p0 = (double*)(w + A.off_p0);
-    double* dpsi = (double*)(w + A.off_dpsi);
-    double* rv = (double*)(w + A.off_rv);
+    double* q_buf[2] = {(double*)(w + A.off_q), (double*)(w + A.off_q + 2 * A.pbytes)};
+    double* p0_buf[2] = {(double*)(w + A.off_p0), (double*)(w + A.off_p0 + A.pbytes)};
+    double* dpsi_buf[2] = {(double*)(w + A.off_dpsi), (double*)(w + A.off_dpsi + A.pbytes)};
+    double* rv_buf[2] = {(double*)(w + A.off_rv), (double*)(w + A.off_rv + A.rbytes)};
     double* gg = (double*)(w + A.off_gg);
-    if ((e = lbm::launch_loss_seed(P, w_centroid, w_wet, yc, sums[0], c_buf[0], s)) != hipSuccess)
-        return hip_fail(c, e, "loss seed");
-    int ca = 0;
+    e = lbm::launch_loss_seed(P, w_centroid, w_wet, yc, sums[0], p0_buf[0], dpsi_buf[0], s);
+    if (e != hipSuccess) return hip_fail(c, e, "loss seed");
+    int k = 0;  // buffers of the later step
     for (int64_t j = A.nck - 1; j >= 0; --j) {
-        const int64_t k0 = j * K;
-        const int64_t len = std::min<int64_t>(K, nsteps - k0);
-        char* seg = w + A.off_seg;
-        e = hipMemcpyAsync(seg, w + A.off_ck + (size_t)j * A.fbytes, fb, hipMemcpyDeviceToDevice, s);
+        const int64_t len = std::min<int64_t>(K, nsteps - j * K);
+        auto seg = [&](int64_t i) { return (double*)(w + A.off_seg + (size_t)i * A.fbytes); };
+        e = hipMemcpyAsync(seg(0), w + A.off_ck + (size_t)j * A.fbytes, fb, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return hip_fail(c, e, "segment restore");
-        // recompute the segment's states, then its adjoint steps in reverse
-        const int ca0 = ca;
-        auto segment = [&](hipStream_t st) -> hipError_t {
-            hipError_t r;
-            for (int64_t i = 0; i + 1 < len; ++i) {
-                r = lbm::launch_step(P, c->schedule == 1 ? 1 : 0, c->tile,
-                                     (const double*)(seg + i * A.fbytes),
-                                     (double*)(seg + (i + 1) * A.fbytes), c->psi, c->gw, st);
-                if (r != hipSuccess) return r;
-            }
-            int k = ca0;
-            for (int64_t i = len - 1; i >= 0; --i) {
-                r = lbm::launch_adj_step(P, (const double*)(seg + i * A.fbytes), a_buf[k], c_buf[k],
-                                         c->gw, a_buf[k ^ 1], q, p0, dpsi, rv, c_buf[k ^ 1], gg, st);
-                if (r != hipSuccess) return r;
-                k ^= 1;
-            }
-            return hipSuccess;
-        };
-        e = segment(s);
-        if (e != hipSuccess) return hip_fail(c, e, "adjoint segment");
-        ca = ca0 ^ (int)(len & 1);
+        // recompute the segment's states, two steps per launch (the first one written too)
+        int64_t i = 0;
+        for (; i + 2 <= len - 1 && e == hipSuccess; i += 2)
+            e = lbm::launch_step2(P, c->tile2, seg(i), seg(i + 2), c->gw, s, seg(i + 1));
+        if (i + 1 <= len - 1 && e == hipSuccess)
+            e = lbm::launch_step(P, 0, c->tile, seg(i), seg(i + 1), c->psi, c->gw, s);
+        if (e != hipSuccess) return hip_fail(c, e, "segment recompute");
+        // then its adjoint steps in reverse
+        for (i = len - 1; i >= 0; --i) {
+            lbm::AdjPtrs ap{seg(i),       a_buf[k],     q_buf[k],     p0_buf[k],
+                            dpsi_buf[k],  rv_buf[k],    c->gw,        a_buf[k ^ 1],
+                            q_buf[k ^ 1], p0_buf[k ^ 1], dpsi_buf[k ^ 1], rv_buf[k ^ 1], gg};
+            e = lbm::launch_adj(P, ap, s);
+            if (e != hipSuccess) return hip_fail(c, e, "adjoint step");
+            k ^= 1;
+        }
     }
-    e = hipMemcpy2DAsync(d_grad_gw, P.nx * sizeof(double), gg, P.pitch * sizeof(double),
-                         P.nx * sizeof(double), 2, hipMemcpyDeviceToDevice, s);
+    e = lbm::launch_adj_gw(P, rv_buf[k], gg, s);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint wall gradient");
+    e = lbm::launch_repack(gg, 0, P.pitch, d_grad_gw, 0, P.nx, P.nx, 2, 1, s);
     if (e != hipSuccess) return hip_fail(c, e, "gradient copy");
     return LBM_OK;
 }
@@ -893,7 +911,7 @@ struct lbm_batch {
     size_t bytes;
     lbm::InstDesc* d_inst;
     int* d_tile_inst;
-    unsigned* d_bar;
+    unsigned long long* d_bar;  // grid-barrier arrival counter of the persistent schedule
     int* d_flag;
     std::vector<double*> psi, part, fin;
     int ntiles;
@@ -909,6 +927,10 @@ struct lbm_batch {
     hipGraphExec_t pgraph;    // persistent schedule: reset + persistent kernel for pgraph_n steps
     int64_t pgraph_n;
     int pgraph_cur;
+    // last lbm_batch_forward_ckpt: where it started, its length and checkpoint interval
+    int64_t adj_start, adj_nsteps;
+    int32_t adj_K;
+    const void* adj_ws;
     std::string err;
 };
 
@@ -1021,7 +1043,7 @@ static int batch_create_impl(const lbm_params* p, int32_t count,
     b->bytes = bytes;
     b->d_inst = (lbm::InstDesc*)(b->ws + B.off_desc);
     b->d_tile_inst = (int*)(b->ws + B.off_tiles);
-    b->d_bar = (unsigned*)(b->ws + B.off_bar);
+    b->d_bar = (unsigned long long*)(b->ws + B.off_bar);
     b->d_flag = (int*)(b->ws + B.off_bar + 64);
     b->ntiles = B.ntiles;
     b->geo = solid_host ? lbm::GEO_MASK : lbm::GEO_ROWS;
@@ -1038,6 +1060,10 @@ static int batch_create_impl(const lbm_params* p, int32_t count,
     b->pgraph = nullptr;
     b->pgraph_n = -1;
     b->pgraph_cur = -1;
+    b->adj_start = -1;
+    b->adj_nsteps = 0;
+    b->adj_K = 0;
+    b->adj_ws = nullptr;
     hipStream_t s = b->stream;
     hipError_t e = lbm::launch_zero(b->ws, B.total, s);
     if (e != hipSuccess) { delete b; return create_fail(LBM_E_HIP, "create: workspace clear", e); }
@@ -1071,16 +1097,14 @@ static int batch_create_impl(const lbm_params* p, int32_t count,
         if (gw_host[i]) {
             for (long long k = 0; k < (long long)gw_rows * p[i].nx; ++k)
                 if (!std::isfinite(gw_host[i][k])) { delete b; return LBM_E_INVAL; }
-            e = hipMemcpy2DAsync(d.gw, L.pitch * sizeof(double), gw_host[i],
-                                 p[i].nx * sizeof(double), p[i].nx * sizeof(double), gw_rows,
-                                 hipMemcpyHostToDevice, s);
+            e = upload_field(s, gw_host[i], 1, gw_rows, p[i].nx, d.g[1], d.gw, 0, L.pitch);
             if (e != hipSuccess) { delete b; return create_fail(LBM_E_HIP, "create: G_w copy", e); }
         }
         if (solid) {
             links[i] = mask_links(&p[i], solid, L.pitch);
             unsigned short* dl = (unsigned short*)(base + L.off_links);
-            e = hipMemcpyAsync(dl, links[i].data(), links[i].size() * sizeof(unsigned short),
-                               hipMemcpyHostToDevice, s);
+            e = host_copy(s, dl, links[i].data(), links[i].size() * sizeof(unsigned short),
+                          hipMemcpyHostToDevice);
             if (e != hipSuccess) { delete b; return create_fail(LBM_E_HIP, "create: links copy", e); }
             kp.links = dl;
             kp.gwn = d.gw;
@@ -1088,17 +1112,16 @@ static int batch_create_impl(const lbm_params* p, int32_t count,
             b->kp.back() = kp;
             b->desc.back() = d;
         }
-        e = hipMemcpy2DAsync(d.g[1], L.pitch * sizeof(double), rho0_host[i],
-                             p[i].nx * sizeof(double), p[i].nx * sizeof(double), p[i].ny,
-                             hipMemcpyHostToDevice, s);
+        double* rho0 = d.g[1] + L.plane;
+        e = upload_field(s, rho0_host[i], 1, p[i].ny, p[i].nx, d.g[1], rho0, 0, L.pitch);
         if (e != hipSuccess) { delete b; return create_fail(LBM_E_HIP, "create: rho0 copy", e); }
-        if ((e = lbm::launch_init(kp, d.g[1], d.g[0], s)) != hipSuccess) { delete b; return create_fail(LBM_E_HIP, "create launch_init", e); }
+        if ((e = lbm::launch_init(kp, rho0, d.g[0], s)) != hipSuccess) { delete b; return create_fail(LBM_E_HIP, "create launch_init", e); }
     }
-    e = hipMemcpyAsync(b->d_inst, b->desc.data(), count * sizeof(lbm::InstDesc),
-                       hipMemcpyHostToDevice, s);
+    e = host_copy(s, b->d_inst, b->desc.data(), count * sizeof(lbm::InstDesc),
+                  hipMemcpyHostToDevice);
     if (e != hipSuccess) { delete b; return create_fail(LBM_E_HIP, "create: descriptor copy", e); }
-    e = hipMemcpyAsync(b->d_tile_inst, tile_inst.data(), B.ntiles * sizeof(int),
-                       hipMemcpyHostToDevice, s);
+    e = host_copy(s, b->d_tile_inst, tile_inst.data(), B.ntiles * sizeof(int),
+                  hipMemcpyHostToDevice);
     if (e != hipSuccess) { delete b; return create_fail(LBM_E_HIP, "create: tile table copy", e); }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) { delete b; return create_fail(LBM_E_HIP, "create hipStreamSynchronize", e); }
     // persistent grid: co-resident workgroups only (occupancy x compute units)
@@ -1187,12 +1210,21 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
     if (n == 0) return LBM_OK;
     (void)hipGetLastError();
     if (b->tune.schedule == 1) {
+        // one launch of n / 2 two-step passes, and a per-step launch for an odd last step
         if (n > (int64_t)1 << 30) return batch_fail(b, LBM_E_INVAL, "too many steps in one call");
         const int cur = b->cur;
+        const int npairs = (int)(n / 2);
         auto persistent = [&]() {
-            return lbm::launch_batch_persistent(b->tune.tile, b->geo, b->eos, b->grid, b->d_inst,
-                                                b->d_tile_inst, b->ntiles, (int)n, cur, b->d_bar,
-                                                b->d_flag, kSpinLimit, b->stream);
+            hipError_t e = hipSuccess;
+            if (npairs > 0)
+                e = lbm::launch_batch_persistent(b->tune.tile, b->geo, b->eos, b->grid, b->d_inst,
+                                                 b->d_tile_inst, b->ntiles, npairs, cur, b->d_bar,
+                                                 b->d_flag, kSpinLimit, b->stream);
+            if (e == hipSuccess && (n & 1))
+                e = lbm::launch_batch_step(b->tune.tile, b->geo, b->eos, b->d_inst,
+                                           b->d_tile_inst, b->ntiles, cur ^ (npairs & 1),
+                                           b->stream);
+            return e;
         };
         if (!b->pgraph || b->pgraph_n != n || b->pgraph_cur != cur) {
             if (b->pgraph) { (void)hipGraphExecDestroy(b->pgraph); b->pgraph = nullptr; }
@@ -1203,7 +1235,7 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
         }
         hipError_t e = b->pgraph ? hipGraphLaunch(b->pgraph, b->stream) : persistent();
         if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "persistent launch");
-        b->cur ^= (int)(n & 1);
+        b->cur ^= (npairs & 1) ^ (int)(n & 1);
         b->step += n;
         return LBM_OK;
     }
@@ -1236,8 +1268,7 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
 
 static int batch_check_abort(lbm_batch* b) {
     int flag = 0;
-    hipError_t e = hipMemcpyAsync(&flag, b->d_flag, sizeof(int), hipMemcpyDeviceToHost, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    hipError_t e = host_copy(b->stream, &flag, b->d_flag, sizeof(int), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "flag read");
     if (flag) return batch_fail(b, LBM_E_HIP, "grid barrier timed out: workgroups not co-resident");
     return LBM_OK;
@@ -1269,8 +1300,8 @@ int lbm_batch_observables_plane(lbm_batch* b, const double* y_wall, lbm_obs* out
             e = lbm::launch_obs(P, d.g[b->cur], rho, b->psi[i], d.gw, A, b->part[i], b->fin[i],
                                 b->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(q.data() + (size_t)i * 32, b->fin[i], lbm::OBS_NQ * sizeof(double),
-                               hipMemcpyDeviceToHost, b->stream);
+            e = host_copy(b->stream, q.data() + (size_t)i * 32, b->fin[i],
+                          lbm::OBS_NQ * sizeof(double), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "batch observables");
     }
     hipError_t e = hipStreamSynchronize(b->stream);
@@ -1299,9 +1330,8 @@ int lbm_batch_record_contact_line(lbm_batch* b, int64_t n, int32_t every, const 
     if (rc) return rc;
     (void)hipGetLastError();
     b->rows.assign(rows, rows + b->count);  // kept alive for the asynchronous copy
-    hipError_t e = hipMemcpyAsync(b->d_rows, b->rows.data(), b->count * sizeof(int),
-                                  hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    hipError_t e = host_copy(b->stream, b->d_rows, b->rows.data(), b->count * sizeof(int),
+                             hipMemcpyHostToDevice);
     if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "record rows");
     for (size_t k = 0; k < samples; ++k) {
         if (k) {
@@ -1322,14 +1352,11 @@ int lbm_batch_read_f(lbm_batch* b, int32_t index, double* host, size_t count) {
     const KParams& P = b->kp[index];
     if (count < (size_t)9 * P.nx * P.ny) return LBM_E_SIZE;
     const lbm::InstDesc& d = b->desc[index];
-    double* scratch = d.g[b->cur ^ 1];
-    hipError_t e = lbm::launch_zero(scratch, (size_t)9 * P.plane * sizeof(double), b->stream);
-    if (e == hipSuccess) e = lbm::launch_pull(P, d.g[b->cur], scratch, b->stream);
-    for (int a = 0; a < 9 && e == hipSuccess; ++a)
-        e = hipMemcpy2DAsync(host + (size_t)a * P.nx * P.ny, P.nx * sizeof(double),
-                             scratch + a * P.plane, P.pitch * sizeof(double),
-                             P.nx * sizeof(double), P.ny, hipMemcpyDeviceToHost, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    double* scratch = d.g[b->cur ^ 1];  // the idle buffer: the next step overwrites it
+    const size_t n = (size_t)9 * P.nx * P.ny;
+    hipError_t e = lbm::launch_zero(scratch, n * sizeof(double), b->stream);
+    if (e == hipSuccess) e = lbm::launch_pull(P, d.g[b->cur], scratch, b->stream, true);
+    if (e == hipSuccess) e = host_copy(b->stream, host, scratch, n * sizeof(double), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "batch read");
     return LBM_OK;
 }
@@ -1346,12 +1373,8 @@ int lbm_batch_save_state(lbm_batch* b, int32_t index, void* host, size_t bytes) 
     std::memcpy(host, &h, sizeof h);
     double* dst = (double*)((char*)host + sizeof h);
     const lbm::InstDesc& d = b->desc[index];
-    hipError_t e = hipSuccess;
-    for (int a = 0; a < 9 && e == hipSuccess; ++a)
-        e = hipMemcpy2DAsync(dst + (size_t)a * P.nx * P.ny, P.nx * sizeof(double),
-                             d.g[b->cur] + a * P.plane, P.pitch * sizeof(double),
-                             P.nx * sizeof(double), P.ny, hipMemcpyDeviceToHost, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    hipError_t e = download_field(b->stream, d.g[b->cur], P.plane, P.pitch, 9, P.ny, P.nx,
+                                  d.g[b->cur ^ 1], dst);
     if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "batch save state");
     return LBM_OK;
 }
@@ -1362,6 +1385,204 @@ int lbm_batch_get_tune(const lbm_batch* b, lbm_tune* t, int32_t* grid) {
     if (!b || !t) return LBM_E_INVAL;
     *t = b->tune;
     if (grid) *grid = b->grid;
+    return LBM_OK;
+}
+
+// ---- ensemble adjoint --------------------------------------------------------------------------
+
+namespace {
+
+// Adjoint workspace of an ensemble: the instance table and the work-list of 64 x 4 tiles, then per
+// instance the single-lattice adjoint layout (checkpoints, segment, adjoint buffers, gradient).
+struct BatchAdjLayout {
+    size_t off_inst, off_tiles, total;
+    std::vector<size_t> off;
+    std::vector<AdjLayout> A;
+    std::vector<int> tile0, ntx, nty;
+    int ntiles;
+};
+
+int batch_adj_layout(const lbm_batch* b, int64_t nsteps, int32_t K, BatchAdjLayout* L) {
+    if (nsteps < 1 || K < 1) return LBM_E_INVAL;
+    for (int i = 0; i < b->count; ++i)
+        if (b->p[i].walls != LBM_WALLS_BOUNCE_BACK) return LBM_E_INVAL;
+    size_t o = 0;
+    L->off_inst = o;
+    o += align_up((size_t)b->count * sizeof(lbm::AdjInst), kAlign);
+    long long nt = 0;
+    L->tile0.resize(b->count); L->ntx.resize(b->count); L->nty.resize(b->count);
+    L->A.resize(b->count); L->off.resize(b->count);
+    for (int i = 0; i < b->count; ++i) {
+        const KParams& P = b->kp[i];
+        L->ntx[i] = (P.nx + 63) / 64;
+        L->nty[i] = (P.y_hi - P.y_lo + 4) / 4;
+        L->tile0[i] = (int)nt;
+        nt += (long long)L->ntx[i] * L->nty[i];
+    }
+    if (nt > (1LL << 30)) return LBM_E_INVAL;
+    L->ntiles = (int)nt;
+    L->off_tiles = o;
+    o += align_up((size_t)nt * sizeof(int), kAlign);
+    for (int i = 0; i < b->count; ++i) {
+        L->A[i] = adj_layout_of(&b->p[i], nsteps, K);
+        L->off[i] = o;
+        o += L->A[i].total;
+    }
+    L->total = o;
+    return LBM_OK;
+}
+
+}  // namespace
+
+int lbm_batch_adjoint_workspace_size(const lbm_batch* b, int64_t nsteps, int32_t K,
+                                     size_t* bytes) {
+    if (!b || !bytes) return LBM_E_INVAL;
+    BatchAdjLayout L;
+    int rc = batch_adj_layout(b, nsteps, K, &L);
+    if (rc) return rc;
+    *bytes = L.total;
+    return LBM_OK;
+}
+
+int lbm_batch_forward_ckpt(lbm_batch* b, int64_t nsteps, int32_t K, void* d_adj, size_t bytes) {
+    if (!b || !d_adj) return LBM_E_INVAL;
+    BatchAdjLayout L;
+    int rc = batch_adj_layout(b, nsteps, K, &L);
+    if (rc) return batch_fail(b, rc, "ensemble adjoint: bounce-back walls only, nsteps, K >= 1");
+    if (bytes < L.total) return batch_fail(b, LBM_E_SIZE, "adjoint workspace too small");
+    if (((uintptr_t)d_adj) % kAlign) return batch_fail(b, LBM_E_INVAL, "adjoint workspace misaligned");
+    (void)hipGetLastError();
+    char* w = (char*)d_adj;
+    b->adj_start = b->step;
+    b->adj_nsteps = nsteps;
+    b->adj_K = K;
+    b->adj_ws = d_adj;
+    for (int64_t i = 0; i < nsteps; i += K) {
+        for (int k = 0; k < b->count; ++k) {
+            const size_t fb = (size_t)9 * b->kp[k].plane * sizeof(double);
+            hipError_t e = hipMemcpyAsync(w + L.off[k] + L.A[k].off_ck + (size_t)(i / K) * L.A[k].fbytes,
+                                          b->desc[k].g[b->cur], fb, hipMemcpyDeviceToDevice,
+                                          b->stream);
+            if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "checkpoint");
+        }
+        rc = lbm_batch_step(b, std::min<int64_t>(K, nsteps - i));
+        if (rc) return rc;
+    }
+    return LBM_OK;
+}
+
+// Loss sums (sum phi, sum phi (y - 1/2), sum_x phi(x, 1)) of instance i's current state.
+static int batch_loss_sums(lbm_batch* b, int i, double* sums) {
+    hipError_t e = lbm::launch_loss(b->kp[i], b->desc[i].g[b->cur], b->part[i], b->fin[i],
+                                    b->stream);
+    if (e == hipSuccess) e = host_copy(b->stream, sums, b->fin[i], 3 * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "ensemble loss");
+    return LBM_OK;
+}
+
+int lbm_batch_loss(lbm_batch* b, double w_centroid, double w_wet, double* L) {
+    if (!b || !L) return LBM_E_INVAL;
+    for (int i = 0; i < b->count; ++i)
+        if (b->p[i].walls != LBM_WALLS_BOUNCE_BACK) return LBM_E_INVAL;
+    int rc = batch_check_abort(b);
+    if (rc) return rc;
+    int bad = 0;
+    for (int i = 0; i < b->count; ++i) {
+        double s[3];
+        if ((rc = batch_loss_sums(b, i, s))) return rc;
+        L[i] = w_centroid * s[1] / s[0] + w_wet * s[2];
+        bad |= !std::isfinite(L[i]);
+    }
+    return bad ? batch_fail(b, LBM_E_NONFINITE, "non-finite loss") : LBM_OK;
+}
+
+int lbm_batch_backward(lbm_batch* b, int64_t nsteps, int32_t K, void* d_adj, size_t bytes,
+                       double w_centroid, double w_wet, double* d_grad_gw) {
+    if (!b || !d_adj || !d_grad_gw) return LBM_E_INVAL;
+    BatchAdjLayout L;
+    int rc = batch_adj_layout(b, nsteps, K, &L);
+    if (rc) return batch_fail(b, rc, "ensemble adjoint: bounce-back walls only, nsteps, K >= 1");
+    if (bytes < L.total) return batch_fail(b, LBM_E_SIZE, "adjoint workspace too small");
+    if (b->adj_ws != d_adj || b->adj_nsteps != nsteps || b->adj_K != K ||
+        b->step != b->adj_start + nsteps)
+        return batch_fail(b, LBM_E_STATE, "backward does not follow the matching forward_ckpt");
+    if ((rc = batch_check_abort(b))) return rc;
+    (void)hipGetLastError();
+    hipStream_t s = b->stream;
+    char* w = (char*)d_adj;
+    // instance table and work-list
+    std::vector<lbm::AdjInst> inst(b->count);
+    std::vector<int> tile_inst(L.ntiles);
+    int max_nx = 0;
+    for (int i = 0; i < b->count; ++i) {
+        const AdjLayout& A = L.A[i];
+        char* base = w + L.off[i];
+        lbm::AdjInst& d = inst[i];
+        d = lbm::AdjInst{};
+        d.P = b->kp[i];
+        d.seg = (double*)(base + A.off_seg);
+        d.fstride = (long long)(A.fbytes / sizeof(double));
+        for (int k = 0; k < 2; ++k) {
+            d.a[k] = (double*)(base + A.off_a + k * A.fbytes);
+            d.q[k] = (double*)(base + A.off_q + 2 * k * A.pbytes);
+            d.p0[k] = (double*)(base + A.off_p0 + k * A.pbytes);
+            d.dpsi[k] = (double*)(base + A.off_dpsi + k * A.pbytes);
+            d.rv[k] = (double*)(base + A.off_rv + k * A.rbytes);
+        }
+        d.gw = b->desc[i].gw;
+        d.gg = (double*)(base + A.off_gg);
+        d.tile0 = L.tile0[i];
+        d.ntx = L.ntx[i];
+        d.nty = L.nty[i];
+        for (int t = 0; t < L.ntx[i] * L.nty[i]; ++t) tile_inst[L.tile0[i] + t] = i;
+        max_nx = std::max(max_nx, d.P.nx);
+        hipError_t e = lbm::launch_zero(base + A.off_a, A.total - A.off_a, s);
+        if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "adjoint clear");
+    }
+    lbm::AdjInst* d_inst = (lbm::AdjInst*)(w + L.off_inst);
+    int* d_tiles = (int*)(w + L.off_tiles);
+    hipError_t e = host_copy(s, d_inst, inst.data(), inst.size() * sizeof(lbm::AdjInst),
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = host_copy(s, d_tiles, tile_inst.data(), tile_inst.size() * sizeof(int),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "adjoint tables");
+    // the objective of every instance seeds its adjoint
+    for (int i = 0; i < b->count; ++i) {
+        double sums[3];
+        if ((rc = batch_loss_sums(b, i, sums))) return rc;
+        const double yc = sums[1] / sums[0];
+        if (!std::isfinite(yc)) return batch_fail(b, LBM_E_NONFINITE, "non-finite loss");
+        e = lbm::launch_loss_seed(b->kp[i], w_centroid, w_wet, yc, sums[0], inst[i].p0[0],
+                                  inst[i].dpsi[0], s);
+        if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "loss seed");
+    }
+    const int64_t nck = (nsteps + K - 1) / K;
+    int k = 0;  // buffers of the later step
+    for (int64_t j = nck - 1; j >= 0; --j) {
+        const int64_t len = std::min<int64_t>(K, nsteps - j * K);
+        for (int i = 0; i < b->count && e == hipSuccess; ++i)
+            e = hipMemcpyAsync(inst[i].seg, w + L.off[i] + L.A[i].off_ck + (size_t)j * L.A[i].fbytes,
+                               (size_t)9 * b->kp[i].plane * sizeof(double), hipMemcpyDeviceToDevice, s);
+        int64_t i = 0;
+        for (; i + 2 <= len - 1 && e == hipSuccess; i += 2)
+            e = lbm::launch_batch_seg_step2(b->eos, d_inst, d_tiles, L.ntiles, (int)i, s);
+        if (i + 1 <= len - 1 && e == hipSuccess)
+            e = lbm::launch_batch_seg_step(b->eos, d_inst, d_tiles, L.ntiles, (int)i, s);
+        for (i = len - 1; i >= 0 && e == hipSuccess; --i) {
+            e = lbm::launch_batch_adj(d_inst, d_tiles, L.ntiles, (int)i, k, s);
+            k ^= 1;
+        }
+        if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "ensemble adjoint segment");
+    }
+    e = lbm::launch_batch_adj_gw(d_inst, b->count, max_nx, k, s);
+    size_t off = 0;
+    for (int i = 0; i < b->count && e == hipSuccess; ++i) {
+        const KParams& P = b->kp[i];
+        e = lbm::launch_repack(inst[i].gg, 0, P.pitch, d_grad_gw + off, 0, P.nx, P.nx, 2, 1, s);
+        off += (size_t)2 * P.nx;
+    }
+    if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "ensemble adjoint gradient");
     return LBM_OK;
 }
 

@@ -4,9 +4,11 @@
 // device function as the single-instance step (so results are bitwise identical to it):
 //   per-step   one launch per time step over the whole work-list (replayed from a hipGraph);
 //   persistent one launch for n steps: an occupancy-sized grid in which each workgroup owns a
-//              contiguous chunk of the work-list (contiguous per XCD), with a grid barrier
-//              between steps. The barrier publishes the step's stores at agent scope (release),
-//              waits for every workgroup, then acquires; its wait is bounded and raises an abort
+//              contiguous chunk of the work-list (contiguous per XCD) and advances each of its
+//              tiles two steps (step2_tile), with a grid barrier between the two-step passes (an
+//              odd last step is one per-step launch after it). The barrier publishes the pass's
+//              stores at agent scope (release), waits for every workgroup, then acquires; its
+//              64-bit arrival counter cannot wrap, and its wait is bounded and raises an abort
 //              flag on timeout so every workgroup always exits.
 #include <algorithm>
 #include <type_traits>
@@ -43,7 +45,7 @@ template <int TX, int TY, int GEO, int EOS>
 __global__
 __launch_bounds__(step2_threads(TX, TY, GEO), step2_waves(TX, TY, GEO)) void k_batch_step2(
     const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, int ntiles, int cur) {
-    __shared__ Step2Lds<TX, TY, GEO == GEO_MASK> lds;
+    __shared__ Step2Lds<TX, TY, GEO> lds;
     const int t = xcd_tile(blockIdx.x, ntiles);
     const InstDesc* D = inst + tile_inst[t];
     int x0, y0;
@@ -51,13 +53,14 @@ __launch_bounds__(step2_threads(TX, TY, GEO), step2_waves(TX, TY, GEO)) void k_b
     step2_tile_any<TX, TY, GEO, EOS>(D->P, D->g[cur], D->g[cur ^ 1], D->gw, x0, y0, lds);
 }
 
-// Grid-wide barrier number `target / gridDim.x`. Returns false when the run was aborted.
-__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, int* flag,
-                                             int spin_limit, int* verdict) {
-    __syncthreads();  // every wave's stores of this step have completed
+// Grid-wide barrier number `target / gridDim.x` on a 64-bit arrival counter. Returns false when
+// the run was aborted.
+__device__ __forceinline__ bool grid_barrier(unsigned long long* bar, unsigned long long target,
+                                             int* flag, int spin_limit, int* verdict) {
+    __syncthreads();  // every wave's stores of this pass have completed
     if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int ok = 1;
         for (int n = 0;; ++n) {
             if (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
@@ -80,29 +83,33 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, int
     return *verdict != 0;
 }
 
+// npairs two-step passes over the work-list in one launch (the tiles are the output tiles of
+// step2_tile, as in k_batch_step2).
 template <int TX, int TY, int GEO, int EOS>
-__global__ __launch_bounds__(TX* TY) void k_batch_persistent(const InstDesc* __restrict__ inst,
-                                                             const int* __restrict__ tile_inst,
-                                                             int ntiles, int nsteps, int cur0,
-                                                             unsigned* bar, int* flag,
-                                                             int spin_limit) {
-    __shared__ double sp[(TY + 2) * (TX + 2)];
+__global__ __launch_bounds__(step2_threads(TX, TY, GEO), step2_waves(TX, TY, GEO)) void
+k_batch_persistent(const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst,
+                   int ntiles, int npairs, int cur0, unsigned long long* bar, int* flag,
+                   int spin_limit) {
+    __shared__ Step2Lds<TX, TY, GEO> lds;
     __shared__ int verdict;
     const int G = gridDim.x;
     const int L = xcd_tile(blockIdx.x, G);
     const int t_lo = (int)((long long)L * ntiles / G);
     const int t_hi = (int)((long long)(L + 1) * ntiles / G);
-    for (int s = 0; s < nsteps; ++s) {
-        const int cur = (cur0 + s) & 1;
+    // each pass reads g[cur0] and writes g[cur0 ^ 1] (two steps), then the two swap roles
+    for (int k = 0; k < npairs; ++k) {
         for (int t = t_lo; t < t_hi; ++t) {
             const InstDesc* D = inst + tile_inst[t];
             int x0, y0;
             batch_tile_origin(D, t, TX, TY, x0, y0);
-            step_tile<TX, TY, true, GEO, EOS>(D->P, D->g[cur], D->g[cur ^ 1], nullptr, D->gw, x0,
-                                              y0, sp);
+            step2_tile_any<TX, TY, GEO, EOS>(D->P, D->g[cur0], D->g[cur0 ^ 1], D->gw, x0, y0,
+                                             lds);
             __syncthreads();  // the LDS tile is reused by the next tile
         }
-        if (!grid_barrier(bar, (unsigned)(s + 1) * (unsigned)G, flag, spin_limit, &verdict)) return;
+        if (!grid_barrier(bar, (unsigned long long)(k + 1) * (unsigned long long)G, flag,
+                          spin_limit, &verdict))
+            return;
+        cur0 ^= 1;
     }
 }
 
@@ -114,11 +121,72 @@ __global__ __launch_bounds__(256) void k_batch_contact_line(const InstDesc* __re
     contact_line_block(D->P, D->g[cur], rows[blockIdx.x], D->P.rho_mid, out + 2 * blockIdx.x);
 }
 
+// ---- ensemble adjoint ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void adj_tile_origin(const AdjInst* D, int t, int& x0, int& y0) {
+    const int lt = t - D->tile0;
+    x0 = (lt % D->ntx) * 64;
+    y0 = D->P.y_lo + (lt / D->ntx) * 4;
+}
+
+// Segment states i -> i+1, i+2 of every instance (two steps per launch, the first written too).
+template <int EOS>
+__global__ __launch_bounds__(step2_threads(64, 4, GEO_ROWS), step2_waves(64, 4, GEO_ROWS)) void
+k_batch_seg_step2(const AdjInst* __restrict__ inst, const int* __restrict__ tile_inst, int ntiles,
+                  int i) {
+    __shared__ Step2Lds<64, 4, GEO_ROWS> lds;
+    const int t = xcd_tile(blockIdx.x, ntiles);
+    const AdjInst* D = inst + tile_inst[t];
+    int x0, y0;
+    adj_tile_origin(D, t, x0, y0);
+    double* s0 = D->seg + (long long)i * D->fstride;
+    step2_tile_any<64, 4, GEO_ROWS, EOS, true>(D->P, s0, s0 + 2 * D->fstride, D->gw, x0, y0, lds,
+                                               s0 + D->fstride);
+}
+
+// Segment state i -> i+1 of every instance (one fused step).
+template <int EOS>
+__global__ __launch_bounds__(256) void k_batch_seg_step(const AdjInst* __restrict__ inst,
+                                                        const int* __restrict__ tile_inst,
+                                                        int ntiles, int i) {
+    __shared__ double sp[6 * 66];
+    const int t = xcd_tile(blockIdx.x, ntiles);
+    const AdjInst* D = inst + tile_inst[t];
+    int x0, y0;
+    adj_tile_origin(D, t, x0, y0);
+    double* s0 = D->seg + (long long)i * D->fstride;
+    step_tile<64, 4, true, GEO_ROWS, EOS>(D->P, s0, s0 + D->fstride, nullptr, D->gw, x0, y0, sp);
+}
+
+// One reverse step of every instance: segment state i, later-step buffers of parity k.
+__global__ __launch_bounds__(256) void k_batch_adj(const AdjInst* __restrict__ inst,
+                                                   const int* __restrict__ tile_inst, int ntiles,
+                                                   int i, int k) {
+    __shared__ AdjLds<64, 4> lds;
+    const int t = xcd_tile(blockIdx.x, ntiles);
+    const AdjInst* D = inst + tile_inst[t];
+    int x0, y0;
+    adj_tile_origin(D, t, x0, y0);
+    const AdjPtrs A{D->seg + (long long)i * D->fstride, D->a[k], D->q[k], D->p0[k], D->dpsi[k],
+                    D->rv[k], D->gw, D->a[k ^ 1], D->q[k ^ 1], D->p0[k ^ 1], D->dpsi[k ^ 1],
+                    D->rv[k ^ 1], D->gg};
+    adj_tile<64, 4>(D->P, A, x0, y0, lds);
+}
+
+// dL/dG_w of the last reverse step's wall vectors (instance blockIdx.y).
+__global__ __launch_bounds__(256) void k_batch_adj_gw(const AdjInst* __restrict__ inst, int k) {
+    const AdjInst* D = inst + blockIdx.y;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= D->P.nx || !D->P.walls) return;
+    adj_gw_node(D->P, D->rv[k], D->gg, x, 1);
+    adj_gw_node(D->P, D->rv[k], D->gg, x, D->P.ny - 2);
+}
+
 // Clears the barrier counter and abort flag (a kernel rather than a memset node, so the pair can
 // sit in a hipGraph).
-__global__ void k_batch_reset(unsigned* bar, int* flag) {
+__global__ void k_batch_reset(unsigned long long* bar, int* flag) {
     if (threadIdx.x == 0) {
-        *bar = 0u;
+        *bar = 0ull;
         *flag = 0;
     }
 }
@@ -150,15 +218,17 @@ static hipError_t launch_batch_t(int geo, int eos, const InstDesc* inst, const i
 
 template <int TX, int TY>
 static hipError_t launch_persist_t(int geo, int eos, int grid, const InstDesc* inst,
-                                   const int* tile_inst, int ntiles, int nsteps, int cur,
-                                   unsigned* bar, int* flag, int spin_limit, hipStream_t s) {
+                                   const int* tile_inst, int ntiles, int npairs, int cur,
+                                   unsigned long long* bar, int* flag, int spin_limit,
+                                   hipStream_t s) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, bar, flag);
     hipError_t e0 = hipGetLastError();
     if (e0 != hipSuccess) return e0;
     return dispatch(geo, eos, [&](auto g, auto e) {
-        hipLaunchKernelGGL((k_batch_persistent<TX, TY, decltype(g)::value, decltype(e)::value>),
-                           dim3(grid), dim3(TX * TY), 0, s, inst, tile_inst, ntiles, nsteps, cur,
-                           bar, flag, spin_limit);
+        constexpr int G = decltype(g)::value;
+        hipLaunchKernelGGL((k_batch_persistent<TX, TY, G, decltype(e)::value>), dim3(grid),
+                           dim3(step2_threads(TX, TY, G)), 0, s, inst, tile_inst, ntiles, npairs,
+                           cur, bar, flag, spin_limit);
         return hipGetLastError();
     });
 }
@@ -172,9 +242,10 @@ static int occupancy_t() {
         for (int eos : {EOS_CS, EOS_PW, EOS_ANY}) {
             int n = 0;
             hipError_t r = dispatch(geo, eos, [&](auto g, auto e) {
+                constexpr int G = decltype(g)::value;
                 return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &n, k_batch_persistent<TX, TY, decltype(g)::value, decltype(e)::value>,
-                    TX * TY, 0);
+                    &n, k_batch_persistent<TX, TY, G, decltype(e)::value>,
+                    step2_threads(TX, TY, G), 0);
             });
             if (r != hipSuccess) return 0;
             lo = std::min(lo, n);
@@ -218,16 +289,17 @@ hipError_t launch_batch_step(int tile, int geo, int eos, const InstDesc* inst,
 }
 
 hipError_t launch_batch_persistent(int tile, int geo, int eos, int grid, const InstDesc* inst,
-                                   const int* tile_inst, int ntiles, int nsteps, int cur,
-                                   unsigned* bar, int* flag, int spin_limit, hipStream_t s) {
+                                   const int* tile_inst, int ntiles, int npairs, int cur,
+                                   unsigned long long* bar, int* flag, int spin_limit,
+                                   hipStream_t s) {
     switch (tile) {
-        case 1: return launch_persist_t<64, 8>(geo, eos, grid, inst, tile_inst, ntiles, nsteps,
+        case 1: return launch_persist_t<64, 8>(geo, eos, grid, inst, tile_inst, ntiles, npairs,
                                                cur, bar, flag, spin_limit, s);
-        case 2: return launch_persist_t<64, 16>(geo, eos, grid, inst, tile_inst, ntiles, nsteps,
+        case 2: return launch_persist_t<64, 16>(geo, eos, grid, inst, tile_inst, ntiles, npairs,
                                                 cur, bar, flag, spin_limit, s);
-        case 3: return launch_persist_t<128, 4>(geo, eos, grid, inst, tile_inst, ntiles, nsteps,
+        case 3: return launch_persist_t<128, 4>(geo, eos, grid, inst, tile_inst, ntiles, npairs,
                                                 cur, bar, flag, spin_limit, s);
-        default: return launch_persist_t<64, 4>(geo, eos, grid, inst, tile_inst, ntiles, nsteps,
+        default: return launch_persist_t<64, 4>(geo, eos, grid, inst, tile_inst, ntiles, npairs,
                                                 cur, bar, flag, spin_limit, s);
     }
 }
@@ -239,6 +311,44 @@ int batch_persistent_occupancy(int tile) {
         case 3: return occupancy_t<128, 4>();
         default: return occupancy_t<64, 4>();
     }
+}
+
+template <class F>
+static hipError_t with_eos(int eos, F&& f) {
+    if (eos == EOS_CS) return f(std::integral_constant<int, EOS_CS>{});
+    if (eos == EOS_PW) return f(std::integral_constant<int, EOS_PW>{});
+    return f(std::integral_constant<int, EOS_ANY>{});
+}
+
+hipError_t launch_batch_seg_step2(int eos, const AdjInst* inst, const int* tile_inst, int ntiles,
+                                  int i, hipStream_t s) {
+    return with_eos(eos, [&](auto e) {
+        hipLaunchKernelGGL((k_batch_seg_step2<decltype(e)::value>), dim3(ntiles),
+                           dim3(step2_threads(64, 4, GEO_ROWS)), 0, s, inst, tile_inst, ntiles, i);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_batch_seg_step(int eos, const AdjInst* inst, const int* tile_inst, int ntiles,
+                                 int i, hipStream_t s) {
+    return with_eos(eos, [&](auto e) {
+        hipLaunchKernelGGL((k_batch_seg_step<decltype(e)::value>), dim3(ntiles), dim3(256), 0, s,
+                           inst, tile_inst, ntiles, i);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_batch_adj(const AdjInst* inst, const int* tile_inst, int ntiles, int i, int k,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_adj, dim3(ntiles), dim3(256), 0, s, inst, tile_inst, ntiles, i, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_adj_gw(const AdjInst* inst, int count, int max_nx, int k,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_adj_gw, dim3((max_nx + 255) / 256, count), dim3(256), 0, s, inst,
+                       k);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch_contact_line(const InstDesc* inst, const int* rows, int count, int cur,

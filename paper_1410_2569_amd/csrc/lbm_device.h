@@ -403,9 +403,25 @@ __device__ __forceinline__ void velocity(const KParams& P, const double f[9], do
     vy = fma(0.5, Fy, jy) * ir;
 }
 
+// The 9 pre-collision populations of node (x, y): pulled from a post-collision buffer (the
+// library's state), or with PRE read in place from an array of pre-collision populations of the
+// same [9][ny][pitch] layout.
+template <bool PRE>
+__device__ __forceinline__ void node_populations(const KParams& P, const double* __restrict__ g,
+                                                 int x, int y, double f[9]) {
+    if constexpr (PRE) {
+        const long long i = (long long)y * P.pitch + x;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) f[a] = g[a * P.plane + i];
+    } else {
+        pull9_any(P, g, x, y, f);
+    }
+}
+
 // Density and pseudopotential of node (x, y) (x < nx, y_lo <= y <= y_hi) into psi_g and, when
 // given, rho_out (fields of [ny][pitch] doubles); a solid node of a mask gets 0 in both. With
 // ghost rows (Eq. 7 applied at the wall) the solid row next to the node's row receives its psi.
+template <bool PRE = false>
 __device__ __forceinline__ void psi_node(const KParams& P, const double* __restrict__ gin,
                                          double* __restrict__ psi_g, double* __restrict__ rho_out,
                                          int x, int y) {
@@ -415,7 +431,7 @@ __device__ __forceinline__ void psi_node(const KParams& P, const double* __restr
         return;
     }
     double f[9];
-    pull9_any(P, gin, x, y, f);
+    node_populations<PRE>(P, gin, x, y, f);
     const double rho = sum9(f);
     const double ps = psi_of_rho(P, rho);
     psi_g[(long long)y * P.pitch + x] = ps;
@@ -461,7 +477,9 @@ __device__ __forceinline__ void add_point(double v[O_NQ], double px, double py, 
 // Observables contribution of node (x, y) (x < nx, y_lo <= y <= y_hi) to v[O_NQ]: its density,
 // velocity of Eq. (6) (forces from psi_g, the psi field with its ghost rows), and the rho_mid
 // crossings on the edges to its right and upper neighbours. rho_f: density of every fluid node.
-// Solid nodes of a mask contribute nothing.
+// Solid nodes of a mask contribute nothing. PRE: gin holds pre-collision populations (see
+// node_populations).
+template <bool PRE = false>
 __device__ __forceinline__ void obs_node(const KParams& P, const double* __restrict__ gin,
                                          const double* __restrict__ rho_f,
                                          const double* __restrict__ psi_g,
@@ -470,7 +488,7 @@ __device__ __forceinline__ void obs_node(const KParams& P, const double* __restr
     if (is_solid_node(P, x, y)) return;
     const long long i = (long long)y * P.pitch + x;
     double f[9];
-    pull9_any(P, gin, x, y, f);
+    node_populations<PRE>(P, gin, x, y, f);
     const double rho = rho_f[i], pc = psi_g[i];
     const int xm = x == 0 ? P.nx - 1 : x - 1, xp = x == P.nx - 1 ? 0 : x + 1;
     int ym = y - 1, yp = y + 1;
@@ -686,15 +704,15 @@ __host__ __device__ constexpr int step2_waves(int TX, int TY, int GEO) {
     return TX == 64 && (TY == 8 || TY == 4) ? 6 : 1;
 }
 
-// LDS of step2_tile; MK: a solid mask, whose link words of R2 are kept too.
-template <int TX, int TY, bool MK = false>
+// LDS of step2_tile; with a solid mask (GEO_MASK) the link words of R2 are kept too.
+template <int TX, int TY, int GEO>
 struct Step2Lds {
     static constexpr int W3 = TX + 6, H3 = TY + 6, W2 = TX + 4, H2 = TY + 4, W1 = TX + 2,
                          H1 = TY + 2, PL = W2 * H2;
     double g1[9 * PL];
     double ps1[W3 * H3];
     double ps2[W1 * H1];
-    unsigned short lk[MK ? PL : 1];
+    unsigned short lk[GEO == GEO_MASK ? PL : 1];
 };
 
 // IN: the tile is interior (step2_interior): every pull of R3 stays inside the lattice, clear of
@@ -702,11 +720,15 @@ struct Step2Lds {
 // rule. Both variants give the same bits on such a tile. With a solid mask (GEO_MASK) the lattice
 // is periodic in x and y, solid nodes hold psi = 0 and are not updated, links select the
 // bounce-back of each population and the adhesion sums G_w over the solid neighbours.
-template <int TX, int TY, int GEO, int EOS = EOS_ANY, bool IN = false>
+// MID: the state after the first of the two steps is also written, to gmid (the tile's nodes;
+// without the wet-node force, so not for that wall).
+template <int TX, int TY, int GEO, int EOS = EOS_ANY, bool IN = false, bool MID = false>
 __device__ __forceinline__ void step2_tile(const KParams& P, const double* __restrict__ gin,
                                            double* __restrict__ gout,
                                            const double* __restrict__ gw, int x0, int y0,
-                                           Step2Lds<TX, TY, GEO == GEO_MASK>& L) {
+                                           Step2Lds<TX, TY, GEO>& L,
+                                           double* __restrict__ gmid = nullptr) {
+    static_assert(!MID || GEO != GEO_WET, "the intermediate state carries no wet-node force");
     constexpr bool MK = GEO == GEO_MASK;
     constexpr int NT = step2_threads(TX, TY, GEO);
     static_assert(NT >= TX * TY, "one thread per output node at least");
@@ -813,6 +835,15 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
         collide(P, fk[r], rk[r], c[0], sx, sy, Ax, Ay);
 #pragma unroll
         for (int a = 0; a < 9; ++a) g1[a * PL + s] = fk[r][a];
+        if constexpr (MID) {
+            // a node of the tile: its state after step n+1
+            const int x = x0 - 2 + lx, y = y0 - 2 + ly;
+            if (lx >= 2 && lx <= W2 - 3 && ly >= 2 && ly <= H2 - 3 && x < P.nx && y <= P.y_hi) {
+                const unsigned i = (unsigned)y * P.pitch + x;
+#pragma unroll
+                for (int a = 0; a < 9; ++a) (gmid + a * P.plane)[i] = fk[r][a];
+            }
+        }
     }
     __syncthreads();
 
@@ -913,15 +944,16 @@ __device__ __forceinline__ bool step2_interior(const KParams& P, int x0, int y0)
 }
 
 // step2_tile with the interior variant where it applies (a uniform branch per workgroup).
-template <int TX, int TY, int GEO, int EOS>
+template <int TX, int TY, int GEO, int EOS, bool MID = false>
 __device__ __forceinline__ void step2_tile_any(const KParams& P, const double* __restrict__ gin,
                                                double* __restrict__ gout,
                                                const double* __restrict__ gw, int x0, int y0,
-                                               Step2Lds<TX, TY, GEO == GEO_MASK>& L) {
+                                               Step2Lds<TX, TY, GEO>& L,
+                                               double* __restrict__ gmid = nullptr) {
     if (step2_interior<TX, TY, GEO>(P, x0, y0))
-        step2_tile<TX, TY, GEO, EOS, true>(P, gin, gout, gw, x0, y0, L);
+        step2_tile<TX, TY, GEO, EOS, true, MID>(P, gin, gout, gw, x0, y0, L, gmid);
     else
-        step2_tile<TX, TY, GEO, EOS, false>(P, gin, gout, gw, x0, y0, L);
+        step2_tile<TX, TY, GEO, EOS, false, MID>(P, gin, gout, gw, x0, y0, L, gmid);
 }
 
 }  // namespace lbm
@@ -1125,11 +1157,11 @@ __device__ __forceinline__ void collide_adj(const KParams& P, const double f[9],
 }
 
 // nu = dL/dg at fluid node (x, y): the transpose of pull streaming with bounce-back applied to
-// lambda = a + c 1 (a: 9 planes, c: one plane), i.e. g_b(y) feeds f_b(y + e_b), or f_opp(b)(y)
-// when y + e_b is solid.
-__device__ __forceinline__ void push_gather(const KParams& P, const double* __restrict__ a,
-                                            const double* __restrict__ c, int x, int y,
-                                            double nu[9]) {
+// lambda = a + c 1 (a: 9 planes, c: one scalar plane read from an LDS tile; l: the node's slot,
+// W: row stride), i.e. g_b(y) feeds f_b(y + e_b), or f_opp(b)(y) when y + e_b is solid.
+__device__ __forceinline__ void push_gather_lds(const KParams& P, const double* __restrict__ a,
+                                                const double* cs, int W, int l, int x, int y,
+                                                double nu[9]) {
     const unsigned nx = P.nx, pitch = P.pitch;
     const unsigned ux = x;
     const unsigned xm = ux == 0 ? nx - 1 : ux - 1;
@@ -1147,18 +1179,179 @@ __device__ __forceinline__ void push_gather(const KParams& P, const double* __re
     const long long pl = P.plane;
     const unsigned r0 = (unsigned)y * pitch, rm = ym * pitch, rp = yp * pitch;
     const unsigned i0 = r0 + ux;
-    const double c0 = c[i0];
+    const double c0 = cs[l];
     nu[0] = a[i0] + c0;
-    nu[1] = (a + 1 * pl)[r0 + xp] + c[r0 + xp];
-    nu[3] = (a + 3 * pl)[r0 + xm] + c[r0 + xm];
+    nu[1] = (a + 1 * pl)[r0 + xp] + cs[l + 1];
+    nu[3] = (a + 3 * pl)[r0 + xm] + cs[l - 1];
     // e_y = +1 populations travel up: reflected at the top wall
-    nu[2] = top ? (a + 4 * pl)[i0] + c0 : (a + 2 * pl)[rp + ux] + c[rp + ux];
-    nu[5] = top ? (a + 7 * pl)[i0] + c0 : (a + 5 * pl)[rp + xp] + c[rp + xp];
-    nu[6] = top ? (a + 8 * pl)[i0] + c0 : (a + 6 * pl)[rp + xm] + c[rp + xm];
+    nu[2] = top ? (a + 4 * pl)[i0] + c0 : (a + 2 * pl)[rp + ux] + cs[l + W];
+    nu[5] = top ? (a + 7 * pl)[i0] + c0 : (a + 5 * pl)[rp + xp] + cs[l + W + 1];
+    nu[6] = top ? (a + 8 * pl)[i0] + c0 : (a + 6 * pl)[rp + xm] + cs[l + W - 1];
     // e_y = -1 populations travel down: reflected at the bottom wall
-    nu[4] = bot ? (a + 2 * pl)[i0] + c0 : (a + 4 * pl)[rm + ux] + c[rm + ux];
-    nu[7] = bot ? (a + 5 * pl)[i0] + c0 : (a + 7 * pl)[rm + xm] + c[rm + xm];
-    nu[8] = bot ? (a + 6 * pl)[i0] + c0 : (a + 8 * pl)[rm + xp] + c[rm + xp];
+    nu[4] = bot ? (a + 2 * pl)[i0] + c0 : (a + 4 * pl)[rm + ux] + cs[l - W];
+    nu[7] = bot ? (a + 5 * pl)[i0] + c0 : (a + 7 * pl)[rm + xm] + cs[l - W - 1];
+    nu[8] = bot ? (a + 6 * pl)[i0] + c0 : (a + 8 * pl)[rm + xp] + cs[l - W + 1];
+}
+
+// xi = dL/dpsi of node (x, y) = p0 + sum_a w_a e_a . q(x - e_a) (+ the mirrored ghost rows, whose
+// psi is this row's), the transpose of the cohesion stencil of Eq. (7); q from an LDS tile
+// (slot l, row stride W; rows outside the fluid hold 0).
+__device__ __forceinline__ double adj_xi(const KParams& P, const double* qx, const double* qy,
+                                         int W, int l, int y, double p0) {
+    double xi = (qx[l - 1] - qx[l + 1] + qy[l - W] - qy[l + W]) * (1.0 / 3.0) +
+                ((qx[l - W - 1] + qy[l - W - 1]) + (qy[l - W + 1] - qx[l - W + 1]) -
+                 (qx[l + W + 1] + qy[l + W + 1]) + (qx[l + W - 1] - qy[l + W - 1])) *
+                    (1.0 / 12.0);
+    if (P.walls && P.ghost) {
+        if (y == 1)
+            xi += -qy[l] * (1.0 / 3.0) +
+                  ((-qx[l + 1] - qy[l + 1]) + (qx[l - 1] - qy[l - 1])) * (1.0 / 12.0);
+        if (y == P.ny - 2)
+            xi += qy[l] * (1.0 / 3.0) +
+                  ((qx[l - 1] + qy[l - 1]) + (qy[l + 1] - qx[l + 1])) * (1.0 / 12.0);
+    }
+    return xi + p0;
+}
+
+// Pointers of one reverse step: the forward state g^{n-1} whose step is reversed, the adjoint
+// quantities of the later step (in) and of this one (out), the G_w gradient being accumulated.
+struct AdjPtrs {
+    const double* gprev;
+    const double* a_in;     // 9 planes: dL/df^n along every path except psi
+    const double* q_in;     // 2 planes: dL/ds of the cohesion sum
+    const double* p0_in;    // dL/dpsi as the node's own pre-factor
+    const double* dpsi_in;  // psi'(rho)
+    const double* rv_in;    // 4 rows: dL/dA on the wall rows (bottom x, y; top x, y)
+    const double* gw;
+    double* a_out;
+    double* q_out;
+    double* p0_out;
+    double* dpsi_out;
+    double* rv_out;
+    double* gwgrad;  // [2][pitch]
+};
+
+template <int TX, int TY>
+struct AdjLds {
+    double sp[(TY + 2) * (TX + 2)];  // psi of g^{n-1} on the tile and one ring
+    double qx[(TY + 4) * (TX + 4)];  // q of the later step on the tile and two rings
+    double qy[(TY + 4) * (TX + 4)];
+    double cs[(TY + 2) * (TX + 2)];  // c = psi' xi of the later step on the tile and one ring
+};
+
+// dL/dG_w of the solid node below (bottom wall) or above (top wall) fluid node x of a wall row,
+// from the wall vectors r = dL/dA of one step (omega = w/3: 1/9 axial, 1/36 diagonal).
+__device__ __forceinline__ void adj_gw_node(const KParams& P, const double* __restrict__ rv,
+                                            double* __restrict__ gwgrad, int x, int y) {
+    const unsigned pitch = P.pitch, ux = x;
+    const unsigned xm = ux == 0 ? P.nx - 1 : ux - 1;
+    const unsigned xp = ux == (unsigned)P.nx - 1 ? 0 : ux + 1;
+    if (y == 1) {
+        const double* rX = rv;
+        const double* rY = rv + pitch;
+        gwgrad[ux] += -rY[ux] * (1.0 / 9.0) + ((-rX[xp] - rY[xp]) + (rX[xm] - rY[xm])) * (1.0 / 36.0);
+    }
+    if (y == P.ny - 2) {
+        const double* rX = rv + 2 * pitch;
+        const double* rY = rv + 3 * pitch;
+        gwgrad[pitch + ux] +=
+            rY[ux] * (1.0 / 9.0) + ((rX[xm] + rY[xm]) + (rY[xp] - rX[xp])) * (1.0 / 36.0);
+    }
+}
+
+// One reverse step on a TX x TY tile (bounce-back or periodic rows), executed by TX * TY threads:
+// lambda^{n-1} = (df^n / df^{n-1})^T lambda^n with lambda = a + c 1, where the scalar part
+// c = psi' xi of the later step is formed here, on the tile and one ring, from that step's q, p0
+// and psi' (the transpose of the cohesion stencil: each node's psi feeds its 8 neighbours' forces);
+// then the forward node is recomputed from g^{n-1} and reverse mode runs through the MRT
+// collision, forcing and adhesion (collide_adj). The later step's wall vectors are added to the
+// G_w gradient (the last reverse step's by adj_gw_node afterwards).
+template <int TX, int TY>
+__device__ __forceinline__ void adj_tile(const KParams& P, const AdjPtrs& A, int x0, int y0,
+                                         AdjLds<TX, TY>& L) {
+    constexpr int NT = TX * TY;
+    constexpr int LW = TX + 2, QW = TX + 4;
+    constexpr int NH = 2 * LW + 2 * TY;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool active = x < P.nx && y <= P.y_hi;
+
+    // forward node and psi on the tile and one ring
+    double f[9];
+    double rho = 1.0, psi_c = 0.0;
+    if (active) {
+        pull9<GEO_ROWS>(P, A.gprev, x, y, f);
+        rho = sum9(f);
+        psi_c = psi_of_rho(P, rho);
+    }
+    L.sp[(ty + 1) * LW + tx + 1] = active ? psi_c : psi_at<GEO_ROWS>(P, A.gprev, x, y);
+    for (int h = threadIdx.x; h < NH; h += NT) {
+        int hx, hy;
+        if (h < LW) { hx = h - 1; hy = -1; }
+        else if (h < 2 * LW) { hx = h - LW - 1; hy = TY; }
+        else if (h < 2 * LW + TY) { hx = -1; hy = h - 2 * LW; }
+        else { hx = TX; hy = h - 2 * LW - TY; }
+        L.sp[(hy + 1) * LW + hx + 1] = psi_at<GEO_ROWS>(P, A.gprev, x0 + hx, y0 + hy);
+    }
+    // q of the later step on the tile and two rings (0 outside the fluid rows)
+    for (int s = threadIdx.x; s < (TY + 4) * QW; s += NT) {
+        const int gx = wrapx(x0 - 2 + s % QW, P.nx);
+        int gy = y0 - 2 + s / QW;
+        bool fluid = true;
+        if (P.walls) fluid = gy >= 1 && gy <= P.ny - 2;
+        else gy = wrapx(gy, P.ny);
+        double vx = 0.0, vy = 0.0;
+        if (fluid) {
+            const unsigned i = (unsigned)gy * P.pitch + gx;
+            vx = A.q_in[i];
+            vy = (A.q_in + P.plane)[i];
+        }
+        L.qx[s] = vx;
+        L.qy[s] = vy;
+    }
+    __syncthreads();
+    // c of the later step on the tile and one ring
+    for (int s = threadIdx.x; s < (TY + 2) * LW; s += NT) {
+        const int hx = s % LW, hy = s / LW;
+        const int gx = wrapx(x0 - 1 + hx, P.nx);
+        int gy = y0 - 1 + hy;
+        bool fluid = true;
+        if (P.walls) fluid = gy >= 1 && gy <= P.ny - 2;
+        else gy = wrapx(gy, P.ny);
+        double c = 0.0;
+        if (fluid) {
+            const unsigned i = (unsigned)gy * P.pitch + gx;
+            c = A.dpsi_in[i] * adj_xi(P, L.qx, L.qy, QW, (hy + 1) * QW + hx + 1, gy, A.p0_in[i]);
+        }
+        L.cs[s] = c;
+    }
+    __syncthreads();
+    if (!active) return;
+
+    const double* cc = L.sp + (ty + 1) * LW + tx + 1;
+    double sx, sy;
+    cohesion_sum(cc[-LW - 1], cc[-LW], cc[-LW + 1], cc[-1], cc[1], cc[LW - 1], cc[LW],
+                 cc[LW + 1], sx, sy);
+    double Ax = 0.0, Ay = 0.0;
+    const bool wall_row = P.walls && (y == 1 || y == P.ny - 2);
+    if (wall_row) adhesion_sum(P, A.gw, x, y, Ax, Ay);
+
+    double nu[9], fb[9], pb, qx, qy, rx, ry;
+    push_gather_lds(P, A.a_in, L.cs, LW, (ty + 1) * LW + tx + 1, x, y, nu);
+    collide_adj(P, f, rho, psi_c, sx, sy, Ax, Ay, nu, fb, pb, qx, qy, rx, ry);
+
+    const unsigned i = (unsigned)y * P.pitch + x;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) (A.a_out + k * P.plane)[i] = fb[k];
+    A.q_out[i] = qx;
+    (A.q_out + P.plane)[i] = qy;
+    A.p0_out[i] = pb;
+    A.dpsi_out[i] = dpsi_drho(P, rho, psi_c);
+    if (wall_row) {
+        if (y == 1) { A.rv_out[x] = rx; A.rv_out[P.pitch + x] = ry; }
+        if (y == P.ny - 2) { A.rv_out[2 * P.pitch + x] = rx; A.rv_out[3 * P.pitch + x] = ry; }
+        adj_gw_node(P, A.rv_in, A.gwgrad, x, y);
+    }
 }
 
 }  // namespace lbm

@@ -18,34 +18,58 @@ struct InstDesc {
     int pad;
 };
 
+// One instance of an ensemble's adjoint run (device memory): its segment of recomputed states
+// and the adjoint quantities of two consecutive reverse steps (see AdjPtrs).
+struct AdjInst {
+    KParams P;
+    double* seg;       // the segment's states, fstride doubles apart
+    long long fstride;
+    double* a[2];
+    double* q[2];
+    double* p0[2];
+    double* dpsi[2];
+    double* rv[2];
+    const double* gw;
+    double* gg;  // [2][pitch] dL/dG_w
+    int tile0;   // first 64 x 4 tile of this instance in the adjoint work-list
+    int ntx, nty;
+    int pad;
+};
+
 int n_tiles();
 void tile_shape(int tile, int* tx, int* ty);
 hipError_t launch_step(const KParams& P, int schedule, int tile, const double* gin, double* gout,
                        double* psi, const double* gw, hipStream_t s);
+// gmid (optional, bounce-back or periodic rows): also receives the state after the first step
 hipError_t launch_step2(const KParams& P, int tile2, const double* gin, double* gout,
-                        const double* gw, hipStream_t s);
+                        const double* gw, hipStream_t s, double* gmid = nullptr);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);  // bytes and p 8-byte aligned
 hipError_t launch_init(const KParams& P, const double* rho0, double* g, hipStream_t s);
-hipError_t launch_pull(const KParams& P, const double* gin, double* fout, hipStream_t s);
+// dense: fout is [9][ny][nx] (otherwise [9][ny][pitch])
+hipError_t launch_pull(const KParams& P, const double* gin, double* fout, hipStream_t s,
+                       bool dense = false);
+// `planes` planes of ny x nx doubles from one row/plane layout to another (device memory)
+hipError_t launch_repack(const double* src, long long src_plane, int src_pitch, double* dst,
+                         long long dst_plane, int dst_pitch, int nx, int ny, int planes,
+                         hipStream_t s);
+// pre: gin holds pre-collision populations (otherwise the post-collision state, pulled)
 hipError_t launch_rho_psi(const KParams& P, const double* gin, double* psi, double* rho,
-                          hipStream_t s);
+                          hipStream_t s, bool pre = false);
 hipError_t launch_contact_line(const KParams& P, const double* gin, int row, double mid,
                                double* out, hipStream_t s);
 int obs_blocks(const KParams& P);
 hipError_t launch_obs(const KParams& P, const double* gin, const double* rho, const double* psi,
                       const double* gw, const ObsArgs& A, double* part, double* out,
-                      hipStream_t s);
+                      hipStream_t s, bool pre = false);
 
 // adjoint
-hipError_t launch_adj_step(const KParams& P, const double* gprev, const double* a_in,
-                           const double* c_in, const double* gw, double* a_out, double* qbuf,
-                           double* p0buf, double* dpsibuf, double* rvec, double* c_out,
-                           double* gwgrad, hipStream_t s);
+hipError_t launch_adj(const KParams& P, const AdjPtrs& A, hipStream_t s);
+hipError_t launch_adj_gw(const KParams& P, const double* rv, double* gwgrad, hipStream_t s);
 int loss_blocks(const KParams& P);
 hipError_t launch_loss(const KParams& P, const double* g, double* part, double* out,
                        hipStream_t s);
 hipError_t launch_loss_seed(const KParams& P, double w_c, double w_w, double yc, double sum_phi,
-                            double* c, hipStream_t s);
+                            double* p0, double* dpsi, hipStream_t s);
 
 // batch
 int batch_tiles(int tile);
@@ -56,11 +80,24 @@ hipError_t launch_batch_step(int tile, int geo, int eos, const InstDesc* inst,
                              const int* tile_inst, int ntiles, int cur, hipStream_t s);
 hipError_t launch_batch_step2(int tile, int geo, int eos, const InstDesc* inst,
                               const int* tile_inst, int ntiles, int cur, hipStream_t s);
+// npairs two-step passes in one launch (after a reset of the barrier counter and abort flag)
 hipError_t launch_batch_persistent(int tile, int geo, int eos, int grid, const InstDesc* inst,
-                                   const int* tile_inst, int ntiles, int nsteps, int cur,
-                                   unsigned* bar, int* flag, int spin_limit, hipStream_t s);
+                                   const int* tile_inst, int ntiles, int npairs, int cur,
+                                   unsigned long long* bar, int* flag, int spin_limit,
+                                   hipStream_t s);
 hipError_t launch_batch_contact_line(const InstDesc* inst, const int* rows, int count, int cur,
                                      double* out, hipStream_t s);
 int batch_persistent_occupancy(int tile);
+// ensemble adjoint, over a work-list of 64 x 4 tiles of every instance (bounce-back walls):
+// recomputation of segment states i -> i+1 (two steps: -> i+1, i+2), one reverse step of segment
+// state i (k: parity of the later step's buffers), and the last step's G_w gradient
+hipError_t launch_batch_seg_step2(int eos, const AdjInst* inst, const int* tile_inst, int ntiles,
+                                  int i, hipStream_t s);
+hipError_t launch_batch_seg_step(int eos, const AdjInst* inst, const int* tile_inst, int ntiles,
+                                 int i, hipStream_t s);
+hipError_t launch_batch_adj(const AdjInst* inst, const int* tile_inst, int ntiles, int i, int k,
+                            hipStream_t s);
+hipError_t launch_batch_adj_gw(const AdjInst* inst, int count, int max_nx, int k,
+                               hipStream_t s);
 
 }  // namespace lbm

@@ -83,28 +83,31 @@ __global__ __launch_bounds__(64 * (TYI + 2)) void k_step_ov(KParams P,
     for (int a = 0; a < 9; ++a) (gout + a * P.plane)[i] = f[a];
 }
 
-// Two steps per launch over TX x TY output tiles (step2_tile).
-template <int TX, int TY, int GEO, int EOS>
+// Two steps per launch over TX x TY output tiles (step2_tile); MID: the state after the first
+// step is written to gmid as well.
+template <int TX, int TY, int GEO, int EOS, bool MID>
 __global__
 __launch_bounds__(step2_threads(TX, TY, GEO), step2_waves(TX, TY, GEO)) void k_step2(
     KParams P, const double* __restrict__ gin, double* __restrict__ gout,
-    const double* __restrict__ gw) {
-    __shared__ Step2Lds<TX, TY, GEO == GEO_MASK> lds;
+    const double* __restrict__ gw, double* __restrict__ gmid) {
+    __shared__ Step2Lds<TX, TY, GEO> lds;
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
     const int tile = xcd_tile(blockIdx.x, ntx * nty);
-    step2_tile_any<TX, TY, GEO, EOS>(P, gin, gout, gw, (tile % ntx) * TX,
-                                     P.y_lo + (tile / ntx) * TY, lds);
+    step2_tile_any<TX, TY, GEO, EOS, MID>(P, gin, gout, gw, (tile % ntx) * TX,
+                                          P.y_lo + (tile / ntx) * TY, lds, gmid);
 }
 
-// psi pass of the two-pass schedule; also writes the mirrored ghost rows.
+// psi pass of the two-pass schedule; also writes the mirrored ghost rows. PRE: gin holds
+// pre-collision populations.
+template <bool PRE = false>
 __global__ __launch_bounds__(256) void k_psi(KParams P, const double* __restrict__ gin,
                                              double* __restrict__ psi_g,
                                              double* __restrict__ rho_out) {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = P.y_lo + blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= P.nx || y > P.y_hi) return;
-    psi_node(P, gin, psi_g, rho_out, x, y);
+    psi_node<PRE>(P, gin, psi_g, rho_out, x, y);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -137,15 +140,35 @@ __global__ __launch_bounds__(256) void k_init(KParams P, const double* __restric
     }
 }
 
-// Pre-collision populations f^n (pulled) into a [9][ny][pitch] buffer.
+// Pre-collision populations f^n (pulled) into a [9][ny][pitch] buffer, or with `dense` a
+// [9][ny][nx] one.
 __global__ __launch_bounds__(256) void k_pull(KParams P, const double* __restrict__ gin,
-                                              double* __restrict__ fout) {
+                                              double* __restrict__ fout, int dense) {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = P.y_lo + blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= P.nx || y > P.y_hi || is_solid_node(P, x, y)) return;
     double f[9];
     pull9_any(P, gin, x, y, f);
-    for (int a = 0; a < 9; ++a) fout[a * P.plane + (long long)y * P.pitch + x] = f[a];
+    const long long pl = dense ? (long long)P.nx * P.ny : P.plane;
+    const long long i = dense ? (long long)y * P.nx + x : (long long)y * P.pitch + x;
+    for (int a = 0; a < 9; ++a) fout[a * pl + i] = f[a];
+}
+
+// Copy of `planes` planes of ny rows of nx doubles between two layouts in device memory: rows
+// src_pitch doubles apart (planes src_plane apart) to rows dst_pitch apart (planes dst_plane
+// apart). Host data enter and leave the library densely packed through it, so that every copy
+// between host and device memory is one contiguous transfer.
+__global__ __launch_bounds__(256) void k_repack(const double* __restrict__ src, long long src_plane,
+                                                int src_pitch, double* __restrict__ dst,
+                                                long long dst_plane, int dst_pitch, int nx,
+                                                int ny, int planes) {
+    const long long per = (long long)ny * nx, n = per * planes;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (long long)gridDim.x * 256) {
+        const long long a = i / per, r = i - a * per;
+        const long long y = r / nx, x = r - y * nx;
+        dst[a * dst_plane + y * dst_pitch + x] = src[a * src_plane + y * src_pitch + x];
+    }
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -153,7 +176,9 @@ __global__ __launch_bounds__(256) void k_pull(KParams P, const double* __restric
 // reduction. No floating-point atomics, so results are bitwise reproducible.
 // ------------------------------------------------------------------------------------------------
 // Block of 256 threads over a 64 x 4 patch. rho_f: rho of every fluid node (from k_psi);
-// psi_g: psi with ghost rows. Writes O_NQ partials per block.
+// psi_g: psi with ghost rows. Writes O_NQ partials per block. PRE: gin holds pre-collision
+// populations.
+template <bool PRE = false>
 __global__ __launch_bounds__(256) void k_obs(KParams P, const double* __restrict__ gin,
                                              const double* __restrict__ rho_f,
                                              const double* __restrict__ psi_g,
@@ -163,7 +188,7 @@ __global__ __launch_bounds__(256) void k_obs(KParams P, const double* __restrict
     const int y = P.y_lo + blockIdx.y * 4 + (threadIdx.x >> 6);
     double v[O_NQ];
     for (int q = 0; q < O_NQ; ++q) v[q] = op_identity(q);
-    if (x < P.nx && y <= P.y_hi) obs_node(P, gin, rho_f, psi_g, gw, A, x, y, v);
+    if (x < P.nx && y <= P.y_hi) obs_node<PRE>(P, gin, rho_f, psi_g, gw, A, x, y, v);
     // wave-level tree (xor shuffles), then across the 4 waves of the block
     __shared__ double red[4][O_NQ];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -273,25 +298,37 @@ static hipError_t launch_step_ov(const KParams& P, const double* gin, double* go
 
 template <int TX, int TY>
 static hipError_t launch_step2_t(const KParams& P, const double* gin, double* gout,
-                                 const double* gw, hipStream_t s) {
+                                 const double* gw, double* gmid, hipStream_t s) {
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
     return dispatch(P, [&](auto geo, auto eos) {
         constexpr int G = decltype(geo)::value;
-        hipLaunchKernelGGL((k_step2<TX, TY, G, decltype(eos)::value>), dim3(ntx * nty),
-                           dim3(step2_threads(TX, TY, G)), 0, s, P, gin, gout, gw);
-        return hipGetLastError();
+        constexpr int E = decltype(eos)::value;
+        if (!gmid) {
+            hipLaunchKernelGGL((k_step2<TX, TY, G, E, false>), dim3(ntx * nty),
+                               dim3(step2_threads(TX, TY, G)), 0, s, P, gin, gout, gw,
+                               (double*)nullptr);
+            return hipGetLastError();
+        }
+        if constexpr (G == GEO_ROWS) {
+            hipLaunchKernelGGL((k_step2<TX, TY, G, E, true>), dim3(ntx * nty),
+                               dim3(step2_threads(TX, TY, G)), 0, s, P, gin, gout, gw, gmid);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;  // intermediate states: bounce-back or periodic rows only
+        }
     });
 }
 
 // Two steps in one launch; tile2 selects the output tile: 0 64x8, 1 64x4, 2 128x4, 3 64x16.
+// gmid (optional): receives the state after the first step.
 hipError_t launch_step2(const KParams& P, int tile2, const double* gin, double* gout,
-                        const double* gw, hipStream_t s) {
+                        const double* gw, hipStream_t s, double* gmid) {
     switch (tile2) {
-        case 1: return launch_step2_t<64, 4>(P, gin, gout, gw, s);
-        case 2: return launch_step2_t<128, 4>(P, gin, gout, gw, s);
-        case 3: return launch_step2_t<64, 16>(P, gin, gout, gw, s);
-        default: return launch_step2_t<64, 8>(P, gin, gout, gw, s);
+        case 1: return launch_step2_t<64, 4>(P, gin, gout, gw, gmid, s);
+        case 2: return launch_step2_t<128, 4>(P, gin, gout, gw, gmid, s);
+        case 3: return launch_step2_t<64, 16>(P, gin, gout, gw, gmid, s);
+        default: return launch_step2_t<64, 8>(P, gin, gout, gw, gmid, s);
     }
 }
 
@@ -310,7 +347,8 @@ void tile_shape(int tile, int* tx, int* ty) {
 hipError_t launch_step(const KParams& P, int schedule, int tile, const double* gin, double* gout,
                        double* psi, const double* gw, hipStream_t s) {
     if (schedule == 1) {
-        hipLaunchKernelGGL(k_psi, node_grid(P), dim3(256), 0, s, P, gin, psi, (double*)nullptr);
+        hipLaunchKernelGGL(k_psi<false>, node_grid(P), dim3(256), 0, s, P, gin, psi,
+                           (double*)nullptr);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         return launch_step_t<64, 4, false>(P, gin, gout, psi, gw, s);
@@ -341,14 +379,27 @@ hipError_t launch_init(const KParams& P, const double* rho0, double* g, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_pull(const KParams& P, const double* gin, double* fout, hipStream_t s) {
-    hipLaunchKernelGGL(k_pull, node_grid(P), dim3(256), 0, s, P, gin, fout);
+hipError_t launch_pull(const KParams& P, const double* gin, double* fout, hipStream_t s,
+                       bool dense) {
+    hipLaunchKernelGGL(k_pull, node_grid(P), dim3(256), 0, s, P, gin, fout, dense ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_repack(const double* src, long long src_plane, int src_pitch, double* dst,
+                         long long dst_plane, int dst_pitch, int nx, int ny, int planes,
+                         hipStream_t s) {
+    const long long n = (long long)planes * ny * nx;
+    if (n <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<long long>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_repack, dim3(blocks), dim3(256), 0, s, src, src_plane, src_pitch, dst,
+                       dst_plane, dst_pitch, nx, ny, planes);
     return hipGetLastError();
 }
 
 hipError_t launch_rho_psi(const KParams& P, const double* gin, double* psi, double* rho,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_psi, node_grid(P), dim3(256), 0, s, P, gin, psi, rho);
+                          hipStream_t s, bool pre) {
+    if (pre) hipLaunchKernelGGL(k_psi<true>, node_grid(P), dim3(256), 0, s, P, gin, psi, rho);
+    else hipLaunchKernelGGL(k_psi<false>, node_grid(P), dim3(256), 0, s, P, gin, psi, rho);
     return hipGetLastError();
 }
 
@@ -365,9 +416,10 @@ int obs_blocks(const KParams& P) {
 
 hipError_t launch_obs(const KParams& P, const double* gin, const double* rho, const double* psi,
                       const double* gw, const ObsArgs& A, double* part, double* out,
-                      hipStream_t s) {
+                      hipStream_t s, bool pre) {
     dim3 g = node_grid(P);
-    hipLaunchKernelGGL(k_obs, g, dim3(256), 0, s, P, gin, rho, psi, gw, A, part);
+    if (pre) hipLaunchKernelGGL(k_obs<true>, g, dim3(256), 0, s, P, gin, rho, psi, gw, A, part);
+    else hipLaunchKernelGGL(k_obs<false>, g, dim3(256), 0, s, P, gin, rho, psi, gw, A, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, s, part, (int)(g.x * g.y), out);

@@ -105,6 +105,13 @@ SIGNATURES = {
                                    C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
     "lbm_batch_step": (C.c_int, [C.c_void_p, C.c_int64]),
     "lbm_batch_observables": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lbm_batch_adjoint_workspace_size": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32,
+                                                   C.POINTER(C.c_size_t)]),
+    "lbm_batch_forward_ckpt": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
+                                         C.c_size_t]),
+    "lbm_batch_loss": (C.c_int, [C.c_void_p, C.c_double, C.c_double, _dp]),
+    "lbm_batch_backward": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_size_t,
+                                     C.c_double, C.c_double, C.c_void_p]),
     "lbm_batch_read_f": (C.c_int, [C.c_void_p, C.c_int32, _dp, C.c_size_t]),
     "lbm_batch_save_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]),
     "lbm_batch_current_step": (C.c_int64, [C.c_void_p]),
@@ -231,6 +238,18 @@ def _use_on(t, stream):
     return t
 
 
+def _done_on(t, stream):
+    """Hand a tensor written by work queued on `stream` back to the caller: the current stream
+    waits for `stream`, so torch work queued after this call (a copy to the host, arithmetic)
+    reads the finished values."""
+    import torch
+
+    cur = torch.cuda.current_stream(t.device)
+    if stream.cuda_stream != cur.cuda_stream:
+        cur.wait_stream(stream)
+    return t
+
+
 def workspace_size(q: Params) -> int:
     n = C.c_size_t()
     check(lib().lbm_workspace_size(C.byref(q), C.byref(n)))
@@ -307,7 +326,8 @@ class Sim:
     def record_contact_line(self, n: int, every: int, row: int = 1, out=None):
         """Advance n steps recording the contact line on `row` every `every` steps (device-side;
         no host synchronisation). Returns a (n/every + 1, 2) float64 device tensor of
-        (left, right) crossings, filled asynchronously on the context stream."""
+        (left, right) crossings, filled asynchronously on the context stream (the current stream
+        is made to wait for it)."""
         import torch
         k = n // every + 1
         if out is None:
@@ -316,7 +336,7 @@ class Sim:
         assert out.is_contiguous() and out.dtype == torch.float64
         self._chk(lib().lbm_record_contact_line(self.h, int(n), int(every), int(row),
                                                 C.c_void_p(out.data_ptr()), out.numel()))
-        return out
+        return _done_on(out, self.stream)
 
     def rho(self) -> np.ndarray:
         out = np.empty((self.ny, self.nx))
@@ -368,7 +388,7 @@ class Sim:
                     self.stream)
         self._chk(lib().lbm_backward(self.h, int(nsteps), int(K), C.c_void_p(ws.data_ptr()),
                                      ws.numel(), w_centroid, w_wet, C.c_void_p(g.data_ptr())))
-        return g
+        return _done_on(g, self.stream)
 
 
 class Batch:
@@ -472,6 +492,40 @@ class Batch:
         rw = (C.c_int32 * self.n)(*[int(r) for r in rows])
         self._chk(lib().lbm_batch_record_contact_line(self.h, int(n), int(every), rw,
                                                       C.c_void_p(out.data_ptr()), out.numel()))
+        return _done_on(out, self.stream)
+
+    # ---- adjoint of every instance ---------------------------------------------------------------
+    def adjoint_workspace(self, nsteps: int, K: int):
+        """A device workspace (torch uint8 tensor) for forward_ckpt / backward of the ensemble."""
+        import torch
+        n = C.c_size_t()
+        self._chk(lib().lbm_batch_adjoint_workspace_size(self.h, int(nsteps), int(K), C.byref(n)))
+        return _use_on(torch.empty(n.value, dtype=torch.uint8, device=self.ws.device), self.stream)
+
+    def forward_ckpt(self, nsteps: int, K: int, ws):
+        self._chk(lib().lbm_batch_forward_ckpt(self.h, int(nsteps), int(K),
+                                               C.c_void_p(ws.data_ptr()), ws.numel()))
+
+    def loss(self, w_centroid: float = 1.0, w_wet: float = 1.0) -> list:
+        L = (C.c_double * self.n)()
+        self._chk(lib().lbm_batch_loss(self.h, w_centroid, w_wet, L))
+        return list(L)
+
+    def backward(self, nsteps: int, K: int, ws, w_centroid: float = 1.0, w_wet: float = 1.0):
+        """dL/dG_w of every instance: a list of (2, nx_i) float64 device tensors (views of one
+        buffer), row 0 bottom wall, row 1 top wall."""
+        import torch
+        sizes = [2 * q.nx for q in self.params]
+        g = _use_on(torch.empty(sum(sizes), dtype=torch.float64, device=self.ws.device),
+                    self.stream)
+        self._chk(lib().lbm_batch_backward(self.h, int(nsteps), int(K), C.c_void_p(ws.data_ptr()),
+                                           ws.numel(), w_centroid, w_wet,
+                                           C.c_void_p(g.data_ptr())))
+        _done_on(g, self.stream)
+        out, o = [], 0
+        for q, n in zip(self.params, sizes):
+            out.append(g[o:o + n].view(2, q.nx))
+            o += n
         return out
 
     def save_state(self, index: int) -> bytes:

@@ -11,7 +11,10 @@
 // the buffers. Each launch is then checked: every state slot of the output written and finite,
 // every other slot untouched, and the two-steps-per-launch kernels (every output tile shape,
 // interior and edge tiles) bit for bit equal to two single fused steps. The psi pass and the
-// per-node observables are run the same way and must produce finite sums.
+// per-node observables are run the same way and must produce finite sums. On periodic and
+// bounce-back lattices the adjoint's kernels run too: the segment recomputation (two steps with
+// the first written) must equal two fused steps, and one reverse step must write every output
+// on the fluid nodes only, bit-equal between its 32 x 4 and 64 x 4 tiles.
 //
 // Test infrastructure: built and run by tests/test_emu_index_maps.py. Usage:
 //   tile_emu            run the built-in case list
@@ -311,7 +314,7 @@ template <int TX, int TY, int GEO, int EOS>
 void step_two(const Lattice& L, const double* gin, double* gout) {
     const KParams& P = L.P;
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.y_hi - P.y_lo + TY) / TY;
-    auto* lds = new lbm::Step2Lds<TX, TY, GEO == lbm::GEO_MASK>;
+    auto* lds = new lbm::Step2Lds<TX, TY, GEO>;
     run_workgroups(
         lbm::step2_threads(TX, TY, GEO), ntx * nty,
         [&](int t) {
@@ -339,6 +342,132 @@ void check_equal(const Lattice& L, const std::vector<double>& a, const std::vect
     for (size_t i = 0; i < a.size(); ++i)
         if (L.state[i] && std::memcmp(&a[i], &b[i], sizeof(double)) != 0) ++diff;
     if (diff) fail(std::string(what) + ": " + std::to_string(diff) + " slots differ from two fused steps");
+}
+
+// Two steps with the intermediate state written (the segment recomputation of the adjoint).
+template <int TX, int TY, int EOS>
+void step_two_mid(const Lattice& L, const double* gin, double* gout, double* gmid) {
+    const KParams& P = L.P;
+    const int ntx = (P.nx + TX - 1) / TX, nty = (P.y_hi - P.y_lo + TY) / TY;
+    auto* lds = new lbm::Step2Lds<TX, TY, lbm::GEO_ROWS>;
+    run_workgroups(
+        lbm::step2_threads(TX, TY, lbm::GEO_ROWS), ntx * nty,
+        [&](int t) {
+            lbm::step2_tile_any<TX, TY, lbm::GEO_ROWS, EOS, true>(
+                P, gin, gout, L.gw.data(), (t % ntx) * TX, P.y_lo + (t / ntx) * TY, *lds, gmid);
+        },
+        [&] { std::memset((void*)lds, 0xFF, sizeof *lds); });
+    delete lds;
+}
+
+// One reverse step (adj_tile) on TX x TY tiles.
+struct AdjBufs {
+    std::vector<double> a_in, q_in, p0_in, dpsi_in, rv_in, a_out, q_out, p0_out, dpsi_out, rv_out,
+        gg;
+};
+
+template <int TX, int TY>
+void adj_step(const Lattice& L, const double* gprev, AdjBufs& B) {
+    const KParams& P = L.P;
+    const int ntx = (P.nx + TX - 1) / TX, nty = (P.y_hi - P.y_lo + TY) / TY;
+    auto* lds = new lbm::AdjLds<TX, TY>;
+    const lbm::AdjPtrs A{gprev,           B.a_in.data(),  B.q_in.data(),  B.p0_in.data(),
+                         B.dpsi_in.data(), B.rv_in.data(), L.gw.data(),    B.a_out.data(),
+                         B.q_out.data(),  B.p0_out.data(), B.dpsi_out.data(), B.rv_out.data(),
+                         B.gg.data()};
+    run_workgroups(
+        TX * TY, ntx * nty,
+        [&](int t) { lbm::adj_tile<TX, TY>(P, A, (t % ntx) * TX, P.y_lo + (t / ntx) * TY, *lds); },
+        [&] { std::fill((double*)lds, (double*)lds + sizeof *lds / sizeof(double), kNaN); });
+    delete lds;
+}
+
+// Later-step adjoint inputs: small seeded values on the fluid nodes (psi' > 0), NaN elsewhere;
+// outputs NaN; the G_w gradient zero on its two rows.
+AdjBufs make_adj(const Lattice& L) {
+    const KParams& P = L.P;
+    const size_t pl = (size_t)P.plane;
+    AdjBufs B;
+    auto fill = [&](std::vector<double>& v, int planes, unsigned long long salt, double lo,
+                    double hi) {
+        v.assign(planes * pl, kNaN);
+        for (int k = 0; k < planes; ++k)
+            for (size_t i = 0; i < pl; ++i)
+                if (L.fluid[i]) v[k * pl + i] = lo + (hi - lo) * unit((salt << 48) + k * pl + i);
+    };
+    fill(B.a_in, 9, 1, -1.0, 1.0);
+    fill(B.q_in, 2, 2, -0.5, 0.5);
+    fill(B.p0_in, 1, 3, -0.5, 0.5);
+    fill(B.dpsi_in, 1, 4, 0.5, 1.5);
+    B.rv_in.assign((size_t)4 * P.pitch, kNaN);
+    for (int r = 0; r < 4; ++r)
+        for (int x = 0; x < P.nx; ++x) B.rv_in[(size_t)r * P.pitch + x] = unit(5000 + 4 * x + r) - 0.5;
+    B.a_out.assign(9 * pl, kNaN);
+    B.q_out.assign(2 * pl, kNaN);
+    B.p0_out.assign(pl, kNaN);
+    B.dpsi_out.assign(pl, kNaN);
+    B.rv_out.assign((size_t)4 * P.pitch, kNaN);
+    B.gg.assign((size_t)2 * P.pitch, kNaN);
+    for (int r = 0; r < 2; ++r)
+        for (int x = 0; x < P.nx; ++x) B.gg[(size_t)r * P.pitch + x] = 0.0;
+    return B;
+}
+
+// Adjoint outputs written and finite exactly on the fluid nodes (wall vectors and G_w gradient:
+// on their rows when there are walls), and bit-equal between two tile shapes.
+void check_adj(const Lattice& L, const AdjBufs& X, const AdjBufs& Y, const char* what) {
+    const KParams& P = L.P;
+    const size_t pl = (size_t)P.plane;
+    size_t bad = 0, stray = 0, diff = 0;
+    auto node = [&](const std::vector<double>& v, const std::vector<double>& w, int planes) {
+        for (int k = 0; k < planes; ++k)
+            for (size_t i = 0; i < pl; ++i) {
+                const double a = v[k * pl + i];
+                if (L.fluid[i]) bad += !std::isfinite(a);
+                else stray += !std::isnan(a);
+                diff += std::memcmp(&a, &w[k * pl + i], sizeof(double)) != 0;
+            }
+    };
+    node(X.a_out, Y.a_out, 9);
+    node(X.q_out, Y.q_out, 2);
+    node(X.p0_out, Y.p0_out, 1);
+    node(X.dpsi_out, Y.dpsi_out, 1);
+    for (int r = 0; r < 4; ++r)
+        for (int x = 0; x < P.pitch; ++x) {
+            const size_t i = (size_t)r * P.pitch + x;
+            const double a = X.rv_out[i];
+            if (P.walls && x < P.nx) bad += !std::isfinite(a);
+            else stray += !std::isnan(a);
+            diff += std::memcmp(&a, &Y.rv_out[i], sizeof(double)) != 0;
+        }
+    for (size_t i = 0; i < X.gg.size(); ++i) {
+        bad += (i % P.pitch) < (size_t)P.nx && !std::isfinite(X.gg[i]);
+        diff += std::memcmp(&X.gg[i], &Y.gg[i], sizeof(double)) != 0;
+    }
+    if (bad) fail(std::string(what) + ": " + std::to_string(bad) + " outputs not finite");
+    if (stray) fail(std::string(what) + ": " + std::to_string(stray) + " slots written off the fluid");
+    if (diff) fail(std::string(what) + ": " + std::to_string(diff) + " outputs differ between tile shapes");
+}
+
+template <int EOS>
+void run_adjoint(const Lattice& L, const std::vector<double>& g0, const std::vector<double>& g1,
+                 const std::vector<double>& g2) {
+    // segment recomputation: two steps with the first written, against two fused steps
+    for (int shape = 0; shape < 2; ++shape) {
+        std::vector<double> mid(g0.size(), kNaN), out(g0.size(), kNaN);
+        const char* name = shape ? "two-step 64x8 + mid" : "two-step 64x4 + mid";
+        if (shape) step_two_mid<64, 8, EOS>(L, g0.data(), out.data(), mid.data());
+        else step_two_mid<64, 4, EOS>(L, g0.data(), out.data(), mid.data());
+        check_output(L, mid, name);
+        check_equal(L, mid, g1, name);
+        check_output(L, out, name);
+        check_equal(L, out, g2, name);
+    }
+    // one reverse step with 32 x 4 and 64 x 4 tiles
+    AdjBufs X = make_adj(L), Y = make_adj(L);
+    adj_step<32, 4>(L, g0.data(), X);
+    adj_step<64, 4>(L, g0.data(), Y);
+    check_adj(L, X, Y, "reverse step 32x4 vs 64x4");
 }
 
 template <int GEO, int EOS>
@@ -385,6 +514,7 @@ void run_case(const Lattice& L) {
     two(step_two<128, 4, GEO, EOS>, "two-step 128x4");
     two(step_two<64, 16, GEO, EOS>, "two-step 64x16");
     observables<GEO, EOS>(L, ref);
+    if constexpr (GEO == lbm::GEO_ROWS) run_adjoint<EOS>(L, g0, g1, ref);
 }
 
 void run_lattice(int nx, int ny, int walls, int ghost, int eos, int force) {

@@ -6,9 +6,12 @@ runs every workgroup of the fused single step, the two-steps-per-launch tiles (6
 poisoned memory (NaN in every slot that is not state, NaN in the LDS before each tile), under
 AddressSanitizer and UndefinedBehaviorSanitizer. It fails when a launch reads outside its
 buffers, reads an LDS slot not written in the same launch, writes outside the state, or when the
-two-step tiles differ by one bit from two fused steps. Lattices from 3x4 to 125x17 (ragged tiles,
-halo wraps) and two with interior tiles; periodic, bounce-back (with and without ghost rows),
-wet-node and solid-mask geometries; both equations of state.
+two-step tiles differ by one bit from two fused steps. On periodic and bounce-back lattices the
+adjoint's kernels run too: the segment recomputation (two steps with the intermediate state
+written) must equal two fused steps, and a reverse step must write all of its outputs on the
+fluid nodes only, bit-equal between its 32x4 and 64x4 tiles. Lattices from 3x4 to 125x17 (ragged
+tiles, halo wraps) and two with interior tiles; periodic, bounce-back (with and without ghost
+rows), wet-node and solid-mask geometries; both equations of state.
 
 The checker is itself checked: copies of the header with an index mistake planted must fail.
 """

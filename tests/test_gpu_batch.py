@@ -123,3 +123,35 @@ def test_c3_full_size_sampled(orc, gpu):
         rel = float((np.abs(b.f(i) - f).max(0)[fl] / f.sum(0)[fl]).max())
         print(f"C3 instance {i} ({q.nx}x{q.ny}): {rel:.3e}", flush=True)
         assert rel <= 1e-9
+
+
+def test_c3_viscosity_ratios_long_run(orc, gpu):
+    """Phase-interpolated viscosity over a long run: the smallest lattice of the 96-lattice
+    ensemble at each of the vapour/liquid viscosity ratios 5 and 15, 2,000 steps as a two-lattice
+    ensemble in the benchmark's launch configuration, against the oracle element by element."""
+    ens = synth.c3_ensemble()
+    pick = []
+    for ratio in (5.0, 15.0):
+        cands = [i for i, e in enumerate(ens) if e["visc_ratio"] == ratio]
+        pick.append(min(cands, key=lambda i: (ens[i]["params"]["nx"], i)))
+    prm, gws, rhos, qs = [], [], [], []
+    for i in pick:
+        e = ens[i]
+        q = orc.make_params(e["params"])
+        assert q.tau_v > q.tau_l  # the viscosity varies between the phases
+        prm.append(dict(e["params"], rho_l=q.rho_l, rho_v=q.rho_v))
+        gws.append(e["gw"])
+        rhos.append(synth.droplet_rho(q.nx, q.ny, q.rho_l, q.rho_v, e["centres"], e["radii"],
+                                      seed=e["seed"]))
+        qs.append(q)
+    b = gpu.Batch(prm, gws, rhos, tune={"tile": 1, "schedule": 2})
+    steps = 2000
+    b.step(steps)
+    for k, i in enumerate(pick):
+        q = qs[k]
+        f = orc.run(q, gws[k], orc.init_rest(q, rhos[k]), steps)
+        fl = orc.fluid_mask(q)
+        rel = float((np.abs(b.f(k) - f).max(0)[fl] / f.sum(0)[fl]).max())
+        print(f"C3 instance {i} ({q.nx}x{q.ny}, ratio {ens[i]['visc_ratio']:g}, "
+              f"{ens[i]['form']}): {steps} steps, {rel:.3e}", flush=True)
+        assert rel <= 1e-9

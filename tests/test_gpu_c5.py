@@ -60,6 +60,18 @@ def test_c5_mass_conservation(orc, c5):
         assert abs(o["mass"] - m0[i]) <= 1e-12 * m0[i], (i, o["mass"], m0[i])
 
 
+def test_c5_parity_after_200_steps(orc, c5):
+    """The first instance against the oracle after the 200 steps of the mass test."""
+    cases, b = c5
+    assert b.current_step == 200
+    _, gw, rho0, q, _ = cases[0]
+    f = orc.run(q, gw, orc.init_rest(q, rho0), 200)
+    fl = orc.fluid_mask(q)
+    rel = float((np.abs(b.f(0) - f).max(0)[fl] / f.sum(0)[fl]).max())
+    print(f"c5 instance 0: 200 steps, max |df|/rho = {rel:.3e}", flush=True)
+    assert rel <= RTOL
+
+
 def test_c5_adjoint_full_size(orc, gpu, c5):
     """dL/dG_w of instance 0 over 200 steps from its state after the ensemble's steps (checkpoint
     every 20) against central differences of the forward run on wall nodes under droplets."""
@@ -96,3 +108,30 @@ def test_c5_adjoint_full_size(orc, gpu, c5):
         print(f"node {x}: adjoint {g[0, x]:.6e}, FD {fd:.6e}", flush=True)
     print("c5 adjoint vs FD, max rel err", max(errs))
     assert max(errs) <= 1e-6
+
+
+def test_c5_batched_adjoint_full_size(orc, gpu, c5):
+    """The ensemble adjoint over all eight 2048 x 1024 lattices at once (200 steps from the state
+    after the tests above, checkpoint every 20): instance 0's gradient bit for bit equal to its
+    lattice's own lbm_backward, and every instance's gradient finite and non-zero."""
+    cases, b = c5
+    p, gw, rho0, q, e = cases[0]
+    state = b.save_state(0)
+    sim = gpu.Sim(p, gw, rho0)
+    sim.load_state(state)
+    n, K = 200, 20
+    ws1 = sim.adjoint_workspace(n, K)
+    sim.forward_ckpt(n, K, ws1)
+    L1 = sim.loss()
+    g1 = sim.backward(n, K, ws1).cpu().numpy()
+    del ws1, sim
+    ws = b.adjoint_workspace(n, K)
+    b.forward_ckpt(n, K, ws)
+    Lb = b.loss()
+    gb = [g.cpu().numpy() for g in b.backward(n, K, ws)]
+    del ws
+    print(f"c5 batched adjoint: L0 {Lb[0]} vs {L1}, max |dg| {np.abs(gb[0] - g1).max():.3e}")
+    assert Lb[0] == L1
+    assert np.array_equal(gb[0], g1)
+    for g in gb:
+        assert np.isfinite(g).all() and np.abs(g[0]).max() > 0

@@ -4,8 +4,9 @@
   adhesion form (tests/sanitize/oracle_driver.c), leak detection on.
 * The host side of liblbm: parameter validation, workspace layouts, the Carnahan-Starling and
   Eq. (15) solvers, rejected buffers and handles (tests/sanitize/host_api_driver.cpp). The C-ABI
-  layer is compiled host-only with the sanitizers and linked with the kernel objects of the
-  regular build, whose launchers the driver never reaches.
+  layer is compiled with the sanitizers on its host pass only (its device code builds as usual)
+  and linked with the kernel objects of the regular build, whose launchers the driver never
+  reaches.
 (The device code's index maps run under the same sanitizers in tests/test_emu_index_maps.py.)
 """
 import os
@@ -41,7 +42,7 @@ def test_library_host_code_under_sanitizers(tmp_path):
         from paper_1410_2569_amd import build
         build.build()
     api = str(tmp_path / "lbm_api_san.o")
-    subprocess.check_call([HIPCC, "--offload-host-only", "-O1", "-g", "-std=c++17", "-fPIC",
+    subprocess.check_call([HIPCC, "-O1", "-g", "-std=c++17", "-fPIC",
                            "--offload-arch=gfx950", "-Xarch_host", "-fsanitize=address",
                            "-Xarch_host", "-fsanitize=undefined", "-Xarch_host",
                            "-fno-sanitize-recover=all", "-I", os.path.join(ROOT, "include"), "-c",
