@@ -174,6 +174,25 @@ int lbm_observables_window(lbm_ctx *c, double x_lo, double x_hi, lbm_obs *out);
  * default plane is y = 0.5 (bounce-back and masked geometries) or 1 (wet-node walls). */
 int lbm_observables_plane(lbm_ctx *c, double x_lo, double x_hi, double y_wall, lbm_obs *out);
 
+/* Allocation-free observables, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the record of
+ * lbm_observables for a population field the caller already holds on the device, with no context
+ * and no workspace.
+ *   p      parameters (walls 0, 1 or 2; a solid mask gets LBM_E_INVAL);
+ *   d_f    device array [9][ny][nx] of the PRE-collision populations f^n (the layout lbm_read_f
+ *          returns), caller-owned, read only, 8-byte aligned;
+ *   d_gw   device array [2][nx] of G_w (bottom wall, top wall), caller-owned; may be NULL with
+ *          walls = 0;
+ *   stream hipStream_t of the current device (NULL = default stream); the call synchronises it;
+ *   out    host record, out->step = 0.
+ * The density and pseudopotential planes and the partial sums live in a fixed 24 MiB device
+ * array of the library (one per GPU, held until the process ends); nothing is allocated. A
+ * lattice that needs more (about 1.5 million nodes; 1024 x 1024 fits) gets LBM_E_SIZE, with the
+ * reason in lbm_last_error(NULL). Calls that overlap on one GPU (several host threads or streams)
+ * share that array and race. Returns LBM_E_NONFINITE (after filling *out) if a fluid node is not
+ * finite. */
+int lbm_observables_of_state(const lbm_params *p, const double *d_f, const double *d_gw,
+                             void *stream, lbm_obs *out);
 
 /* Dynamic wetting (Sec. III.B, Fig. 7): advance n steps (a multiple of `every`) and record the
  * contact line on fluid row `row` at steps 0, every, 2 every, ..., n of this call, without any

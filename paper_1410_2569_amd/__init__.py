@@ -5,8 +5,8 @@ its thin Python binding.
 """
 from .lbm import (ABI_VERSION, EOS, SCHEDULE, WALL, WALLS, Batch, LBMError, Obs, Params,  # noqa: F401
                   Sim, Tune, autotune, cs_temperature, lib, make_params, maxwell_cs,
-                  piecewise_spinodals, workspace_size)
+                  observables_of_state, piecewise_spinodals, workspace_size)
 
 __all__ = ["Sim", "Batch", "Tune", "autotune", "Params", "Obs", "LBMError", "make_params",
-           "maxwell_cs", "cs_temperature", "piecewise_spinodals", "workspace_size", "lib", "WALL",
+           "maxwell_cs", "cs_temperature", "piecewise_spinodals", "workspace_size", "observables_of_state", "lib", "WALL",
            "WALLS", "EOS", "SCHEDULE", "ABI_VERSION"]

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -303,6 +304,39 @@ AdjLayout adj_layout_of(const lbm_params* p, int64_t nsteps, int32_t K) {
     A.off_fin = o; o += kAlign;
     A.total = o;
     return A;
+}
+
+}  // namespace
+
+// ---- allocation-free observables ------------------------------------------------------------
+// Scratch of lbm_observables_of_state: a fixed device array of the library (every GPU the library
+// runs on holds one until the process ends). In host code `scratch` names a host-side stand-in,
+// not device memory: kernels and copies only ever get the per-device address that
+// hipGetSymbolAddress returns.
+constexpr size_t kStaticScratchBytes = size_t(24) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on the current device, looked up once per device.
+hipError_t static_scratch(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace
@@ -696,6 +730,67 @@ int lbm_record_contact_line(lbm_ctx* c, int64_t n, int32_t every, int32_t row, d
 
 int lbm_observables(lbm_ctx* c, lbm_obs* out) {
     return lbm_observables_window(c, -INFINITY, INFINITY, out);
+}
+
+int lbm_observables_of_state(const lbm_params* p, const double* d_f, const double* d_gw,
+                             void* stream, lbm_obs* out) {
+    if (!out || !d_f) return LBM_E_INVAL;
+    std::string msg;
+    int rc = validate(p, &msg);
+    if (rc) {
+        g_create_err = "observables_of_state: " + msg;
+        return rc;
+    }
+    if (is_mask(p) || (p->walls && !d_gw) || ((uintptr_t)d_f) % 8 || ((uintptr_t)d_gw) % 8) {
+        g_create_err = "observables_of_state: a solid mask, a missing G_w or a misaligned array";
+        return LBM_E_INVAL;
+    }
+    // the caller's arrays are dense: row pitch nx, plane nx * ny
+    Layout L{};
+    L.pitch = p->nx;
+    L.plane = (long long)p->nx * p->ny;
+    const KParams P = kparams_of(p, L);
+    const size_t plane_b = align_up((size_t)L.plane * sizeof(double), kAlign);
+    const size_t part_b = align_up((size_t)lbm::obs_blocks(P) * lbm::OBS_NQ * sizeof(double), kAlign);
+    const size_t need = 2 * plane_b + part_b + align_up(32 * sizeof(double), kAlign);
+    if (need > kStaticScratchBytes) {
+        g_create_err = "observables_of_state: the lattice needs " + std::to_string(need) +
+                       " bytes of scratch, more than the " + std::to_string(kStaticScratchBytes) +
+                       "-byte static array";
+        return LBM_E_SIZE;
+    }
+    (void)hipGetLastError();  // report only errors of this call
+    void* base = nullptr;
+    hipError_t e = static_scratch(&base);
+    if (e != hipSuccess) return create_fail(LBM_E_HIP, "observables_of_state: scratch address", e);
+    char* w = (char*)base;
+    double* rho = (double*)w;
+    double* psi = (double*)(w + plane_b);
+    double* part = (double*)(w + 2 * plane_b);
+    double* fin = (double*)(w + 2 * plane_b + part_b);
+    hipStream_t s = (hipStream_t)stream;
+    // the array keeps the previous call's contents: rows no kernel below writes must read 0
+    if (p->walls && !p->ghost_psi) {
+        e = lbm::launch_zero(psi, (size_t)p->nx * sizeof(double), s);
+        if (e == hipSuccess)
+            e = lbm::launch_zero(psi + (size_t)(p->ny - 1) * p->nx, (size_t)p->nx * sizeof(double), s);
+        if (e != hipSuccess) return create_fail(LBM_E_HIP, "observables_of_state: clear", e);
+    }
+    lbm::ObsArgs A;
+    const double yw = wall_plane(p->walls);
+    A.rho_mid = 0.5 * (p->rho_l + p->rho_v);
+    A.y_min = yw + 3.0;
+    A.x_lo = -INFINITY;
+    A.x_hi = INFINITY;
+    A.cx = 0.5 * P.nx;
+    A.cy = yw;
+    e = lbm::launch_rho_psi(P, d_f, psi, rho, s, true);
+    if (e == hipSuccess) e = lbm::launch_obs(P, d_f, rho, psi, d_gw, A, part, fin, s, true);
+    double q[32];
+    if (e == hipSuccess) e = host_copy(s, q, fin, lbm::OBS_NQ * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return create_fail(LBM_E_HIP, "observables_of_state", e);
+    obs_from_sums(q, A, 0, out);
+    return out->nonfinite ? LBM_E_NONFINITE : LBM_OK;
 }
 
 // Read-outs use the idle population buffer as scratch: the next step overwrites it.

@@ -77,6 +77,8 @@ SIGNATURES = {
     "lbm_observables_window": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.POINTER(Obs)]),
     "lbm_observables_plane": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double,
                                         C.POINTER(Obs)]),
+    "lbm_observables_of_state": (C.c_int, [_P, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.POINTER(Obs)]),
     "lbm_record_contact_line": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
                                           C.c_void_p, C.c_size_t]),
     "lbm_batch_create_masked": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(_dp),
@@ -254,6 +256,29 @@ def workspace_size(q: Params) -> int:
     n = C.c_size_t()
     check(lib().lbm_workspace_size(C.byref(q), C.byref(n)))
     return n.value
+
+
+def observables_of_state(params, f, gw=None, stream=None, allow_nonfinite=False) -> dict:
+    """Observables of pre-collision populations the caller holds on the device: f a contiguous
+    float64 tensor of shape (9, ny, nx) (the layout of Sim.f()), gw (2, nx) on the same device or
+    None with periodic y. Runs the library's allocation-free entry point (its scratch is a fixed
+    device array of the library)."""
+    import torch
+
+    q = params if isinstance(params, Params) else make_params(params)
+    assert f.is_cuda and f.dtype == torch.float64 and f.is_contiguous()
+    assert tuple(f.shape) == (9, q.ny, q.nx)
+    if gw is not None:
+        assert gw.is_cuda and gw.dtype == torch.float64 and gw.is_contiguous()
+        assert tuple(gw.shape) == (2, q.nx) and gw.device == f.device
+    st = stream if stream is not None else torch.cuda.current_stream(f.device)
+    o = Obs()
+    rc = lib().lbm_observables_of_state(C.byref(q), C.c_void_p(f.data_ptr()),
+                                        C.c_void_p(gw.data_ptr() if gw is not None else 0),
+                                        C.c_void_p(st.cuda_stream), C.byref(o))
+    if not (rc == E_NONFINITE and allow_nonfinite):
+        check(rc)
+    return o.as_dict()
 
 
 class Sim:
