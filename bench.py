@@ -127,6 +127,20 @@ def cpu_baseline(budget_s: float = 12.0) -> dict:
                       f"{dt:.1f} s"}
 
 
+def cpu_baseline_single_core(budget_s: float = 10.0) -> dict:
+    """cpu_baseline on one core: the same oracle sample in a child process started with
+    OMP_NUM_THREADS=1 (the thread count of the oracle's OpenMP loops is fixed at process start)."""
+    import subprocess
+
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
+                        str(budget_s)], env=env, capture_output=True, text=True,
+                       timeout=4 * budget_s + 300)
+    if r.returncode != 0:
+        return {"error": r.stderr[-400:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def _timed(fn, stream=None):
     """Seconds of device time of fn(), with HIP events on the stream its work is launched on."""
     import torch
@@ -774,10 +788,15 @@ def main():
     ap.add_argument("--c5-adj-steps", type=int, default=2_000,
                     help="steps of the c5 gradient run (0: forward only)")
     ap.add_argument("--c5-K", type=int, default=45)
+    ap.add_argument("--cpu-baseline-only", type=float, default=None, metavar="SECONDS",
+                    help="print the oracle's cpu_baseline over a budget of SECONDS (no GPU use)")
     ap.add_argument("--profile-probe", action="store_true",
                     help="for counter runs: a device copy of known size, then 20 step launches "
                          "of one run of the workload; prints no JSON")
     args = ap.parse_args()
+    if args.cpu_baseline_only is not None:
+        print(json.dumps(cpu_baseline(args.cpu_baseline_only)), flush=True)
+        return
 
     if args.steps % 2:
         args.steps += 1  # two steps per launch: keep the timed region a whole number of launches
@@ -913,6 +932,7 @@ def main():
         out["adjoint"] = adjoint_speedup(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"]["single_core"] = cpu_baseline_single_core()
     print(json.dumps(out), flush=True)
 
 

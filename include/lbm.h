@@ -143,6 +143,29 @@ int lbm_workspace_size(const lbm_params *p, size_t *bytes);
 int lbm_create(const lbm_params *p, const double *gw_host, const double *rho0_host, void *d_ws,
                size_t ws_bytes, void *stream, lbm_ctx **out);
 
+/* Initial state generated on the device: liquid droplets in their vapour (Sec. III: a droplet
+ * placed on the wall relaxes to its contact angle; the tanh profile below replaces the sharp
+ * step of Eq. 16, which at density ratio 500 starts with a shock). On every fluid node
+ *     rho0 = max_k [ (rho_l + rho_v)/2 - (rho_l - rho_v)/2 tanh(2 (d_k - radius[k]) / width) ]
+ * with d_k the distance of (x, y) from (x0[k], y0[k]) in lattice units, then, when jitter > 0,
+ *     rho0 <- rho0 (1 + jitter (2u - 1)),
+ * u = (splitmix64(splitmix64(seed) + y nx + x) >> 11) 2^-53 with S. Vigna's SplitMix64 (all
+ * arithmetic modulo 2^64). */
+#define LBM_MAX_DROPLETS 64
+typedef struct {
+    int32_t count;    /* 1 .. LBM_MAX_DROPLETS */
+    int32_t reserved; /* must be 0 */
+    double x0[LBM_MAX_DROPLETS], y0[LBM_MAX_DROPLETS], radius[LBM_MAX_DROPLETS]; /* radius > 0 */
+    double width;     /* > 0 */
+    double jitter;    /* 0 <= jitter < 1 (0: none) */
+    uint64_t seed;
+} lbm_droplets;
+
+/* lbm_create with the initial density of `drops` (copied) computed on the device instead of a
+ * host array; walls 0, 1 or 2 (LBM_E_INVAL for a solid mask or an invalid description). */
+int lbm_create_droplets(const lbm_params *p, const double *gw_host, const lbm_droplets *drops,
+                        void *d_ws, size_t ws_bytes, void *stream, lbm_ctx **out);
+
 /* Create a context on an arbitrary solid geometry (p->walls = LBM_WALLS_MASK, ghost_psi = 0;
  * rough surfaces of Sec. III.B). solid_host: [ny][nx] bytes, nonzero = solid node; gw_host:
  * [ny][nx] G_w of every solid node (values on fluid nodes are ignored); rho0_host: [ny][nx]
@@ -224,7 +247,8 @@ int lbm_set_gw(lbm_ctx *c, const double *gw_host);
  *          algorithmic bytes per lattice update), tile 64x8;
  *   1      two passes (psi pass, then the force-collide-stream pass reading psi through LDS);
  *   2      (default) two time steps per launch (the first step's populations stay in LDS;
- *          72 bytes per lattice update), an odd remainder step runs fused;
+ *          72 bytes per lattice update), an odd remainder step runs fused; output tile 64x8,
+ *          or 64x4 when 64x8 tiles would give fewer than 512 workgroups;
  *   16+t   fused with tile shape t (0..7: 64x4, 64x8, 64x16, 128x4, and the overlapped
  *          62-column tiles with 4, 6, 8, 14 rows);
  *   32+t   two steps per launch with output tile t (0..3: 64x8, 64x4, 128x4, 64x16).
@@ -250,8 +274,11 @@ int lbm_set_schedule(lbm_ctx *c, int32_t schedule);
  *     lbm_forward_ckpt on the same context (LBM_E_STATE otherwise). It recomputes each segment of
  *     K steps from its checkpoint, runs the adjoint steps in reverse and writes dL/dG_w into the
  *     device array d_grad [2][nx] (row 0 bottom wall, row 1 top wall). Asynchronous on the
- *     context stream; the context's own state is left at step N.
- * Memory: ceil(N/K) + K states of 9 * ny * round_up(nx, 32) doubles, plus 26 planes.
+ *     context stream; the context's own state is left at step N. The recomputation of the next
+ *     segment runs on a stream the context creates on first use (default priority, destroyed by
+ *     lbm_destroy) while the current segment is reversed; the context stream waits for it, so
+ *     all of the call's work is ordered before later work on the context stream.
+ * Memory: ceil(N/K) + 2K states of 9 * ny * round_up(nx, 32) doubles, plus 26 planes.
  */
 int lbm_adjoint_workspace_size(const lbm_params *p, int64_t nsteps, int32_t K, size_t *bytes);
 int lbm_forward_ckpt(lbm_ctx *c, int64_t nsteps, int32_t K, void *d_ws, size_t bytes);

@@ -38,6 +38,10 @@ struct lbm_ctx {
     int64_t adj_start, adj_nsteps;
     int32_t adj_K;
     const void* adj_ws;
+    // lbm_backward recomputes the next segment on a stream of its own (default priority) while
+    // the caller's stream runs the current one in reverse; created on first use
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_start = nullptr, ev_rc[2] = {}, ev_free[2] = {};
     std::string err;
 };
 
@@ -278,10 +282,12 @@ struct AdjLayout {
         total;
 };
 
-// Adjoint workspace: the checkpoints, one segment of states, then the adjoint quantities of two
-// consecutive reverse steps (a: 9 planes, q: 2 planes, p0, psi', r: 4 rows, each twice) and the
-// G_w gradient; the adjoint part is cleared at the start of every backward pass.
-AdjLayout adj_layout_of(const lbm_params* p, int64_t nsteps, int32_t K) {
+// Adjoint workspace: the checkpoints, the segment store (segs of them, K states each), then the
+// adjoint quantities of two consecutive reverse steps (a: 9 planes, q: 2 planes, p0, psi', r: 4
+// rows, each twice) and the G_w gradient; the adjoint part is cleared at the start of every
+// backward pass. A single lattice keeps two segment stores (one recomputed while the other is
+// reversed), an ensemble instance one.
+AdjLayout adj_layout_of(const lbm_params* p, int64_t nsteps, int32_t K, int segs) {
     AdjLayout A;
     Layout L = layout_of(p);
     A.nck = (nsteps + K - 1) / K;
@@ -293,7 +299,7 @@ AdjLayout adj_layout_of(const lbm_params* p, int64_t nsteps, int32_t K) {
     tmp.y_lo = p->walls ? 1 : 0; tmp.y_hi = p->walls ? p->ny - 2 : p->ny - 1;
     size_t o = 0;
     A.off_ck = o; o += (size_t)A.nck * A.fbytes;
-    A.off_seg = o; o += (size_t)K * A.fbytes;
+    A.off_seg = o; o += (size_t)segs * K * A.fbytes;
     A.off_a = o; o += 2 * A.fbytes;
     A.off_q = o; o += 4 * A.pbytes;
     A.off_p0 = o; o += 2 * A.pbytes;
@@ -475,25 +481,48 @@ static std::vector<unsigned short> mask_links(const lbm_params* p, const uint8_t
     return lk;
 }
 
+// Droplet description checks: count in 1..64, finite centres, positive radii and width, jitter in
+// [0, 1) (so that every generated density stays positive).
+static bool droplets_ok(const lbm_droplets* d) {
+    if (!d || d->count < 1 || d->count > LBM_MAX_DROPLETS || d->reserved != 0) return false;
+    if (!finite_pos(d->width) || !std::isfinite(d->jitter) || d->jitter < 0.0 || d->jitter >= 1.0)
+        return false;
+    for (int k = 0; k < d->count; ++k)
+        if (!std::isfinite(d->x0[k]) || !std::isfinite(d->y0[k]) || !finite_pos(d->radius[k]))
+            return false;
+    return true;
+}
+
+static uint64_t splitmix64_host(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// One of rho0_host (host density field) and drops (droplets generated on the device) is given.
 static int create_impl(const lbm_params* p, const uint8_t* solid, const double* gw_host,
-                       const double* rho0_host, void* d_ws, size_t ws_bytes, void* stream,
-                       lbm_ctx** out) {
+                       const double* rho0_host, const lbm_droplets* drops, void* d_ws,
+                       size_t ws_bytes, void* stream, lbm_ctx** out) {
     if (!out) return LBM_E_INVAL;
     *out = nullptr;
     std::string msg;
     int rc = validate(p, &msg);
     if (rc) return rc;
-    if (!rho0_host || !d_ws) return LBM_E_INVAL;
+    if (!rho0_host == !drops || !d_ws) return LBM_E_INVAL;
+    if (drops && (solid || !droplets_ok(drops))) return LBM_E_INVAL;
     if (p->walls && !gw_host) return LBM_E_INVAL;
     if (is_mask(p) != (solid != nullptr)) return LBM_E_INVAL;
-    long long nfluid = 0;
-    for (long long i = 0; i < (long long)p->nx * p->ny; ++i) {
-        const int y = (int)(i / p->nx);
-        if (solid ? solid[i] != 0 : (y < y_lo_of(p) || y > y_hi_of(p))) continue;
-        if (!finite_pos(rho0_host[i])) return LBM_E_INVAL;
-        ++nfluid;
+    if (rho0_host) {
+        long long nfluid = 0;
+        for (long long i = 0; i < (long long)p->nx * p->ny; ++i) {
+            const int y = (int)(i / p->nx);
+            if (solid ? solid[i] != 0 : (y < y_lo_of(p) || y > y_hi_of(p))) continue;
+            if (!finite_pos(rho0_host[i])) return LBM_E_INVAL;
+            ++nfluid;
+        }
+        if (nfluid == 0) return LBM_E_INVAL;
     }
-    if (nfluid == 0) return LBM_E_INVAL;
     const int gw_rows = solid ? p->ny : 2;
     if (gw_host)
         for (long long i = 0; i < (long long)gw_rows * p->nx; ++i)
@@ -519,7 +548,9 @@ static int create_impl(const lbm_params* p, const uint8_t* solid, const double* 
     c->step = 0;
     c->schedule = 2;  // two steps per launch (bit-identical to single steps, fastest)
     c->tile = 1;
-    c->tile2 = 0;
+    // 64 x 8 output tiles, or 64 x 4 on lattices that would give fewer than 512 workgroups with
+    // those (twice the workgroups on the 256 compute units)
+    c->tile2 = ((p->nx + 63) / 64) * ((y_hi_of(p) - y_lo_of(p) + 8) / 8) < 512 ? 1 : 0;
     c->adj_start = -1;
     c->adj_nsteps = 0;
     c->adj_K = 0;
@@ -544,8 +575,25 @@ static int create_impl(const lbm_params* p, const uint8_t* solid, const double* 
     }
     // rho0 into plane 1 of the second population buffer, then the first buffer built from it
     double* rho0 = c->g[1] + L.plane;
-    e = upload_field(s, rho0_host, 1, p->ny, p->nx, c->g[1], rho0, 0, L.pitch);
-    if (e != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create: rho0 copy", e); }
+    if (rho0_host) {
+        e = upload_field(s, rho0_host, 1, p->ny, p->nx, c->g[1], rho0, 0, L.pitch);
+        if (e != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create: rho0 copy", e); }
+    } else {
+        lbm::DropletArgs D{};
+        D.count = drops->count;
+        for (int k = 0; k < drops->count; ++k) {
+            D.x0[k] = drops->x0[k];
+            D.y0[k] = drops->y0[k];
+            D.r[k] = drops->radius[k];
+        }
+        D.mid = 0.5 * (p->rho_l + p->rho_v);
+        D.half = 0.5 * (p->rho_l - p->rho_v);
+        D.width = drops->width;
+        D.jitter = drops->jitter;
+        D.base = splitmix64_host(drops->seed);
+        e = lbm::launch_droplets(c->kp, D, rho0, s);
+        if (e != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create: droplets", e); }
+    }
     if ((e = lbm::launch_init(c->kp, rho0, c->g[0], s)) != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create launch_init", e); }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) { delete c; return create_fail(LBM_E_HIP, "create hipStreamSynchronize", e); }
     *out = c;
@@ -558,7 +606,20 @@ int lbm_create(const lbm_params* p, const double* gw_host, const double* rho0_ho
         if (out) *out = nullptr;
         return LBM_E_INVAL;  // a solid mask is given through lbm_create_masked
     }
-    return create_impl(p, nullptr, gw_host, rho0_host, d_ws, ws_bytes, stream, out);
+    return create_impl(p, nullptr, gw_host, rho0_host, nullptr, d_ws, ws_bytes, stream, out);
+}
+
+int lbm_create_droplets(const lbm_params* p, const double* gw_host, const lbm_droplets* drops,
+                        void* d_ws, size_t ws_bytes, void* stream, lbm_ctx** out) {
+    if (p && is_mask(p)) {
+        if (out) *out = nullptr;
+        return LBM_E_INVAL;
+    }
+    if (!drops) {
+        if (out) *out = nullptr;
+        return LBM_E_INVAL;
+    }
+    return create_impl(p, nullptr, gw_host, nullptr, drops, d_ws, ws_bytes, stream, out);
 }
 
 int lbm_create_masked(const lbm_params* p, const uint8_t* solid_host, const double* gw_host,
@@ -568,7 +629,7 @@ int lbm_create_masked(const lbm_params* p, const uint8_t* solid_host, const doub
         if (out) *out = nullptr;
         return LBM_E_INVAL;
     }
-    return create_impl(p, solid_host, gw_host, rho0_host, d_ws, ws_bytes, stream, out);
+    return create_impl(p, solid_host, gw_host, rho0_host, nullptr, d_ws, ws_bytes, stream, out);
 }
 
 int lbm_set_schedule(lbm_ctx* c, int32_t schedule) {
@@ -890,7 +951,7 @@ int lbm_adjoint_workspace_size(const lbm_params* p, int64_t nsteps, int32_t K, s
     int rc = validate(p, nullptr);
     if (rc) return rc;
     if (p->walls != LBM_WALLS_BOUNCE_BACK) return LBM_E_INVAL;  // objective and adjoint: bounce-back walls
-    *bytes = adj_layout_of(p, nsteps, K).total;
+    *bytes = adj_layout_of(p, nsteps, K, 2).total;
     return LBM_OK;
 }
 
@@ -911,10 +972,24 @@ int lbm_loss(lbm_ctx* c, double w_centroid, double w_wet, double* L) {
     return std::isfinite(*L) ? LBM_OK : fail(c, LBM_E_NONFINITE, "non-finite loss");
 }
 
+// The auxiliary stream and events of lbm_backward, created on first use on the context's device.
+static hipError_t adj_streams(lbm_ctx* c) {
+    if (c->aux) return hipSuccess;
+    hipError_t e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        c->aux = nullptr;
+        return e;
+    }
+    hipEvent_t* evs[5] = {&c->ev_start, &c->ev_rc[0], &c->ev_rc[1], &c->ev_free[0], &c->ev_free[1]};
+    for (hipEvent_t* ev : evs)
+        if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+    return e;
+}
+
 int lbm_forward_ckpt(lbm_ctx* c, int64_t nsteps, int32_t K, void* d_adj, size_t bytes) {
     if (!c || !d_adj || nsteps < 1 || K < 1 || c->p.walls != LBM_WALLS_BOUNCE_BACK)
         return LBM_E_INVAL;
-    AdjLayout A = adj_layout_of(&c->p, nsteps, K);
+    AdjLayout A = adj_layout_of(&c->p, nsteps, K, 2);
     if (bytes < A.total) return fail(c, LBM_E_SIZE, "adjoint workspace too small");
     if (((uintptr_t)d_adj) % kAlign) return fail(c, LBM_E_INVAL, "adjoint workspace misaligned");
     char* w = (char*)d_adj;
@@ -937,7 +1012,7 @@ int lbm_backward(lbm_ctx* c, int64_t nsteps, int32_t K, void* d_adj, size_t byte
                  double w_centroid, double w_wet, double* d_grad_gw) {
     if (!c || !d_adj || !d_grad_gw || nsteps < 1 || K < 1 || c->p.walls != LBM_WALLS_BOUNCE_BACK)
         return LBM_E_INVAL;
-    AdjLayout A = adj_layout_of(&c->p, nsteps, K);
+    AdjLayout A = adj_layout_of(&c->p, nsteps, K, 2);
     if (bytes < A.total) return fail(c, LBM_E_SIZE, "adjoint workspace too small");
     if (c->adj_ws != d_adj || c->adj_nsteps != nsteps || c->adj_K != K ||
         c->step != c->adj_start + nsteps)
@@ -963,28 +1038,54 @@ int lbm_backward(lbm_ctx* c, int64_t nsteps, int32_t K, void* d_adj, size_t byte
     double* gg = (double*)(w + A.off_gg);
     e = lbm::launch_loss_seed(P, w_centroid, w_wet, yc, sums[0], p0_buf[0], dpsi_buf[0], s);
     if (e != hipSuccess) return hip_fail(c, e, "loss seed");
+    // Segment j is recomputed from its checkpoint into store j % 2 on the auxiliary stream while
+    // the context stream runs segment j + 1 in reverse; the reverse sweep of segment j waits for
+    // its recomputation (ev_rc), and the recomputation of segment j - 2 into the same store waits
+    // for the reverse sweep of segment j (ev_free).
+    if ((e = adj_streams(c)) != hipSuccess) return hip_fail(c, e, "adjoint stream");
+    auto seg = [&](int64_t j, int64_t i) {
+        return (double*)(w + A.off_seg + ((size_t)(j & 1) * K + (size_t)i) * A.fbytes);
+    };
+    auto seg_len = [&](int64_t j) { return std::min<int64_t>(K, nsteps - j * K); };
+    auto recompute = [&](int64_t j) -> hipError_t {
+        hipStream_t a = c->aux;
+        hipError_t r = hipMemcpyAsync(seg(j, 0), w + A.off_ck + (size_t)j * A.fbytes, fb,
+                                      hipMemcpyDeviceToDevice, a);
+        const int64_t len = seg_len(j);
+        int64_t i = 0;
+        // two steps per launch, the first one written too
+        for (; i + 2 <= len - 1 && r == hipSuccess; i += 2)
+            r = lbm::launch_step2(P, c->tile2, seg(j, i), seg(j, i + 2), c->gw, a, seg(j, i + 1));
+        if (i + 1 <= len - 1 && r == hipSuccess)
+            r = lbm::launch_step(P, 0, c->tile, seg(j, i), seg(j, i + 1), c->psi, c->gw, a);
+        if (r == hipSuccess) r = hipEventRecord(c->ev_rc[j & 1], a);
+        return r;
+    };
+    e = hipEventRecord(c->ev_start, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->aux, c->ev_start, 0);
+    if (e == hipSuccess) e = recompute(A.nck - 1);
+    if (e != hipSuccess) return hip_fail(c, e, "segment recompute");
     int k = 0;  // buffers of the later step
     for (int64_t j = A.nck - 1; j >= 0; --j) {
-        const int64_t len = std::min<int64_t>(K, nsteps - j * K);
-        auto seg = [&](int64_t i) { return (double*)(w + A.off_seg + (size_t)i * A.fbytes); };
-        e = hipMemcpyAsync(seg(0), w + A.off_ck + (size_t)j * A.fbytes, fb, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) return hip_fail(c, e, "segment restore");
-        // recompute the segment's states, two steps per launch (the first one written too)
-        int64_t i = 0;
-        for (; i + 2 <= len - 1 && e == hipSuccess; i += 2)
-            e = lbm::launch_step2(P, c->tile2, seg(i), seg(i + 2), c->gw, s, seg(i + 1));
-        if (i + 1 <= len - 1 && e == hipSuccess)
-            e = lbm::launch_step(P, 0, c->tile, seg(i), seg(i + 1), c->psi, c->gw, s);
-        if (e != hipSuccess) return hip_fail(c, e, "segment recompute");
-        // then its adjoint steps in reverse
-        for (i = len - 1; i >= 0; --i) {
-            lbm::AdjPtrs ap{seg(i),       a_buf[k],     q_buf[k],     p0_buf[k],
+        if (j >= 1) {
+            // the store of segment j - 1 last held segment j + 1
+            if (j + 1 <= A.nck - 1) e = hipStreamWaitEvent(c->aux, c->ev_free[(j + 1) & 1], 0);
+            if (e == hipSuccess) e = recompute(j - 1);
+            if (e != hipSuccess) return hip_fail(c, e, "segment recompute");
+        }
+        e = hipStreamWaitEvent(s, c->ev_rc[j & 1], 0);
+        if (e != hipSuccess) return hip_fail(c, e, "segment wait");
+        // the segment's adjoint steps in reverse
+        for (int64_t i = seg_len(j) - 1; i >= 0; --i) {
+            lbm::AdjPtrs ap{seg(j, i),    a_buf[k],     q_buf[k],     p0_buf[k],
                             dpsi_buf[k],  rv_buf[k],    c->gw,        a_buf[k ^ 1],
                             q_buf[k ^ 1], p0_buf[k ^ 1], dpsi_buf[k ^ 1], rv_buf[k ^ 1], gg};
             e = lbm::launch_adj(P, ap, s);
             if (e != hipSuccess) return hip_fail(c, e, "adjoint step");
             k ^= 1;
         }
+        e = hipEventRecord(c->ev_free[j & 1], s);
+        if (e != hipSuccess) return hip_fail(c, e, "segment event");
     }
     e = lbm::launch_adj_gw(P, rv_buf[k], gg, s);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint wall gradient");
@@ -1519,7 +1620,7 @@ int batch_adj_layout(const lbm_batch* b, int64_t nsteps, int32_t K, BatchAdjLayo
     L->off_tiles = o;
     o += align_up((size_t)nt * sizeof(int), kAlign);
     for (int i = 0; i < b->count; ++i) {
-        L->A[i] = adj_layout_of(&b->p[i], nsteps, K);
+        L->A[i] = adj_layout_of(&b->p[i], nsteps, K, 1);
         L->off[i] = o;
         o += L->A[i].total;
     }
@@ -1757,7 +1858,14 @@ int lbm_autotune(const lbm_params* p, int32_t count, const double* const* gw_hos
 int lbm_destroy(lbm_ctx* c) {
     if (!c) return LBM_E_INVAL;
     // queued launches still use the workspace: the caller may release it once this returns
-    const hipError_t e = hipStreamSynchronize(c->stream);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (c->aux) {
+        const hipError_t e2 = hipStreamSynchronize(c->aux);
+        if (e == hipSuccess) e = e2;
+        for (hipEvent_t ev : {c->ev_start, c->ev_rc[0], c->ev_rc[1], c->ev_free[0], c->ev_free[1]})
+            if (ev) (void)hipEventDestroy(ev);
+        (void)hipStreamDestroy(c->aux);
+    }
     delete c;
     return e == hipSuccess ? LBM_OK : LBM_E_HIP;
 }

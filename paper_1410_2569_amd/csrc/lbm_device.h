@@ -1156,12 +1156,12 @@ __device__ __forceinline__ void collide_adj(const KParams& P, const double f[9],
     fb[8] = rb + bd + X - Y - m8b;
 }
 
-// nu = dL/dg at fluid node (x, y): the transpose of pull streaming with bounce-back applied to
-// lambda = a + c 1 (a: 9 planes, c: one scalar plane read from an LDS tile; l: the node's slot,
-// W: row stride), i.e. g_b(y) feeds f_b(y + e_b), or f_opp(b)(y) when y + e_b is solid.
-__device__ __forceinline__ void push_gather_lds(const KParams& P, const double* __restrict__ a,
-                                                const double* cs, int W, int l, int x, int y,
-                                                double nu[9]) {
+// nu = dL/dg at fluid node (x, y) is the transpose of pull streaming with bounce-back applied to
+// lambda = a + c 1 (a: 9 planes, c: one scalar plane): g_b(y) feeds f_b(y + e_b), or f_opp(b)(y)
+// when y + e_b is solid. push_gather_a reads the a part from HBM (av[b]); push_add_c adds c from
+// an LDS tile (l: the node's slot, W: row stride), the same source node for each b.
+__device__ __forceinline__ void push_gather_a(const KParams& P, const double* __restrict__ a,
+                                              int x, int y, double av[9]) {
     const unsigned nx = P.nx, pitch = P.pitch;
     const unsigned ux = x;
     const unsigned xm = ux == 0 ? nx - 1 : ux - 1;
@@ -1179,18 +1179,32 @@ __device__ __forceinline__ void push_gather_lds(const KParams& P, const double* 
     const long long pl = P.plane;
     const unsigned r0 = (unsigned)y * pitch, rm = ym * pitch, rp = yp * pitch;
     const unsigned i0 = r0 + ux;
-    const double c0 = cs[l];
-    nu[0] = a[i0] + c0;
-    nu[1] = (a + 1 * pl)[r0 + xp] + cs[l + 1];
-    nu[3] = (a + 3 * pl)[r0 + xm] + cs[l - 1];
+    av[0] = a[i0];
+    av[1] = (a + 1 * pl)[r0 + xp];
+    av[3] = (a + 3 * pl)[r0 + xm];
     // e_y = +1 populations travel up: reflected at the top wall
-    nu[2] = top ? (a + 4 * pl)[i0] + c0 : (a + 2 * pl)[rp + ux] + cs[l + W];
-    nu[5] = top ? (a + 7 * pl)[i0] + c0 : (a + 5 * pl)[rp + xp] + cs[l + W + 1];
-    nu[6] = top ? (a + 8 * pl)[i0] + c0 : (a + 6 * pl)[rp + xm] + cs[l + W - 1];
+    av[2] = top ? (a + 4 * pl)[i0] : (a + 2 * pl)[rp + ux];
+    av[5] = top ? (a + 7 * pl)[i0] : (a + 5 * pl)[rp + xp];
+    av[6] = top ? (a + 8 * pl)[i0] : (a + 6 * pl)[rp + xm];
     // e_y = -1 populations travel down: reflected at the bottom wall
-    nu[4] = bot ? (a + 2 * pl)[i0] + c0 : (a + 4 * pl)[rm + ux] + cs[l - W];
-    nu[7] = bot ? (a + 5 * pl)[i0] + c0 : (a + 7 * pl)[rm + xm] + cs[l - W - 1];
-    nu[8] = bot ? (a + 6 * pl)[i0] + c0 : (a + 8 * pl)[rm + xp] + cs[l - W + 1];
+    av[4] = bot ? (a + 2 * pl)[i0] : (a + 4 * pl)[rm + ux];
+    av[7] = bot ? (a + 5 * pl)[i0] : (a + 7 * pl)[rm + xm];
+    av[8] = bot ? (a + 6 * pl)[i0] : (a + 8 * pl)[rm + xp];
+}
+
+__device__ __forceinline__ void push_add_c(const KParams& P, const double av[9], const double* cs,
+                                           int W, int l, int y, double nu[9]) {
+    const bool top = P.walls && y == P.ny - 2, bot = P.walls && y == 1;
+    const double c0 = cs[l];
+    nu[0] = av[0] + c0;
+    nu[1] = av[1] + cs[l + 1];
+    nu[3] = av[3] + cs[l - 1];
+    nu[2] = av[2] + (top ? c0 : cs[l + W]);
+    nu[5] = av[5] + (top ? c0 : cs[l + W + 1]);
+    nu[6] = av[6] + (top ? c0 : cs[l + W - 1]);
+    nu[4] = av[4] + (bot ? c0 : cs[l - W]);
+    nu[7] = av[7] + (bot ? c0 : cs[l - W - 1]);
+    nu[8] = av[8] + (bot ? c0 : cs[l - W + 1]);
 }
 
 // xi = dL/dpsi of node (x, y) = p0 + sum_a w_a e_a . q(x - e_a) (+ the mirrored ghost rows, whose
@@ -1276,6 +1290,8 @@ __device__ __forceinline__ void adj_tile(const KParams& P, const AdjPtrs& A, int
     const int x = x0 + tx, y = y0 + ty;
     const bool active = x < P.nx && y <= P.y_hi;
 
+    // Every global load is issued before the first barrier: the forward node, psi of the ring,
+    // q of two rings, the a part of the transposed streaming, p0 and psi' of the c ring and G_w.
     // forward node and psi on the tile and one ring
     double f[9];
     double rho = 1.0, psi_c = 0.0;
@@ -1283,6 +1299,34 @@ __device__ __forceinline__ void adj_tile(const KParams& P, const AdjPtrs& A, int
         pull9<GEO_ROWS>(P, A.gprev, x, y, f);
         rho = sum9(f);
         psi_c = psi_of_rho(P, rho);
+    }
+    double av[9];
+    if (active) push_gather_a(P, A.a_in, x, y, av);
+    double Ax = 0.0, Ay = 0.0;
+    const bool wall_row = P.walls && (y == 1 || y == P.ny - 2);
+    if (active && wall_row) adhesion_sum(P, A.gw, x, y, Ax, Ay);
+    // p0 and psi' of the later step on this thread's slots of the c ring
+    constexpr int NC = (TY + 2) * LW, NCR = (NC + NT - 1) / NT;
+    double p0v[NCR], dpv[NCR];
+    bool flv[NCR];
+#pragma unroll
+    for (int r = 0; r < NCR; ++r) {
+        const int s = threadIdx.x + r * NT;
+        p0v[r] = 0.0;
+        dpv[r] = 0.0;
+        flv[r] = false;
+        if (s >= NC) continue;
+        const int gx = wrapx(x0 - 1 + s % LW, P.nx);
+        int gy = y0 - 1 + s / LW;
+        if (P.walls) {
+            if (gy < 1 || gy > P.ny - 2) continue;
+        } else {
+            gy = wrapx(gy, P.ny);
+        }
+        const unsigned i = (unsigned)gy * P.pitch + gx;
+        p0v[r] = A.p0_in[i];
+        dpv[r] = A.dpsi_in[i];
+        flv[r] = true;
     }
     L.sp[(ty + 1) * LW + tx + 1] = active ? psi_c : psi_at<GEO_ROWS>(P, A.gprev, x, y);
     for (int h = threadIdx.x; h < NH; h += NT) {
@@ -1310,20 +1354,16 @@ __device__ __forceinline__ void adj_tile(const KParams& P, const AdjPtrs& A, int
         L.qy[s] = vy;
     }
     __syncthreads();
-    // c of the later step on the tile and one ring
-    for (int s = threadIdx.x; s < (TY + 2) * LW; s += NT) {
+    // c of the later step on the tile and one ring (0 on the solid rows)
+#pragma unroll
+    for (int r = 0; r < NCR; ++r) {
+        const int s = threadIdx.x + r * NT;
+        if (s >= NC) continue;
         const int hx = s % LW, hy = s / LW;
-        const int gx = wrapx(x0 - 1 + hx, P.nx);
         int gy = y0 - 1 + hy;
-        bool fluid = true;
-        if (P.walls) fluid = gy >= 1 && gy <= P.ny - 2;
-        else gy = wrapx(gy, P.ny);
-        double c = 0.0;
-        if (fluid) {
-            const unsigned i = (unsigned)gy * P.pitch + gx;
-            c = A.dpsi_in[i] * adj_xi(P, L.qx, L.qy, QW, (hy + 1) * QW + hx + 1, gy, A.p0_in[i]);
-        }
-        L.cs[s] = c;
+        if (!P.walls) gy = wrapx(gy, P.ny);
+        L.cs[s] = flv[r] ? dpv[r] * adj_xi(P, L.qx, L.qy, QW, (hy + 1) * QW + hx + 1, gy, p0v[r])
+                         : 0.0;
     }
     __syncthreads();
     if (!active) return;
@@ -1332,12 +1372,9 @@ __device__ __forceinline__ void adj_tile(const KParams& P, const AdjPtrs& A, int
     double sx, sy;
     cohesion_sum(cc[-LW - 1], cc[-LW], cc[-LW + 1], cc[-1], cc[1], cc[LW - 1], cc[LW],
                  cc[LW + 1], sx, sy);
-    double Ax = 0.0, Ay = 0.0;
-    const bool wall_row = P.walls && (y == 1 || y == P.ny - 2);
-    if (wall_row) adhesion_sum(P, A.gw, x, y, Ax, Ay);
 
     double nu[9], fb[9], pb, qx, qy, rx, ry;
-    push_gather_lds(P, A.a_in, L.cs, LW, (ty + 1) * LW + tx + 1, x, y, nu);
+    push_add_c(P, av, L.cs, LW, (ty + 1) * LW + tx + 1, y, nu);
     collide_adj(P, f, rho, psi_c, sx, sy, Ax, Ay, nu, fb, pb, qx, qy, rx, ry);
 
     const unsigned i = (unsigned)y * P.pitch + x;

@@ -45,6 +45,16 @@ hipError_t launch_step2(const KParams& P, int tile2, const double* gin, double* 
                         const double* gw, hipStream_t s, double* gmid = nullptr);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);  // bytes and p 8-byte aligned
 hipError_t launch_init(const KParams& P, const double* rho0, double* g, hipStream_t s);
+// droplets of the initial state (lbm_create_droplets): up to kMaxDroplets tanh profiles
+constexpr int kMaxDroplets = 64;
+struct DropletArgs {
+    int count;
+    double x0[kMaxDroplets], y0[kMaxDroplets], r[kMaxDroplets];
+    double mid, half;            // (rho_l + rho_v) / 2, (rho_l - rho_v) / 2
+    double width, jitter;
+    unsigned long long base;     // splitmix64(seed)
+};
+hipError_t launch_droplets(const KParams& P, const DropletArgs& D, double* rho, hipStream_t s);
 // dense: fout is [9][ny][nx] (otherwise [9][ny][pitch])
 hipError_t launch_pull(const KParams& P, const double* gin, double* fout, hipStream_t s,
                        bool dense = false);

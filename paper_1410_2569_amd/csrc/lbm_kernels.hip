@@ -374,6 +374,48 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
+// SplitMix64 (S. Vigna's public-domain mixer): add the golden-ratio increment, then two
+// xor-shift-multiply rounds and a final xor-shift, all modulo 2^64.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Initial density of liquid droplets in their vapour on every node of the lattice (pitched
+// rows): the largest of the droplets' tanh profiles, times 1 + jitter (2u - 1) with u the
+// node's uniform of the seeded counter stream; 0 on solid rows.
+__global__ __launch_bounds__(256) void k_droplets(KParams P, DropletArgs D, double* __restrict__ rho) {
+#pragma clang fp contract(off)
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= P.nx || y >= P.ny) return;
+    double v = 0.0;
+    if (y >= P.y_lo && y <= P.y_hi) {
+        v = -INFINITY;
+        for (int k = 0; k < D.count; ++k) {
+            const double dx = x - D.x0[k], dy = y - D.y0[k];
+            const double d = sqrt(dx * dx + dy * dy);
+            const double rk = D.mid - D.half * tanh(2.0 * (d - D.r[k]) / D.width);
+            v = fmax(v, rk);
+        }
+        if (D.jitter != 0.0) {
+            const unsigned long long z =
+                splitmix64(D.base + (unsigned long long)y * (unsigned long long)P.nx + x);
+            const double u = (double)(z >> 11) * 0x1.0p-53;
+            v = v * (1.0 + D.jitter * (2.0 * u - 1.0));
+        }
+    }
+    rho[(long long)y * P.pitch + x] = v;
+}
+
+hipError_t launch_droplets(const KParams& P, const DropletArgs& D, double* rho, hipStream_t s) {
+    hipLaunchKernelGGL(k_droplets, dim3((P.nx + 63) / 64, (P.ny + 3) / 4), dim3(256), 0, s, P, D,
+                       rho);
+    return hipGetLastError();
+}
+
 hipError_t launch_init(const KParams& P, const double* rho0, double* g, hipStream_t s) {
     hipLaunchKernelGGL(k_init, node_grid(P), dim3(256), 0, s, P, rho0, g);
     return hipGetLastError();

@@ -51,6 +51,23 @@ class Tune(C.Structure):
         return {"tile": self.tile, "waves_per_cu": self.waves_per_cu, "schedule": self.schedule}
 
 
+class Droplets(C.Structure):
+    _fields_ = [("count", C.c_int32), ("reserved", C.c_int32),
+                ("x0", C.c_double * 64), ("y0", C.c_double * 64), ("radius", C.c_double * 64),
+                ("width", C.c_double), ("jitter", C.c_double), ("seed", C.c_uint64)]
+
+
+def make_droplets(centres, radii, width=2.0, jitter=1e-3, seed=1) -> Droplets:
+    """lbm_droplets for lbm_create_droplets: centres [(x0, y0), ...] and radii in lattice units."""
+    d = Droplets()
+    assert 1 <= len(centres) == len(radii) <= 64
+    d.count = len(centres)
+    for k, ((x0, y0), r) in enumerate(zip(centres, radii)):
+        d.x0[k], d.y0[k], d.radius[k] = float(x0), float(y0), float(r)
+    d.width, d.jitter, d.seed = float(width), float(jitter), int(seed) & 0xFFFFFFFFFFFFFFFF
+    return d
+
+
 class Obs(C.Structure):
     _fields_ = [("step", C.c_int64), ("rho_min", C.c_double), ("rho_max", C.c_double),
                 ("umax", C.c_double), ("umax_liquid", C.c_double), ("mass", C.c_double),
@@ -89,6 +106,8 @@ SIGNATURES = {
                                                 C.POINTER(C.c_int32), C.c_void_p, C.c_size_t]),
     "lbm_create_masked": (C.c_int, [_P, C.c_void_p, _dp, _dp, C.c_void_p, C.c_size_t, C.c_void_p,
                                     C.POINTER(C.c_void_p)]),
+    "lbm_create_droplets": (C.c_int, [_P, _dp, C.POINTER(Droplets), C.c_void_p, C.c_size_t,
+                                      C.c_void_p, C.POINTER(C.c_void_p)]),
     "lbm_read_rho": (C.c_int, [C.c_void_p, _dp, C.c_size_t]),
     "lbm_read_f": (C.c_int, [C.c_void_p, _dp, C.c_size_t]),
     "lbm_state_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
@@ -282,9 +301,10 @@ def observables_of_state(params, f, gw=None, stream=None, allow_nonfinite=False)
 
 
 class Sim:
-    """One lattice on the current HIP device, in a torch-allocated workspace. With
-    walls = 3 ("mask") pass the solid mask ((ny, nx), nonzero = solid) as `solid` (or under
-    params["solid"]) and G_w per node, shape (ny, nx)."""
+    """One lattice on the current HIP device, in a torch-allocated workspace. rho0: the initial
+    density, shape (ny, nx), or a Droplets description (make_droplets) whose density the library
+    generates on the device. With walls = 3 ("mask") pass the solid mask ((ny, nx), nonzero =
+    solid) as `solid` (or under params["solid"]) and G_w per node, shape (ny, nx)."""
 
     def __init__(self, params, gw, rho0, device="cuda", stream=None, solid=None):
         import torch
@@ -301,10 +321,16 @@ class Sim:
         _use_on(self.ws, self.stream)
         gshape = (self.ny, self.nx) if self.masked else (2, self.nx)
         g = np.ascontiguousarray(gw if gw is not None else np.zeros(gshape), dtype=np.float64)
-        r = np.ascontiguousarray(rho0, dtype=np.float64)
-        assert g.shape == gshape and r.shape == (self.ny, self.nx)
+        assert g.shape == gshape
         h = C.c_void_p()
         ws, st = C.c_void_p(self.ws.data_ptr()), C.c_void_p(self.stream.cuda_stream)
+        if isinstance(rho0, Droplets):  # initial density generated on the device
+            check(lib().lbm_create_droplets(C.byref(self.q), _dptr(g), C.byref(rho0), ws, nbytes,
+                                            st, C.byref(h)))
+            self.h = h
+            return
+        r = np.ascontiguousarray(rho0, dtype=np.float64)
+        assert r.shape == (self.ny, self.nx)
         if self.masked:
             m = np.ascontiguousarray(np.asarray(solid) != 0, dtype=np.uint8)
             assert m.shape == (self.ny, self.nx)

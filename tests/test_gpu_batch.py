@@ -155,3 +155,33 @@ def test_c3_viscosity_ratios_long_run(orc, gpu):
         print(f"C3 instance {i} ({q.nx}x{q.ny}, ratio {ens[i]['visc_ratio']:g}, "
               f"{ens[i]['form']}): {steps} steps, {rel:.3e}", flush=True)
         assert rel <= 1e-9
+
+
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_delete_and_reallocate_without_sync(orc, gpu, schedule):
+    """An ensemble dropped right after queuing steps on its own stream, with no synchronisation
+    by the caller: its workspace block must not be handed to the next allocation while those
+    kernels still run (the destroy call waits for the stream; the binding marks the workspace
+    with record_stream), and a second run still gives the same bits."""
+    import torch
+
+    cases = ensemble(orc, n=4, seed=5)
+    args = ([c[0] for c in cases], [c[1] for c in cases], [c[2] for c in cases])
+    tune = {"tile": 1, "schedule": schedule}
+    b = gpu.Batch(*args, tune=tune)
+    b.step(200)
+    ref = [b.f(i) for i in range(len(cases))]
+    del b
+    for _ in range(3):
+        b = gpu.Batch(*args, tune=tune)
+        nbytes = b.ws.numel()
+        b.step(200)
+        del b  # no synchronisation before the block goes back to torch's allocator
+        x = torch.full((nbytes // 8,), 7.0, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        assert bool((x == 7.0).all()), "a freed workspace block was written after reuse"
+        del x
+    b = gpu.Batch(*args, tune=tune)
+    b.step(200)
+    for i in range(len(cases)):
+        assert np.array_equal(b.f(i), ref[i])

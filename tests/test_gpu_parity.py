@@ -313,3 +313,65 @@ def test_c2_full_size_sampled(orc, gpu):
         sim.step(60)
         f = orc.run(q, r["gw"], orc.init_rest(q, rho0), 60)
         assert_f_close(q, sim.f(), f, what=f"C2 {r['form']} G_w={r['G_w']:.3f}")
+
+
+@pytest.mark.parametrize("walls,ghost,eos", [(1, 1, 0), (0, 1, 0), (2, 1, 1), (1, 0, 0)])
+def test_device_droplets_match_host_field(orc, gpu, walls, ghost, eos):
+    """lbm_create_droplets generates the initial density on the device (tanh droplets, seeded
+    multiplicative jitter from SplitMix64): against the seeded host field of the same recipe,
+    every fluid node within 1e-15 of rho_l, the scale of the profile's two terms (the device
+    tanh may differ from the host's in the last bit; in the vapour, rho = (rho_l + rho_v)/2 -
+    (rho_l - rho_v)/2 tanh cancels down to rho_v = rho_l/500, so that bit is 500 times larger
+    relative to rho there), and the same populations after 50 steps within 1e-12."""
+    import paper_1410_2569_amd as L
+
+    nx, ny = 150, 61
+    if eos:  # the paper's Eq. (15) at 500/1
+        p = dict(nx=nx, ny=ny, walls=walls, ghost=ghost, eos="piecewise", th_v=0.64 / 3,
+                 th_m=-0.04 / 3, th_l=1 / 3, rho_v=1.0, rho_l=500.0, G=-1.0, sigma=0.084,
+                 tau_l=1.1, tau_v=1.1, wall_force="modpsi", **synth.RATES)
+    else:
+        p = synth.base_params(nx=nx, ny=ny, wall_force="modpsi", walls=walls, ghost=ghost)
+    q = orc.make_params(p)
+    centres, radii = [(40.3, 0.5), (111.0, 0.5)], [14.5, 9.25]
+    if walls == 0:
+        centres = [(40.3, 30.0), (111.0, 25.5)]
+    rho_host = synth.droplet_rho(nx, ny, q.rho_l, q.rho_v, centres, radii, width=2.0,
+                                 jitter=1e-3, seed=77, walls=walls != 0)
+    gw = synth.gw_uniform(nx, 0.05)
+    pp = dict(p, rho_l=q.rho_l, rho_v=q.rho_v)
+    a = gpu.Sim(pp, gw, rho_host)
+    b = gpu.Sim(pp, gw, L.make_droplets(centres, radii, width=2.0, jitter=1e-3, seed=77))
+    fl = orc.fluid_mask(q)
+    ra, rb = a.rho(), b.rho()
+    rel0 = float(np.abs(ra - rb)[fl].max() / q.rho_l)
+    print(f"walls {walls}: initial max |drho|/rho_l {rel0:.2e}, "
+          f"max rel {float((np.abs(ra - rb)[fl] / ra[fl]).max()):.2e}")
+    assert rel0 <= 1e-15
+    a.step(50)
+    b.step(50)
+    fa, fb = a.f(), b.f()
+    rel = float((np.abs(fa - fb).max(0)[fl] / fa.sum(0)[fl]).max())
+    assert rel <= 1e-12
+
+
+def test_device_droplets_reject_bad_descriptions(orc, gpu):
+    import ctypes as C
+
+    import paper_1410_2569_amd as L
+
+    p = synth.base_params(nx=64, ny=32, wall_force="rho")
+    q = orc.make_params(p)
+    pp = L.make_params(dict(p, rho_l=q.rho_l, rho_v=q.rho_v))
+    gw = np.zeros((2, 64))
+    ws = __import__("torch").empty(L.workspace_size(pp), dtype=__import__("torch").uint8,
+                                   device="cuda")
+    for bad in (dict(radii=[-1.0]), dict(width=0.0), dict(jitter=1.0), dict(jitter=-0.1)):
+        kw = dict(centres=[(32.0, 0.5)], radii=[8.0], width=2.0, jitter=1e-3, seed=1)
+        kw.update(bad)
+        d = L.make_droplets(**kw)
+        h = C.c_void_p()
+        rc = L.lib().lbm_create_droplets(C.byref(pp), gw.ctypes.data_as(C.POINTER(C.c_double)),
+                                         C.byref(d), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                         None, C.byref(h))
+        assert rc == -1 and not h.value, bad
