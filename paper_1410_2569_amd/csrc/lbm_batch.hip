@@ -3,10 +3,11 @@
 // The tiles of every instance form one flattened work-list. Two schedules run the same per-tile
 // device function as the single-instance step (so results are bitwise identical to it):
 //   per-step   one launch per time step over the whole work-list (replayed from a hipGraph);
-//   persistent one launch for n steps: an occupancy-sized grid in which each workgroup owns a
-//              contiguous chunk of the work-list (contiguous per XCD) and advances each of its
-//              tiles two steps (step2_tile), with a grid barrier between the two-step passes (an
-//              odd last step is one per-step launch after it). The barrier publishes the pass's
+//   persistent one launch for n steps: an occupancy-sized grid that walks the work-list G tiles
+//              at a time (workgroup L takes tiles L, L + G, ...; consecutive L on one XCD) and
+//              advances each tile two steps (step2_tile), with a grid barrier between the
+//              two-step passes (an odd last step is one per-step launch after it). The barrier
+//              publishes the pass's
 //              stores at agent scope (release), waits for every workgroup, then acquires; its
 //              64-bit arrival counter cannot wrap, and its wait is bounded and raises an abort
 //              flag on timeout so every workgroup always exits.
@@ -84,7 +85,11 @@ __device__ __forceinline__ bool grid_barrier(unsigned long long* bar, unsigned l
 }
 
 // npairs two-step passes over the work-list in one launch (the tiles are the output tiles of
-// step2_tile, as in k_batch_step2).
+// step2_tile, as in k_batch_step2). Workgroup L takes tiles L, L + G, L + 2G, ...: the grid
+// works on G consecutive tiles at a time, so its loads stream through contiguous rows (and
+// consecutive L run on one XCD), as those of separate launches do. The tile function sees an
+// opaque thread index, so that its per-thread index arithmetic is not hoisted out of the loops
+// (held across them it would need more registers than the two-step tile leaves free).
 template <int TX, int TY, int GEO, int EOS>
 __global__ __launch_bounds__(step2_threads(TX, TY, GEO), step2_waves(TX, TY, GEO)) void
 k_batch_persistent(const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst,
@@ -94,16 +99,14 @@ k_batch_persistent(const InstDesc* __restrict__ inst, const int* __restrict__ ti
     __shared__ int verdict;
     const int G = gridDim.x;
     const int L = xcd_tile(blockIdx.x, G);
-    const int t_lo = (int)((long long)L * ntiles / G);
-    const int t_hi = (int)((long long)(L + 1) * ntiles / G);
     // each pass reads g[cur0] and writes g[cur0 ^ 1] (two steps), then the two swap roles
     for (int k = 0; k < npairs; ++k) {
-        for (int t = t_lo; t < t_hi; ++t) {
+        for (int t = L; t < ntiles; t += G) {
             const InstDesc* D = inst + tile_inst[t];
             int x0, y0;
             batch_tile_origin(D, t, TX, TY, x0, y0);
-            step2_tile_any<TX, TY, GEO, EOS>(D->P, D->g[cur0], D->g[cur0 ^ 1], D->gw, x0, y0,
-                                             lds);
+            step2_tile_any<TX, TY, GEO, EOS, false, true>(D->P, D->g[cur0], D->g[cur0 ^ 1],
+                                                          D->gw, x0, y0, lds);
             __syncthreads();  // the LDS tile is reused by the next tile
         }
         if (!grid_barrier(bar, (unsigned long long)(k + 1) * (unsigned long long)G, flag,

@@ -722,12 +722,17 @@ struct Step2Lds {
 // bounce-back of each population and the adhesion sums G_w over the solid neighbours.
 // MID: the state after the first of the two steps is also written, to gmid (the tile's nodes;
 // without the wet-node force, so not for that wall).
-template <int TX, int TY, int GEO, int EOS = EOS_ANY, bool IN = false, bool MID = false>
+template <int TX, int TY, int GEO, int EOS = EOS_ANY, bool IN = false, bool MID = false,
+          bool OPQ = false>
 __device__ __forceinline__ void step2_tile(const KParams& P, const double* __restrict__ gin,
                                            double* __restrict__ gout,
                                            const double* __restrict__ gw, int x0, int y0,
                                            Step2Lds<TX, TY, GEO>& L,
                                            double* __restrict__ gmid = nullptr) {
+    // OPQ: the thread index is opaque to the compiler, so nothing derived from it is hoisted
+    // out of a loop over tiles around this call (which would hold it in registers throughout)
+    int tid = threadIdx.x;
+    if constexpr (OPQ) asm volatile("" : "+v"(tid));
     static_assert(!MID || GEO != GEO_WET, "the intermediate state carries no wet-node force");
     constexpr bool MK = GEO == GEO_MASK;
     constexpr int NT = step2_threads(TX, TY, GEO);
@@ -746,7 +751,7 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
     bool ok[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        const int s = threadIdx.x + r * NT;
+        const int s = tid + r * NT;
         ok[r] = false;
         rk[r] = 1.0;
         if (s >= PL) continue;
@@ -793,7 +798,7 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
     constexpr int LAST = PL - (NR - 1) * NT;  // threads with a slot in the last pass
     constexpr int RB = (LAST + 63) / 64 * 64;
     constexpr int R0 = RB + NRING <= NT ? RB : 0;
-    for (int h = (int)threadIdx.x - R0; h < NRING; h += NT) {
+    for (int h = tid - R0; h < NRING; h += NT) {
         if (h < 0) continue;
         int lx, ly;  // R3-local coordinates
         if (h < W3) { lx = h; ly = 0; }
@@ -814,7 +819,7 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         if (!ok[r]) continue;
-        const int s = threadIdx.x + r * NT;
+        const int s = tid + r * NT;
         const int lx = s % W2, ly = s / W2;
         const double* c = ps1 + (ly + 1) * W3 + lx + 1;
         double sx, sy;
@@ -853,8 +858,8 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
     // are enough of them, otherwise to the first threads after their own node.
     constexpr int NTILE = TX * TY;
     constexpr int NRING1 = 2 * W1 + 2 * TY;  // R1 outside the tile
-    const bool own = NT == NTILE || (int)threadIdx.x < NTILE;
-    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const bool own = NT == NTILE || tid < NTILE;
+    const int tx = tid % TX, ty = tid / TX;
     const int x = x0 + tx, y = y0 + ty;
     const int l = (ty + 2) * W2 + tx + 2;
     unsigned lk = 0;  // links of the node (solid mask)
@@ -890,7 +895,7 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
         ps2[(ty + 1) * W1 + tx + 1] = slot_psi(tx + 1, ty + 1);  // outside the lattice, or solid
     }
     constexpr int RR0 = NT >= NTILE + NRING1 ? NTILE : 0;
-    for (int h = (int)threadIdx.x - RR0; h < NRING1; h += NT) {
+    for (int h = tid - RR0; h < NRING1; h += NT) {
         if (h < 0) continue;
         int lx, ly;  // R1-local coordinates
         if (h < W1) { lx = h; ly = 0; }
@@ -944,16 +949,16 @@ __device__ __forceinline__ bool step2_interior(const KParams& P, int x0, int y0)
 }
 
 // step2_tile with the interior variant where it applies (a uniform branch per workgroup).
-template <int TX, int TY, int GEO, int EOS, bool MID = false>
+template <int TX, int TY, int GEO, int EOS, bool MID = false, bool OPQ = false>
 __device__ __forceinline__ void step2_tile_any(const KParams& P, const double* __restrict__ gin,
                                                double* __restrict__ gout,
                                                const double* __restrict__ gw, int x0, int y0,
                                                Step2Lds<TX, TY, GEO>& L,
                                                double* __restrict__ gmid = nullptr) {
     if (step2_interior<TX, TY, GEO>(P, x0, y0))
-        step2_tile<TX, TY, GEO, EOS, true, MID>(P, gin, gout, gw, x0, y0, L, gmid);
+        step2_tile<TX, TY, GEO, EOS, true, MID, OPQ>(P, gin, gout, gw, x0, y0, L, gmid);
     else
-        step2_tile<TX, TY, GEO, EOS, false, MID>(P, gin, gout, gw, x0, y0, L, gmid);
+        step2_tile<TX, TY, GEO, EOS, false, MID, OPQ>(P, gin, gout, gw, x0, y0, L, gmid);
 }
 
 }  // namespace lbm
