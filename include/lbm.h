@@ -251,7 +251,8 @@ int lbm_set_gw(lbm_ctx *c, const double *gw_host);
  *          or 64x4 when 64x8 tiles would give fewer than 512 workgroups;
  *   16+t   fused with tile shape t (0..7: 64x4, 64x8, 64x16, 128x4, and the overlapped
  *          62-column tiles with 4, 6, 8, 14 rows);
- *   32+t   two steps per launch with output tile t (0..3: 64x8, 64x4, 128x4, 64x16).
+ *   32+t   two steps per launch with output tile t (0..5: 64x8, 64x4, 128x4, 64x16, 32x8,
+ *          32x4).
  * All schedules give bit-identical populations. A solid mask accepts every schedule but
  * 20..23 (LBM_E_INVAL). */
 int lbm_set_schedule(lbm_ctx *c, int32_t schedule);

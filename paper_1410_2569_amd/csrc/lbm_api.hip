@@ -645,7 +645,7 @@ int lbm_set_schedule(lbm_ctx* c, int32_t schedule) {
         c->tile = schedule - 16;
         return LBM_OK;
     }
-    if (schedule >= 32 && schedule < 36) {
+    if (schedule >= 32 && schedule < 38) {
         c->schedule = 2;
         c->tile2 = schedule - 32;
         return LBM_OK;

@@ -1285,15 +1285,21 @@ __device__ __forceinline__ void adj_gw_node(const KParams& P, const double* __re
 // then the forward node is recomputed from g^{n-1} and reverse mode runs through the MRT
 // collision, forcing and adhesion (collide_adj). The later step's wall vectors are added to the
 // G_w gradient (the last reverse step's by adj_gw_node afterwards).
-template <int TX, int TY>
+// NTH threads: one per tile node, or twice as many, the others taking ring work only (more
+// waves per compute unit on small lattices).
+template <int TX, int TY, int NTH = TX * TY>
 __device__ __forceinline__ void adj_tile(const KParams& P, const AdjPtrs& A, int x0, int y0,
                                          AdjLds<TX, TY>& L) {
-    constexpr int NT = TX * TY;
+    constexpr int NT = NTH, NTILE = TX * TY;
+    static_assert(NTH == NTILE || NTH == 2 * NTILE, "one or two threads per tile node");
     constexpr int LW = TX + 2, QW = TX + 4;
     constexpr int NH = 2 * LW + 2 * TY;
-    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const bool owner = NTH == NTILE || (int)threadIdx.x < NTILE;
+    const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY;
     const int x = x0 + tx, y = y0 + ty;
-    const bool active = x < P.nx && y <= P.y_hi;
+    const bool active = owner && x < P.nx && y <= P.y_hi;
+    // ring work starts at the threads that own no node
+    const int rt = NTH == NTILE ? (int)threadIdx.x : ((int)threadIdx.x + NTH - NTILE) % NTH;
 
     // Every global load is issued before the first barrier: the forward node, psi of the ring,
     // q of two rings, the a part of the transposed streaming, p0 and psi' of the c ring and G_w.
@@ -1316,7 +1322,7 @@ __device__ __forceinline__ void adj_tile(const KParams& P, const AdjPtrs& A, int
     bool flv[NCR];
 #pragma unroll
     for (int r = 0; r < NCR; ++r) {
-        const int s = threadIdx.x + r * NT;
+        const int s = rt + r * NT;
         p0v[r] = 0.0;
         dpv[r] = 0.0;
         flv[r] = false;
@@ -1333,8 +1339,8 @@ __device__ __forceinline__ void adj_tile(const KParams& P, const AdjPtrs& A, int
         dpv[r] = A.dpsi_in[i];
         flv[r] = true;
     }
-    L.sp[(ty + 1) * LW + tx + 1] = active ? psi_c : psi_at<GEO_ROWS>(P, A.gprev, x, y);
-    for (int h = threadIdx.x; h < NH; h += NT) {
+    if (owner) L.sp[(ty + 1) * LW + tx + 1] = active ? psi_c : psi_at<GEO_ROWS>(P, A.gprev, x, y);
+    for (int h = rt; h < NH; h += NT) {
         int hx, hy;
         if (h < LW) { hx = h - 1; hy = -1; }
         else if (h < 2 * LW) { hx = h - LW - 1; hy = TY; }
@@ -1343,7 +1349,7 @@ __device__ __forceinline__ void adj_tile(const KParams& P, const AdjPtrs& A, int
         L.sp[(hy + 1) * LW + hx + 1] = psi_at<GEO_ROWS>(P, A.gprev, x0 + hx, y0 + hy);
     }
     // q of the later step on the tile and two rings (0 outside the fluid rows)
-    for (int s = threadIdx.x; s < (TY + 4) * QW; s += NT) {
+    for (int s = rt; s < (TY + 4) * QW; s += NT) {
         const int gx = wrapx(x0 - 2 + s % QW, P.nx);
         int gy = y0 - 2 + s / QW;
         bool fluid = true;
@@ -1362,7 +1368,7 @@ __device__ __forceinline__ void adj_tile(const KParams& P, const AdjPtrs& A, int
     // c of the later step on the tile and one ring (0 on the solid rows)
 #pragma unroll
     for (int r = 0; r < NCR; ++r) {
-        const int s = threadIdx.x + r * NT;
+        const int s = rt + r * NT;
         if (s >= NC) continue;
         const int hx = s % LW, hy = s / LW;
         int gy = y0 - 1 + hy;

@@ -320,7 +320,8 @@ static hipError_t launch_step2_t(const KParams& P, const double* gin, double* go
     });
 }
 
-// Two steps in one launch; tile2 selects the output tile: 0 64x8, 1 64x4, 2 128x4, 3 64x16.
+// Two steps in one launch; tile2 selects the output tile: 0 64x8, 1 64x4, 2 128x4, 3 64x16,
+// 4 32x8, 5 32x4 (the narrow tiles for lattices too small to fill the chip with the others).
 // gmid (optional): receives the state after the first step.
 hipError_t launch_step2(const KParams& P, int tile2, const double* gin, double* gout,
                         const double* gw, hipStream_t s, double* gmid) {
@@ -328,6 +329,8 @@ hipError_t launch_step2(const KParams& P, int tile2, const double* gin, double* 
         case 1: return launch_step2_t<64, 4>(P, gin, gout, gw, gmid, s);
         case 2: return launch_step2_t<128, 4>(P, gin, gout, gw, gmid, s);
         case 3: return launch_step2_t<64, 16>(P, gin, gout, gw, gmid, s);
+        case 4: return launch_step2_t<32, 8>(P, gin, gout, gw, gmid, s);
+        case 5: return launch_step2_t<32, 4>(P, gin, gout, gw, gmid, s);
         default: return launch_step2_t<64, 8>(P, gin, gout, gw, gmid, s);
     }
 }

@@ -513,6 +513,8 @@ void run_case(const Lattice& L) {
     two(step_two<64, 4, GEO, EOS>, "two-step 64x4");
     two(step_two<128, 4, GEO, EOS>, "two-step 128x4");
     two(step_two<64, 16, GEO, EOS>, "two-step 64x16");
+    two(step_two<32, 8, GEO, EOS>, "two-step 32x8");
+    two(step_two<32, 4, GEO, EOS>, "two-step 32x4");
     observables<GEO, EOS>(L, ref);
     if constexpr (GEO == lbm::GEO_ROWS) run_adjoint<EOS>(L, g0, g1, ref);
 }
