@@ -1588,14 +1588,15 @@ int lbm_batch_get_tune(const lbm_batch* b, lbm_tune* t, int32_t* grid) {
 
 namespace {
 
-// Adjoint workspace of an ensemble: the instance table and the work-list of 64 x 4 tiles, then per
+// Adjoint workspace of an ensemble: the instance table and the work-lists of 64 x 4 tiles (reverse
+// steps) and 64 x 8 tiles (two-step recomputation), then per
 // instance the single-lattice adjoint layout (checkpoints, segment, adjoint buffers, gradient).
 struct BatchAdjLayout {
-    size_t off_inst, off_tiles, total;
+    size_t off_inst, off_tiles, off_tiles8, total;
     std::vector<size_t> off;
     std::vector<AdjLayout> A;
-    std::vector<int> tile0, ntx, nty;
-    int ntiles;
+    std::vector<int> tile0, ntx, nty, tile0_8, nty8;
+    int ntiles, ntiles8;  // 64 x 4 (reverse steps) and 64 x 8 (two-step recomputation) tiles
 };
 
 int batch_adj_layout(const lbm_batch* b, int64_t nsteps, int32_t K, BatchAdjLayout* L) {
@@ -1605,20 +1606,27 @@ int batch_adj_layout(const lbm_batch* b, int64_t nsteps, int32_t K, BatchAdjLayo
     size_t o = 0;
     L->off_inst = o;
     o += align_up((size_t)b->count * sizeof(lbm::AdjInst), kAlign);
-    long long nt = 0;
+    long long nt = 0, nt8 = 0;
     L->tile0.resize(b->count); L->ntx.resize(b->count); L->nty.resize(b->count);
+    L->tile0_8.resize(b->count); L->nty8.resize(b->count);
     L->A.resize(b->count); L->off.resize(b->count);
     for (int i = 0; i < b->count; ++i) {
         const KParams& P = b->kp[i];
         L->ntx[i] = (P.nx + 63) / 64;
         L->nty[i] = (P.y_hi - P.y_lo + 4) / 4;
+        L->nty8[i] = (P.y_hi - P.y_lo + 8) / 8;
         L->tile0[i] = (int)nt;
+        L->tile0_8[i] = (int)nt8;
         nt += (long long)L->ntx[i] * L->nty[i];
+        nt8 += (long long)L->ntx[i] * L->nty8[i];
     }
     if (nt > (1LL << 30)) return LBM_E_INVAL;
     L->ntiles = (int)nt;
+    L->ntiles8 = (int)nt8;
     L->off_tiles = o;
     o += align_up((size_t)nt * sizeof(int), kAlign);
+    L->off_tiles8 = o;
+    o += align_up((size_t)nt8 * sizeof(int), kAlign);
     for (int i = 0; i < b->count; ++i) {
         L->A[i] = adj_layout_of(&b->p[i], nsteps, K, 1);
         L->off[i] = o;
@@ -1708,7 +1716,7 @@ int lbm_batch_backward(lbm_batch* b, int64_t nsteps, int32_t K, void* d_adj, siz
     char* w = (char*)d_adj;
     // instance table and work-list
     std::vector<lbm::AdjInst> inst(b->count);
-    std::vector<int> tile_inst(L.ntiles);
+    std::vector<int> tile_inst(L.ntiles), tile_inst8(L.ntiles8);
     int max_nx = 0;
     for (int i = 0; i < b->count; ++i) {
         const AdjLayout& A = L.A[i];
@@ -1730,17 +1738,24 @@ int lbm_batch_backward(lbm_batch* b, int64_t nsteps, int32_t K, void* d_adj, siz
         d.tile0 = L.tile0[i];
         d.ntx = L.ntx[i];
         d.nty = L.nty[i];
+        d.tile0_8 = L.tile0_8[i];
+        d.nty8 = L.nty8[i];
         for (int t = 0; t < L.ntx[i] * L.nty[i]; ++t) tile_inst[L.tile0[i] + t] = i;
+        for (int t = 0; t < L.ntx[i] * L.nty8[i]; ++t) tile_inst8[L.tile0_8[i] + t] = i;
         max_nx = std::max(max_nx, d.P.nx);
         hipError_t e = lbm::launch_zero(base + A.off_a, A.total - A.off_a, s);
         if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "adjoint clear");
     }
     lbm::AdjInst* d_inst = (lbm::AdjInst*)(w + L.off_inst);
     int* d_tiles = (int*)(w + L.off_tiles);
+    int* d_tiles8 = (int*)(w + L.off_tiles8);
     hipError_t e = host_copy(s, d_inst, inst.data(), inst.size() * sizeof(lbm::AdjInst),
                              hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = host_copy(s, d_tiles, tile_inst.data(), tile_inst.size() * sizeof(int),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = host_copy(s, d_tiles8, tile_inst8.data(), tile_inst8.size() * sizeof(int),
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "adjoint tables");
     // the objective of every instance seeds its adjoint
@@ -1762,7 +1777,7 @@ int lbm_batch_backward(lbm_batch* b, int64_t nsteps, int32_t K, void* d_adj, siz
                                (size_t)9 * b->kp[i].plane * sizeof(double), hipMemcpyDeviceToDevice, s);
         int64_t i = 0;
         for (; i + 2 <= len - 1 && e == hipSuccess; i += 2)
-            e = lbm::launch_batch_seg_step2(b->eos, d_inst, d_tiles, L.ntiles, (int)i, s);
+            e = lbm::launch_batch_seg_step2(b->eos, d_inst, d_tiles8, L.ntiles8, (int)i, s);
         if (i + 1 <= len - 1 && e == hipSuccess)
             e = lbm::launch_batch_seg_step(b->eos, d_inst, d_tiles, L.ntiles, (int)i, s);
         for (i = len - 1; i >= 0 && e == hipSuccess; --i) {

@@ -132,18 +132,20 @@ __device__ __forceinline__ void adj_tile_origin(const AdjInst* D, int t, int& x0
     y0 = D->P.y_lo + (lt / D->ntx) * 4;
 }
 
-// Segment states i -> i+1, i+2 of every instance (two steps per launch, the first written too).
+// Segment states i -> i+1, i+2 of every instance (two steps per launch, the first written too),
+// over a work-list of 64 x 8 output tiles (the recomputation work-list).
 template <int EOS>
-__global__ __launch_bounds__(step2_threads(64, 4, GEO_ROWS), step2_waves(64, 4, GEO_ROWS)) void
+__global__ __launch_bounds__(step2_threads(64, 8, GEO_ROWS), step2_waves(64, 8, GEO_ROWS)) void
 k_batch_seg_step2(const AdjInst* __restrict__ inst, const int* __restrict__ tile_inst, int ntiles,
                   int i) {
-    __shared__ Step2Lds<64, 4, GEO_ROWS> lds;
+    __shared__ Step2Lds<64, 8, GEO_ROWS> lds;
     const int t = xcd_tile(blockIdx.x, ntiles);
     const AdjInst* D = inst + tile_inst[t];
-    int x0, y0;
-    adj_tile_origin(D, t, x0, y0);
+    const int lt = t - D->tile0_8;
+    const int x0 = (lt % D->ntx) * 64;
+    const int y0 = D->P.y_lo + (lt / D->ntx) * 8;
     double* s0 = D->seg + (long long)i * D->fstride;
-    step2_tile_any<64, 4, GEO_ROWS, EOS, true>(D->P, s0, s0 + 2 * D->fstride, D->gw, x0, y0, lds,
+    step2_tile_any<64, 8, GEO_ROWS, EOS, true>(D->P, s0, s0 + 2 * D->fstride, D->gw, x0, y0, lds,
                                                s0 + D->fstride);
 }
 
@@ -327,7 +329,7 @@ hipError_t launch_batch_seg_step2(int eos, const AdjInst* inst, const int* tile_
                                   int i, hipStream_t s) {
     return with_eos(eos, [&](auto e) {
         hipLaunchKernelGGL((k_batch_seg_step2<decltype(e)::value>), dim3(ntiles),
-                           dim3(step2_threads(64, 4, GEO_ROWS)), 0, s, inst, tile_inst, ntiles, i);
+                           dim3(step2_threads(64, 8, GEO_ROWS)), 0, s, inst, tile_inst, ntiles, i);
         return hipGetLastError();
     });
 }

@@ -33,6 +33,8 @@ struct AdjInst {
     double* gg;  // [2][pitch] dL/dG_w
     int tile0;   // first 64 x 4 tile of this instance in the adjoint work-list
     int ntx, nty;
+    int tile0_8;  // first 64 x 8 tile in the recomputation work-list (ntx columns as above)
+    int nty8;
     int pad;
 };
 
@@ -98,9 +100,10 @@ hipError_t launch_batch_persistent(int tile, int geo, int eos, int grid, const I
 hipError_t launch_batch_contact_line(const InstDesc* inst, const int* rows, int count, int cur,
                                      double* out, hipStream_t s);
 int batch_persistent_occupancy(int tile);
-// ensemble adjoint, over a work-list of 64 x 4 tiles of every instance (bounce-back walls):
-// recomputation of segment states i -> i+1 (two steps: -> i+1, i+2), one reverse step of segment
-// state i (k: parity of the later step's buffers), and the last step's G_w gradient
+// ensemble adjoint, over work-lists of the tiles of every instance (bounce-back walls):
+// recomputation of segment states i -> i+1, i+2 (two steps, 64 x 8 output tiles) or i -> i+1 (one
+// step, 64 x 4), one reverse step of segment state i (64 x 4; k: parity of the later step's
+// buffers), and the last step's G_w gradient
 hipError_t launch_batch_seg_step2(int eos, const AdjInst* inst, const int* tile_inst, int ntiles,
                                   int i, hipStream_t s);
 hipError_t launch_batch_seg_step(int eos, const AdjInst* inst, const int* tile_inst, int ntiles,
