@@ -381,6 +381,15 @@ int lbm_autotune(const lbm_params *p, int32_t count, const double *const *gw_hos
                  int32_t steps, lbm_tune *best, double *best_ms);
 
 int64_t lbm_current_step(const lbm_ctx *c);
+
+/* The device's FP64 square root and division as the step kernels compile them (the pseudo-
+ * potential's square root and the velocity's division of Eq. 6 rely on them): for i < n,
+ * d_sqrt[i] = sqrt(d_a[i]) and d_quot[i] = d_a[i] / d_b[i]. All four are device arrays of n
+ * doubles, caller-owned; asynchronous on `stream`. For checking their rounding against the host's
+ * correctly rounded operations. LBM_E_INVAL for null arrays (n > 0). */
+int lbm_fp64_probe(const double *d_a, const double *d_b, double *d_sqrt, double *d_quot, size_t n,
+                   void *stream);
+
 /* Release a context (host memory only). Waits for the work queued on its stream first, so the
  * caller may free the workspace as soon as it returns; LBM_E_HIP if that wait failed (the
  * context is released all the same). */

@@ -97,7 +97,12 @@ def step(F, gw, q):
                      Fx, -Fx, Fy, -Fy, 2 * (vx * Fx - vy * Fy), vx * Fy + vy * Fx])
     ms = m - s * (m - meq) + (1 - s / 2) * S
     fs = torch.einsum("ak,kyx->ayx", MINV, ms)
+    return stream(fs)
 
+
+def stream(fs):
+    """Eq. (5) with halfway bounce-back on the fluid rows: f_a(x) = f*_a(x - e_a), or f*_opp(a)(x)
+    when x - e_a lies in a solid row; x periodic."""
     out = []
     for a in range(9):
         src = torch.roll(fs[a], shifts=EX[a], dims=1)

@@ -1870,6 +1870,16 @@ int lbm_autotune(const lbm_params* p, int32_t count, const double* const* gw_hos
     return rc_all;
 }
 
+int lbm_fp64_probe(const double* d_a, const double* d_b, double* d_sqrt, double* d_quot,
+                   size_t n, void* stream) {
+    if (n == 0) return LBM_OK;
+    if (!d_a || !d_b || !d_sqrt || !d_quot || n > ((size_t)1 << 40)) return LBM_E_INVAL;
+    (void)hipGetLastError();
+    const hipError_t e = lbm::launch_fp64_probe(d_a, d_b, d_sqrt, d_quot, (long long)n,
+                                                (hipStream_t)stream);
+    return e == hipSuccess ? LBM_OK : create_fail(LBM_E_HIP, "fp64 probe", e);
+}
+
 int lbm_destroy(lbm_ctx* c) {
     if (!c) return LBM_E_INVAL;
     // queued launches still use the workspace: the caller may release it once this returns

@@ -57,6 +57,8 @@ struct DropletArgs {
     unsigned long long base;     // splitmix64(seed)
 };
 hipError_t launch_droplets(const KParams& P, const DropletArgs& D, double* rho, hipStream_t s);
+hipError_t launch_fp64_probe(const double* a, const double* b, double* sq, double* quot,
+                             long long n, hipStream_t s);
 // dense: fout is [9][ny][nx] (otherwise [9][ny][pitch])
 hipError_t launch_pull(const KParams& P, const double* gin, double* fout, hipStream_t s,
                        bool dense = false);

@@ -419,6 +419,26 @@ hipError_t launch_droplets(const KParams& P, const DropletArgs& D, double* rho, 
     return hipGetLastError();
 }
 
+// The device's FP64 square root and division as the step kernels compile them: sq = sqrt(a),
+// quot = a / b, element-wise.
+__global__ __launch_bounds__(256) void k_fp64_probe(const double* __restrict__ a,
+                                                    const double* __restrict__ b,
+                                                    double* __restrict__ sq,
+                                                    double* __restrict__ quot, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    sq[i] = sqrt(a[i]);
+    quot[i] = a[i] / b[i];
+}
+
+hipError_t launch_fp64_probe(const double* a, const double* b, double* sq, double* quot,
+                             long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fp64_probe, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b,
+                       sq, quot, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_init(const KParams& P, const double* rho0, double* g, hipStream_t s) {
     hipLaunchKernelGGL(k_init, node_grid(P), dim3(256), 0, s, P, rho0, g);
     return hipGetLastError();

@@ -142,6 +142,8 @@ SIGNATURES = {
     "lbm_autotune": (C.c_int, [_P, C.c_int32, C.POINTER(_dp), C.POINTER(_dp), C.c_void_p,
                                C.c_size_t, C.c_void_p, C.c_int32, C.c_void_p,
                                C.POINTER(C.c_double)]),
+    "lbm_fp64_probe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                 C.c_void_p]),
     "lbm_destroy": (C.c_int, [C.c_void_p]),
     "lbm_strerror": (C.c_char_p, [C.c_int]),
     "lbm_last_error": (C.c_char_p, [C.c_void_p]),
@@ -269,6 +271,21 @@ def _done_on(t, stream):
     if stream.cuda_stream != cur.cuda_stream:
         cur.wait_stream(stream)
     return t
+
+
+def fp64_probe(a, b, stream=None):
+    """sqrt(a) and a / b computed by the library's device code (contiguous float64 device
+    tensors of one shape); returns the two result tensors."""
+    import torch
+
+    assert a.is_cuda and a.dtype == torch.float64 and a.is_contiguous() and a.shape == b.shape
+    assert b.is_cuda and b.dtype == torch.float64 and b.is_contiguous()
+    st = stream if stream is not None else torch.cuda.current_stream(a.device)
+    sq, qt = torch.empty_like(a), torch.empty_like(a)
+    check(lib().lbm_fp64_probe(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()),
+                               C.c_void_p(sq.data_ptr()), C.c_void_p(qt.data_ptr()), a.numel(),
+                               C.c_void_p(st.cuda_stream)))
+    return sq, qt
 
 
 def workspace_size(q: Params) -> int:

@@ -52,6 +52,28 @@ def test_adjoint_matches_autograd(orc, gpu, form, ghost, tau_v, nsteps, K):
     assert err <= 1e-9
 
 
+@pytest.mark.parametrize("form,gw_mean", [("modpsi", 0.3), ("rho", 0.15), ("psi", -1.0)])
+def test_adjoint_matches_autograd_piecewise_eos(orc, gpu, form, gw_mean):
+    """The paper's Eq. (15) EOS at 500/1 (sigma = 0.084, viscosity ratio 5): every form, 90
+    steps, checkpoint every 17 (a ragged last segment)."""
+    from oracle import grad_oracle as G
+    nx, ny, n, K = 70, 26, 90, 17
+    p = dict(nx=nx, ny=ny, walls=1, ghost=1, eos="piecewise", th_v=0.64 / 3, th_m=-0.04 / 3,
+             th_l=1 / 3, rho_v=1.0, rho_l=500.0, G=-1.0, sigma=0.084, tau_l=1.1, tau_v=2.0,
+             wall_force=form, **synth.RATES)
+    q = orc.make_params(p)
+    rho0 = synth.droplet_rho(nx, ny, q.rho_l, q.rho_v, [(35.0, 0.5)], [10.0], width=4.0, seed=8)
+    gw = synth.gw_smooth(nx, gw_mean, abs(gw_mean) * 0.3, seed=4)
+    gw[1] = np.linspace(-0.03, 0.02, nx)
+    sim = gpu.Sim(dict(p, rho_l=q.rho_l, rho_v=q.rho_v), gw, rho0)
+    L_ref, g_ref = G.loss_and_grad(orc.init_rest(q, rho0), gw, q, n, 0.7, 1.3)
+    L, g = gpu_grad(sim, n, K, 0.7, 1.3)
+    err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    print(f"Eq. 15 {form}: L {L} vs {L_ref}, max |dg|/max|g| = {err:.3e}")
+    assert abs(L - L_ref) <= 1e-9 * abs(L_ref)
+    assert err <= 1e-9
+
+
 def test_adjoint_c4_vs_finite_differences(orc, gpu):
     """256x128, droplet R = 40, modified form, smooth bottom G_w pattern (mean -0.1, amplitude
     0.05), 4,000 steps, checkpoint every 200: adjoint vs central differences (h = 1e-5, checked
