@@ -127,6 +127,22 @@ def cpu_baseline(budget_s: float = 12.0) -> dict:
                       f"{dt:.1f} s"}
 
 
+def host_info() -> dict:
+    """The host the CPU baseline ran on: CPU model (from /proc/cpuinfo), logical CPUs, and the
+    CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline_single_core(budget_s: float = 10.0) -> dict:
     """cpu_baseline on one core: the same oracle sample in a child process started with
     OMP_NUM_THREADS=1 (the thread count of the oracle's OpenMP loops is fixed at process start)."""
@@ -933,6 +949,7 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
         out["cpu_baseline"]["single_core"] = cpu_baseline_single_core()
+        out["cpu_baseline"]["host"] = host_info()
     print(json.dumps(out), flush=True)
 
 

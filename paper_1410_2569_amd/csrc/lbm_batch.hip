@@ -90,8 +90,18 @@ __device__ __forceinline__ bool grid_barrier(unsigned long long* bar, unsigned l
 // consecutive L run on one XCD), as those of separate launches do. The tile function sees an
 // opaque thread index, so that its per-thread index arithmetic is not hoisted out of the loops
 // (held across them it would need more registers than the two-step tile leaves free).
+// Threads of a persistent workgroup: those of the two-step launches, except 512 for 64 x 8 tiles:
+// two workgroups per CU then leave 128 VGPRs per thread (4 waves per SIMD) where 768 threads leave
+// 80, which the loop state around the tile function overflows.
+__host__ __device__ constexpr int persist_threads(int TX, int TY, int GEO) {
+    return TX == 64 && TY == 8 ? 512 : step2_threads(TX, TY, GEO);
+}
+__host__ __device__ constexpr int persist_waves(int TX, int TY, int GEO) {
+    return TX == 64 && TY == 8 ? 4 : step2_waves(TX, TY, GEO);
+}
+
 template <int TX, int TY, int GEO, int EOS>
-__global__ __launch_bounds__(step2_threads(TX, TY, GEO), step2_waves(TX, TY, GEO)) void
+__global__ __launch_bounds__(persist_threads(TX, TY, GEO), persist_waves(TX, TY, GEO)) void
 k_batch_persistent(const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst,
                    int ntiles, int npairs, int cur0, unsigned long long* bar, int* flag,
                    int spin_limit) {
@@ -105,8 +115,8 @@ k_batch_persistent(const InstDesc* __restrict__ inst, const int* __restrict__ ti
             const InstDesc* D = inst + tile_inst[t];
             int x0, y0;
             batch_tile_origin(D, t, TX, TY, x0, y0);
-            step2_tile_any<TX, TY, GEO, EOS, false, true>(D->P, D->g[cur0], D->g[cur0 ^ 1],
-                                                          D->gw, x0, y0, lds);
+            step2_tile_any<TX, TY, GEO, EOS, false, true, persist_threads(TX, TY, GEO)>(
+                D->P, D->g[cur0], D->g[cur0 ^ 1], D->gw, x0, y0, lds);
             __syncthreads();  // the LDS tile is reused by the next tile
         }
         if (!grid_barrier(bar, (unsigned long long)(k + 1) * (unsigned long long)G, flag,
@@ -232,7 +242,7 @@ static hipError_t launch_persist_t(int geo, int eos, int grid, const InstDesc* i
     return dispatch(geo, eos, [&](auto g, auto e) {
         constexpr int G = decltype(g)::value;
         hipLaunchKernelGGL((k_batch_persistent<TX, TY, G, decltype(e)::value>), dim3(grid),
-                           dim3(step2_threads(TX, TY, G)), 0, s, inst, tile_inst, ntiles, npairs,
+                           dim3(persist_threads(TX, TY, G)), 0, s, inst, tile_inst, ntiles, npairs,
                            cur, bar, flag, spin_limit);
         return hipGetLastError();
     });
@@ -250,7 +260,7 @@ static int occupancy_t() {
                 constexpr int G = decltype(g)::value;
                 return hipOccupancyMaxActiveBlocksPerMultiprocessor(
                     &n, k_batch_persistent<TX, TY, G, decltype(e)::value>,
-                    step2_threads(TX, TY, G), 0);
+                    persist_threads(TX, TY, G), 0);
             });
             if (r != hipSuccess) return 0;
             lo = std::min(lo, n);

@@ -723,7 +723,7 @@ struct Step2Lds {
 // MID: the state after the first of the two steps is also written, to gmid (the tile's nodes;
 // without the wet-node force, so not for that wall).
 template <int TX, int TY, int GEO, int EOS = EOS_ANY, bool IN = false, bool MID = false,
-          bool OPQ = false>
+          bool OPQ = false, int NTH = step2_threads(TX, TY, GEO)>
 __device__ __forceinline__ void step2_tile(const KParams& P, const double* __restrict__ gin,
                                            double* __restrict__ gout,
                                            const double* __restrict__ gw, int x0, int y0,
@@ -735,7 +735,9 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
     if constexpr (OPQ) asm volatile("" : "+v"(tid));
     static_assert(!MID || GEO != GEO_WET, "the intermediate state carries no wet-node force");
     constexpr bool MK = GEO == GEO_MASK;
-    constexpr int NT = step2_threads(TX, TY, GEO);
+    // NTH threads in the workgroup (the default of the tile shape, or fewer for a caller that
+    // needs registers for more waves)
+    constexpr int NT = NTH;
     static_assert(NT >= TX * TY, "one thread per output node at least");
     constexpr int W3 = TX + 6, H3 = TY + 6, W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
     constexpr int PL = W2 * H2;
@@ -933,7 +935,7 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
 // [0, nx) and, with walls, in rows [1, ny-2] (only nodes of rows 1 and ny-2 have solid
 // neighbours), otherwise in rows [0, ny). A solid mask also needs no solid node among them: the
 // whole workgroup checks the link words of the tile grown by 4 rings (a barrier).
-template <int TX, int TY, int GEO>
+template <int TX, int TY, int GEO, int NTH = step2_threads(TX, TY, GEO)>
 __device__ __forceinline__ bool step2_interior(const KParams& P, int x0, int y0) {
     if (x0 - 4 < 0 || x0 + TX + 3 > P.nx - 1) return false;
     if (GEO != GEO_MASK && P.walls) return y0 - 3 >= 2 && y0 + TY + 2 <= P.ny - 3;
@@ -941,7 +943,7 @@ __device__ __forceinline__ bool step2_interior(const KParams& P, int x0, int y0)
     if constexpr (GEO == GEO_MASK) {
         constexpr int W4 = TX + 8, N4 = (TX + 8) * (TY + 8);
         int solid = 0;
-        for (int s = threadIdx.x; s < N4; s += step2_threads(TX, TY, GEO))
+        for (int s = threadIdx.x; s < N4; s += NTH)
             solid |= P.links[(unsigned)(y0 - 4 + s / W4) * P.pitch + (x0 - 4 + s % W4)] & 1;
         return !__syncthreads_or(solid);
     }
@@ -949,16 +951,17 @@ __device__ __forceinline__ bool step2_interior(const KParams& P, int x0, int y0)
 }
 
 // step2_tile with the interior variant where it applies (a uniform branch per workgroup).
-template <int TX, int TY, int GEO, int EOS, bool MID = false, bool OPQ = false>
+template <int TX, int TY, int GEO, int EOS, bool MID = false, bool OPQ = false,
+          int NTH = step2_threads(TX, TY, GEO)>
 __device__ __forceinline__ void step2_tile_any(const KParams& P, const double* __restrict__ gin,
                                                double* __restrict__ gout,
                                                const double* __restrict__ gw, int x0, int y0,
                                                Step2Lds<TX, TY, GEO>& L,
                                                double* __restrict__ gmid = nullptr) {
-    if (step2_interior<TX, TY, GEO>(P, x0, y0))
-        step2_tile<TX, TY, GEO, EOS, true, MID, OPQ>(P, gin, gout, gw, x0, y0, L, gmid);
+    if (step2_interior<TX, TY, GEO, NTH>(P, x0, y0))
+        step2_tile<TX, TY, GEO, EOS, true, MID, OPQ, NTH>(P, gin, gout, gw, x0, y0, L, gmid);
     else
-        step2_tile<TX, TY, GEO, EOS, false, MID, OPQ>(P, gin, gout, gw, x0, y0, L, gmid);
+        step2_tile<TX, TY, GEO, EOS, false, MID, OPQ, NTH>(P, gin, gout, gw, x0, y0, L, gmid);
 }
 
 }  // namespace lbm

@@ -310,16 +310,16 @@ void step_fused(const Lattice& L, const double* gin, double* gout) {
         [&] { std::fill(sp.begin(), sp.end(), kNaN); });
 }
 
-template <int TX, int TY, int GEO, int EOS>
+template <int TX, int TY, int GEO, int EOS, int NTH = lbm::step2_threads(TX, TY, GEO)>
 void step_two(const Lattice& L, const double* gin, double* gout) {
     const KParams& P = L.P;
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.y_hi - P.y_lo + TY) / TY;
     auto* lds = new lbm::Step2Lds<TX, TY, GEO>;
     run_workgroups(
-        lbm::step2_threads(TX, TY, GEO), ntx * nty,
+        NTH, ntx * nty,
         [&](int t) {
-            lbm::step2_tile_any<TX, TY, GEO, EOS>(P, gin, gout, L.gw.data(), (t % ntx) * TX,
-                                                  P.y_lo + (t / ntx) * TY, *lds);
+            lbm::step2_tile_any<TX, TY, GEO, EOS, false, false, NTH>(
+                P, gin, gout, L.gw.data(), (t % ntx) * TX, P.y_lo + (t / ntx) * TY, *lds);
         },
         [&] { std::memset((void*)lds, 0xFF, sizeof *lds); });
     delete lds;
@@ -510,6 +510,7 @@ void run_case(const Lattice& L) {
         check_equal(L, out, ref, name);
     };
     two(step_two<64, 8, GEO, EOS>, "two-step 64x8");
+    two(step_two<64, 8, GEO, EOS, 512>, "two-step 64x8, 512 threads");
     two(step_two<64, 4, GEO, EOS>, "two-step 64x4");
     two(step_two<128, 4, GEO, EOS>, "two-step 128x4");
     two(step_two<64, 16, GEO, EOS>, "two-step 64x16");
