@@ -136,8 +136,10 @@ int lbm_workspace_size(const lbm_params *p, size_t *bytes);
 
 /* Create a context in the caller's workspace d_ws (device pointer, >= lbm_workspace_size()).
  * gw_host: [2][nx] host array of G_w per solid node (may be NULL with walls = 0; copied).
- * rho0_host: [ny][nx] host array of the initial density (solid rows ignored; copied). The
- * initial populations are the rest equilibrium f_a = t_a rho0 with t = 4/9, 1/9, 1/36.
+ * rho0_host: [ny][nx] host array of the initial density (solid rows ignored; copied); every
+ * fluid value positive and inside the pseudopotential's domain (2 (p_EOS - rho/3) / G >= 0),
+ * else LBM_E_INVAL. The initial populations are the rest equilibrium f_a = t_a rho0 with
+ * t = 4/9, 1/9, 1/36.
  * stream: hipStream_t (NULL = default). On success *out owns host memory only.
  * walls = LBM_WALLS_MASK is rejected here (LBM_E_INVAL): use lbm_create_masked. */
 int lbm_create(const lbm_params *p, const double *gw_host, const double *rho0_host, void *d_ws,
@@ -162,7 +164,8 @@ typedef struct {
 } lbm_droplets;
 
 /* lbm_create with the initial density of `drops` (copied) computed on the device instead of a
- * host array; walls 0, 1 or 2 (LBM_E_INVAL for a solid mask or an invalid description). */
+ * host array; walls 0, 1 or 2 (LBM_E_INVAL for a solid mask, an invalid description, or a jitter
+ * that would take a density out of the pseudopotential's domain). */
 int lbm_create_droplets(const lbm_params *p, const double *gw_host, const lbm_droplets *drops,
                         void *d_ws, size_t ws_bytes, void *stream, lbm_ctx **out);
 
@@ -386,7 +389,7 @@ int64_t lbm_current_step(const lbm_ctx *c);
  * potential's square root and the velocity's division of Eq. 6 rely on them): for i < n,
  * d_sqrt[i] = sqrt(d_a[i]) and d_quot[i] = d_a[i] / d_b[i]. All four are device arrays of n
  * doubles, caller-owned; asynchronous on `stream`. For checking their rounding against the host's
- * correctly rounded operations. LBM_E_INVAL for null arrays (n > 0). */
+ * correctly rounded operations. LBM_E_INVAL for null arrays (n > 0) or n > 2^36. */
 int lbm_fp64_probe(const double *d_a, const double *d_b, double *d_sqrt, double *d_quot, size_t n,
                    void *stream);
 

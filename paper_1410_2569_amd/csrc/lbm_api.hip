@@ -441,18 +441,32 @@ int lbm_piecewise_spinodals(double rho_v, double rho_l, double th_v, double th_m
 
 // p_EOS(rho) on the host: Carnahan-Starling or Eq. (15). With psi = sqrt(2 (p - rho/3)/G) the
 // bulk pressure of Eq. (8), rho c_s^2 + G c^2 psi^2 / 2, equals it.
-int lbm_pressure(const lbm_params* p, double rho, double* out) {
-    if (!out || validate(p, nullptr) != LBM_OK || !std::isfinite(rho) || rho < 0.0) return LBM_E_INVAL;
+// p_EOS(rho) on the host (Carnahan-Starling or Eq. 15); false outside the EOS domain.
+static bool host_pressure(const lbm_params* p, double rho, double* out) {
+    if (!std::isfinite(rho) || rho < 0.0) return false;
     if (p->eos == LBM_EOS_CS) {
         const double e = p->b * rho / 4.0, om = 1.0 - e;
-        if (!(om > 0.0)) return LBM_E_INVAL;
+        if (!(om > 0.0)) return false;
         *out = rho * p->R * p->T * (1.0 + e + e * e - e * e * e) / (om * om * om) - p->a * rho * rho;
     } else {
         const double p1 = p->rho1 * p->th_v, p2 = p1 + (p->rho2 - p->rho1) * p->th_m;
         *out = rho <= p->rho1 ? rho * p->th_v
              : (rho <= p->rho2 ? p1 + (rho - p->rho1) * p->th_m : p2 + (rho - p->rho2) * p->th_l);
     }
-    return LBM_OK;
+    return std::isfinite(*out);
+}
+
+// The pseudopotential psi = sqrt(2 (p_EOS(rho) - rho/3) / G) exists at rho (non-negative radicand).
+static bool psi_defined(const lbm_params* p, double rho) {
+    double pr;
+    if (!host_pressure(p, rho, &pr)) return false;
+    const double rad = 2.0 * (pr - rho / 3.0) / p->G;
+    return std::isfinite(rad) && rad >= 0.0;
+}
+
+int lbm_pressure(const lbm_params* p, double rho, double* out) {
+    if (!out || validate(p, nullptr) != LBM_OK) return LBM_E_INVAL;
+    return host_pressure(p, rho, out) ? LBM_OK : LBM_E_INVAL;
 }
 
 int lbm_workspace_size(const lbm_params* p, size_t* bytes) {
@@ -514,14 +528,20 @@ static int create_impl(const lbm_params* p, const uint8_t* solid, const double* 
     if (p->walls && !gw_host) return LBM_E_INVAL;
     if (is_mask(p) != (solid != nullptr)) return LBM_E_INVAL;
     if (rho0_host) {
+        // every fluid density positive, finite and inside the pseudopotential's domain
         long long nfluid = 0;
         for (long long i = 0; i < (long long)p->nx * p->ny; ++i) {
             const int y = (int)(i / p->nx);
             if (solid ? solid[i] != 0 : (y < y_lo_of(p) || y > y_hi_of(p))) continue;
-            if (!finite_pos(rho0_host[i])) return LBM_E_INVAL;
+            if (!finite_pos(rho0_host[i]) || !psi_defined(p, rho0_host[i])) return LBM_E_INVAL;
             ++nfluid;
         }
         if (nfluid == 0) return LBM_E_INVAL;
+    } else {
+        // the droplet profiles lie between rho_v (1 - jitter) and rho_l (1 + jitter)
+        const double lo = p->rho_v * (1.0 - drops->jitter), hi = p->rho_l * (1.0 + drops->jitter);
+        for (int k = 0; k <= 1024; ++k)
+            if (!psi_defined(p, lo + (hi - lo) * k / 1024.0)) return LBM_E_INVAL;
     }
     const int gw_rows = solid ? p->ny : 2;
     if (gw_host)
@@ -1287,7 +1307,7 @@ static int batch_create_impl(const lbm_params* p, int32_t count,
         for (long long k = 0; k < (long long)p[i].nx * p[i].ny; ++k) {
             const int y = (int)(k / p[i].nx);
             if (solid ? solid[k] != 0 : (y < y_lo_of(&p[i]) || y > y_hi_of(&p[i]))) continue;
-            if (!finite_pos(rho0_host[i][k])) { delete b; return LBM_E_INVAL; }
+            if (!finite_pos(rho0_host[i][k]) || !psi_defined(&p[i], rho0_host[i][k])) { delete b; return LBM_E_INVAL; }
         }
         const int gw_rows = solid ? p[i].ny : 2;
         if (gw_host[i]) {
@@ -1873,7 +1893,8 @@ int lbm_autotune(const lbm_params* p, int32_t count, const double* const* gw_hos
 int lbm_fp64_probe(const double* d_a, const double* d_b, double* d_sqrt, double* d_quot,
                    size_t n, void* stream) {
     if (n == 0) return LBM_OK;
-    if (!d_a || !d_b || !d_sqrt || !d_quot || n > ((size_t)1 << 40)) return LBM_E_INVAL;
+    // at most 2^36 elements: 2^28 workgroups of 256, within the grid's x limit
+    if (!d_a || !d_b || !d_sqrt || !d_quot || n > ((size_t)1 << 36)) return LBM_E_INVAL;
     (void)hipGetLastError();
     const hipError_t e = lbm::launch_fp64_probe(d_a, d_b, d_sqrt, d_quot, (long long)n,
                                                 (hipStream_t)stream);

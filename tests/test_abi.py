@@ -73,7 +73,7 @@ def test_invalid_parameters_rejected_without_gpu(L, field, value, code):
     n = C.c_size_t()
     assert L.lib().lbm_workspace_size(C.byref(q), C.byref(n)) == code
     h = C.c_void_p()
-    rho0 = np.ones((q.ny, q.nx)); gw = np.zeros((2, q.nx))
+    rho0 = np.full((q.ny, q.nx), 0.3); gw = np.zeros((2, q.nx))
     dp = C.POINTER(C.c_double)
     rc = L.lib().lbm_create(C.byref(q), gw.ctypes.data_as(dp), rho0.ctypes.data_as(dp),
                             C.c_void_p(256), 1 << 40, None, C.byref(h))
@@ -95,7 +95,7 @@ def test_create_rejects_bad_buffers_without_gpu(L):
     q = good_params(L)
     need = L.workspace_size(q)
     dp = C.POINTER(C.c_double)
-    rho0 = np.ones((q.ny, q.nx)); gw = np.zeros((2, q.nx))
+    rho0 = np.full((q.ny, q.nx), 0.3); gw = np.zeros((2, q.nx))
     h = C.c_void_p()
     lib = L.lib()
     # workspace too small
@@ -112,6 +112,21 @@ def test_create_rejects_bad_buffers_without_gpu(L):
     bad = rho0.copy(); bad[5, 5] = 0.0
     assert lib.lbm_create(C.byref(q), gw.ctypes.data_as(dp), bad.ctypes.data_as(dp),
                           C.c_void_p(256), need, None, C.byref(h)) == -1
+    # a density outside the pseudopotential's domain (Carnahan-Starling: psi is real only below
+    # about 0.593 at these constants)
+    bad = rho0.copy(); bad[7, 9] = 0.7
+    assert lib.lbm_create(C.byref(q), gw.ctypes.data_as(dp), bad.ctypes.data_as(dp),
+                          C.c_void_p(256), need, None, C.byref(h)) == -1
+    # droplets whose jitter would leave that domain, or an invalid description
+    for kw in (dict(jitter=0.5), dict(width=-1.0), dict(radii=[0.0])):
+        args = dict(centres=[(32.0, 0.5)], radii=[8.0], width=2.0, jitter=1e-3, seed=1)
+        args.update(kw)
+        d = L.make_droplets(**args)
+        assert lib.lbm_create_droplets(C.byref(q), gw.ctypes.data_as(dp), C.byref(d),
+                                       C.c_void_p(256), need, None, C.byref(h)) == -1, kw
+    d = L.make_droplets([(32.0, 0.5)], [8.0])
+    assert lib.lbm_create_droplets(C.byref(q), gw.ctypes.data_as(dp), C.byref(d),
+                                   C.c_void_p(256), need - 1, None, C.byref(h)) == -2
     g2 = gw.copy(); g2[0, 3] = math.nan
     assert lib.lbm_create(C.byref(q), g2.ctypes.data_as(dp), rho0.ctypes.data_as(dp),
                           C.c_void_p(256), need, None, C.byref(h)) == -1
