@@ -239,6 +239,11 @@ def batched_speedup(args) -> dict:
     t_plain = _timed(plain)
     same = all(np.array_equal(b.f(i), sims[i].f()) for i in (0, len(sims) // 2, len(sims) - 1))
     bad = sum(1 for o in obs if o["nonfinite"])
+    # the ensemble's output: contact angle against G_w and the spurious current, per instance
+    per_instance = [{"nx": e["params"]["nx"], "form": e["form"], "G_w": round(e["G_w"], 5),
+                     "visc_ratio": e["visc_ratio"],
+                     "theta": None if math.isnan(o["theta_deg"]) else round(o["theta_deg"], 2),
+                     "umax": float(f"{o['umax']:.4g}")} for e, o in zip(ens, obs)]
     log(f"bench: batched {t_batch:.2f} s vs plain loop {t_plain:.2f} s")
     return {"value": round(t_plain / t_batch, 3), "unit": "x (plain loop time / batched time)",
             "mlups_batched": round(fluid * n / t_batch / 1e6, 1),
@@ -247,6 +252,7 @@ def batched_speedup(args) -> dict:
             "tune": {k: best[k] for k in ("tile", "schedule", "waves_per_cu")},
             "bitwise_equal_to_plain": bool(same), "nonfinite_instances": bad,
             "schedules": schedule_table(prm, gws, rhos, 40),
+            "per_instance": per_instance,
             "workload": "96 uneven lattices 128x64..512x256, 3 forms x G_w sweep x viscosity "
                         "ratios {1,5,15}"}
 
@@ -359,6 +365,8 @@ def c5_run(args) -> dict:
     states = [b.save_state(i) for i in range(len(prm))]
     ws = b.adjoint_workspace(NA, K)
     log(f"c5: ensemble adjoint workspace {ws.numel() / 2**30:.1f} GiB")
+    free, total = torch.cuda.mem_get_info()  # device-wide (hipMemGetInfo), at the high-water mark
+    used_at_peak = total - free
     t_ckpt = _timed(lambda: b.forward_ckpt(NA, K, ws), b.stream)
     holder = {}
     t_back = _timed(lambda: holder.update(L=b.loss(), g=b.backward(NA, K, ws)), b.stream)
@@ -423,7 +431,8 @@ def c5_run(args) -> dict:
                         "backward_roofline": back,
                         "losses": [round(v, 6) for v in holder["L"]],
                         "fd_nodes": 16, "max_rel_err_vs_fd": float(max(errs))},
-            "peak_device_bytes": int(peak), "droplet_angles_deg": angles, "dtype": "f64"}
+            "peak_device_bytes": int(peak), "device_bytes_in_use_at_peak": int(used_at_peak),
+            "droplet_angles_deg": angles, "dtype": "f64"}
 
 
 def paper_cases():
