@@ -14,13 +14,13 @@
 
 namespace lbm {
 
-template <int TX, int TY, int NTH>
+template <int TX, int TY, int NTH, int EOS>
 __global__ __launch_bounds__(NTH) void k_adj(KParams P, AdjPtrs A) {
     __shared__ AdjLds<TX, TY> lds;
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
     const int tile = xcd_tile(blockIdx.x, ntx * nty);
-    adj_tile<TX, TY, NTH>(P, A, (tile % ntx) * TX, P.y_lo + (tile / ntx) * TY, lds);
+    adj_tile<TX, TY, NTH, EOS>(P, A, (tile % ntx) * TX, P.y_lo + (tile / ntx) * TY, lds);
 }
 
 // dL/dG_w of the wall vectors of the last reverse step.
@@ -105,7 +105,10 @@ template <int TX, int TY, int NTH>
 static hipError_t launch_adj_t(const KParams& P, const AdjPtrs& A, hipStream_t s) {
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
-    hipLaunchKernelGGL((k_adj<TX, TY, NTH>), dim3(ntx * nty), dim3(NTH), 0, s, P, A);
+    if (P.eos == 0)
+        hipLaunchKernelGGL((k_adj<TX, TY, NTH, EOS_CS>), dim3(ntx * nty), dim3(NTH), 0, s, P, A);
+    else
+        hipLaunchKernelGGL((k_adj<TX, TY, NTH, EOS_PW>), dim3(ntx * nty), dim3(NTH), 0, s, P, A);
     return hipGetLastError();
 }
 

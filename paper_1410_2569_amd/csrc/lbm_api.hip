@@ -1801,7 +1801,7 @@ int lbm_batch_backward(lbm_batch* b, int64_t nsteps, int32_t K, void* d_adj, siz
         if (i + 1 <= len - 1 && e == hipSuccess)
             e = lbm::launch_batch_seg_step(b->eos, d_inst, d_tiles, L.ntiles, (int)i, s);
         for (i = len - 1; i >= 0 && e == hipSuccess; --i) {
-            e = lbm::launch_batch_adj(d_inst, d_tiles, L.ntiles, (int)i, k, s);
+            e = lbm::launch_batch_adj(b->eos, d_inst, d_tiles, L.ntiles, (int)i, k, s);
             k ^= 1;
         }
         if (e != hipSuccess) return batch_fail(b, LBM_E_HIP, "ensemble adjoint segment");

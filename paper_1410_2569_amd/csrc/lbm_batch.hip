@@ -174,6 +174,7 @@ __global__ __launch_bounds__(256) void k_batch_seg_step(const AdjInst* __restric
 }
 
 // One reverse step of every instance: segment state i, later-step buffers of parity k.
+template <int EOS>
 __global__ __launch_bounds__(256) void k_batch_adj(const AdjInst* __restrict__ inst,
                                                    const int* __restrict__ tile_inst, int ntiles,
                                                    int i, int k) {
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(256) void k_batch_adj(const AdjInst* __restrict__ i
     const AdjPtrs A{D->seg + (long long)i * D->fstride, D->a[k], D->q[k], D->p0[k], D->dpsi[k],
                     D->rv[k], D->gw, D->a[k ^ 1], D->q[k ^ 1], D->p0[k ^ 1], D->dpsi[k ^ 1],
                     D->rv[k ^ 1], D->gg};
-    adj_tile<64, 4>(D->P, A, x0, y0, lds);
+    adj_tile<64, 4, 256, EOS>(D->P, A, x0, y0, lds);
 }
 
 // dL/dG_w of the last reverse step's wall vectors (instance blockIdx.y).
@@ -353,10 +354,13 @@ hipError_t launch_batch_seg_step(int eos, const AdjInst* inst, const int* tile_i
     });
 }
 
-hipError_t launch_batch_adj(const AdjInst* inst, const int* tile_inst, int ntiles, int i, int k,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_adj, dim3(ntiles), dim3(256), 0, s, inst, tile_inst, ntiles, i, k);
-    return hipGetLastError();
+hipError_t launch_batch_adj(int eos, const AdjInst* inst, const int* tile_inst, int ntiles, int i,
+                            int k, hipStream_t s) {
+    return with_eos(eos, [&](auto e) {
+        hipLaunchKernelGGL((k_batch_adj<decltype(e)::value>), dim3(ntiles), dim3(256), 0, s, inst,
+                           tile_inst, ntiles, i, k);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_batch_adj_gw(const AdjInst* inst, int count, int max_nx, int k,

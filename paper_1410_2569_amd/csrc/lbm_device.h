@@ -65,7 +65,9 @@ __device__ __forceinline__ int wrapx(int x, int nx) {
 // Floating-point contraction is switched off inside the per-node arithmetic and the multiply-adds
 // are written as explicit fma(): the rounding of every result is then fixed by the source alone,
 // so every kernel that inlines these functions (plain step, every tile shape, ensembles,
-// persistent loop, adjoint recomputation) produces the same bits.
+// persistent loop, adjoint recomputation) produces the same bits. The reverse-mode functions
+// further down follow the same rule, so that every reverse-step tile (interior or not, of any
+// shape, single lattice or ensemble) gives the same gradient bits.
 
 // p_EOS(rho) and psi(rho); a negative radicand yields NaN, caught by the observables. EOS selects
 // the equation of state compiled in (EOS_ANY: P.eos at run time).
@@ -1014,9 +1016,11 @@ __device__ __forceinline__ void contact_line_block(const KParams& P, const doubl
 namespace lbm {
 
 // dpsi/drho = (p'(rho) - 1/3) / (G psi), from psi^2 = 2 (p - rho/3)/G.
+template <int EOS = EOS_ANY>
 __device__ __forceinline__ double dpsi_drho(const KParams& P, double rho, double psi) {
+#pragma clang fp contract(off)
     double dp;
-    if (P.eos == 0) {
+    if (EOS == EOS_CS || (EOS == EOS_ANY && P.eos == 0)) {
         const double e = P.b4 * rho, om = 1.0 - e;
         const double om2 = om * om;
         const double D1 = (1.0 + e * (4.0 + e * (4.0 + e * (-4.0 + e)))) / (om2 * om2);
@@ -1038,6 +1042,7 @@ __device__ __forceinline__ void collide_adj(const KParams& P, const double f[9],
                                             double Ay, const double nu[9], double fb[9],
                                             double& pb, double& qx, double& qy, double& rx,
                                             double& ry) {
+#pragma clang fp contract(off)
     // ---- forward recomputation (same expressions as collide) ----
     const double fmx = P.negG * psi_c * sx, fmy = P.negG * psi_c * sy;
     const double pre = P.wall_force == 0 ? rho : (P.wall_force == 1 ? psi_c : psi_c * psi_c);
@@ -1200,9 +1205,26 @@ __device__ __forceinline__ void push_gather_a(const KParams& P, const double* __
     av[8] = bot ? (a + 6 * pl)[i0] : (a + 8 * pl)[rm + xp];
 }
 
+// push_gather_a for a node whose neighbours are all fluid, inside the lattice (no wrap).
+__device__ __forceinline__ void push_gather_a_in(const KParams& P, const double* __restrict__ a,
+                                                 int x, int y, double av[9]) {
+    const long long pl = P.plane;
+    const unsigned r0 = (unsigned)y * P.pitch + x, rm = r0 - P.pitch, rp = r0 + P.pitch;
+    av[0] = a[r0];
+    av[1] = (a + 1 * pl)[r0 + 1];
+    av[3] = (a + 3 * pl)[r0 - 1];
+    av[2] = (a + 2 * pl)[rp];
+    av[5] = (a + 5 * pl)[rp + 1];
+    av[6] = (a + 6 * pl)[rp - 1];
+    av[4] = (a + 4 * pl)[rm];
+    av[7] = (a + 7 * pl)[rm - 1];
+    av[8] = (a + 8 * pl)[rm + 1];
+}
+
+template <bool IN = false>
 __device__ __forceinline__ void push_add_c(const KParams& P, const double av[9], const double* cs,
                                            int W, int l, int y, double nu[9]) {
-    const bool top = P.walls && y == P.ny - 2, bot = P.walls && y == 1;
+    const bool top = !IN && P.walls && y == P.ny - 2, bot = !IN && P.walls && y == 1;
     const double c0 = cs[l];
     nu[0] = av[0] + c0;
     nu[1] = av[1] + cs[l + 1];
@@ -1218,13 +1240,15 @@ __device__ __forceinline__ void push_add_c(const KParams& P, const double av[9],
 // xi = dL/dpsi of node (x, y) = p0 + sum_a w_a e_a . q(x - e_a) (+ the mirrored ghost rows, whose
 // psi is this row's), the transpose of the cohesion stencil of Eq. (7); q from an LDS tile
 // (slot l, row stride W; rows outside the fluid hold 0).
+template <bool IN = false>
 __device__ __forceinline__ double adj_xi(const KParams& P, const double* qx, const double* qy,
                                          int W, int l, int y, double p0) {
+#pragma clang fp contract(off)
     double xi = (qx[l - 1] - qx[l + 1] + qy[l - W] - qy[l + W]) * (1.0 / 3.0) +
                 ((qx[l - W - 1] + qy[l - W - 1]) + (qy[l - W + 1] - qx[l - W + 1]) -
                  (qx[l + W + 1] + qy[l + W + 1]) + (qx[l + W - 1] - qy[l + W - 1])) *
                     (1.0 / 12.0);
-    if (P.walls && P.ghost) {
+    if (!IN && P.walls && P.ghost) {
         if (y == 1)
             xi += -qy[l] * (1.0 / 3.0) +
                   ((-qx[l + 1] - qy[l + 1]) + (qx[l - 1] - qy[l - 1])) * (1.0 / 12.0);
@@ -1265,6 +1289,7 @@ struct AdjLds {
 // from the wall vectors r = dL/dA of one step (omega = w/3: 1/9 axial, 1/36 diagonal).
 __device__ __forceinline__ void adj_gw_node(const KParams& P, const double* __restrict__ rv,
                                             double* __restrict__ gwgrad, int x, int y) {
+#pragma clang fp contract(off)
     const unsigned pitch = P.pitch, ux = x;
     const unsigned xm = ux == 0 ? P.nx - 1 : ux - 1;
     const unsigned xp = ux == (unsigned)P.nx - 1 ? 0 : ux + 1;
@@ -1289,10 +1314,12 @@ __device__ __forceinline__ void adj_gw_node(const KParams& P, const double* __re
 // collision, forcing and adhesion (collide_adj). The later step's wall vectors are added to the
 // G_w gradient (the last reverse step's by adj_gw_node afterwards).
 // NTH threads: one per tile node, or twice as many, the others taking ring work only (more
-// waves per compute unit on small lattices).
-template <int TX, int TY, int NTH = TX * TY>
-__device__ __forceinline__ void adj_tile(const KParams& P, const AdjPtrs& A, int x0, int y0,
-                                         AdjLds<TX, TY>& L) {
+// waves per compute unit on small lattices). EOS: the equation of state (EOS_ANY: chosen at run
+// time). IN: the interior variant (adj_interior), without wall, ghost and wrap rules.
+template <int TX, int TY, int NTH, int EOS, bool IN>
+__device__ __forceinline__ void adj_tile_impl(const KParams& P, const AdjPtrs& A, int x0, int y0,
+                                              AdjLds<TX, TY>& L) {
+#pragma clang fp contract(off)
     constexpr int NT = NTH, NTILE = TX * TY;
     static_assert(NTH == NTILE || NTH == 2 * NTILE, "one or two threads per tile node");
     constexpr int LW = TX + 2, QW = TX + 4;
@@ -1310,14 +1337,18 @@ __device__ __forceinline__ void adj_tile(const KParams& P, const AdjPtrs& A, int
     double f[9];
     double rho = 1.0, psi_c = 0.0;
     if (active) {
-        pull9<GEO_ROWS>(P, A.gprev, x, y, f);
+        if constexpr (IN) pull9_in(P, A.gprev, x, y, f);
+        else pull9<GEO_ROWS>(P, A.gprev, x, y, f);
         rho = sum9(f);
-        psi_c = psi_of_rho(P, rho);
+        psi_c = psi_of_rho<EOS>(P, rho);
     }
     double av[9];
-    if (active) push_gather_a(P, A.a_in, x, y, av);
+    if (active) {
+        if constexpr (IN) push_gather_a_in(P, A.a_in, x, y, av);
+        else push_gather_a(P, A.a_in, x, y, av);
+    }
     double Ax = 0.0, Ay = 0.0;
-    const bool wall_row = P.walls && (y == 1 || y == P.ny - 2);
+    const bool wall_row = !IN && P.walls && (y == 1 || y == P.ny - 2);
     if (active && wall_row) adhesion_sum(P, A.gw, x, y, Ax, Ay);
     // p0 and psi' of the later step on this thread's slots of the c ring
     constexpr int NC = (TY + 2) * LW, NCR = (NC + NT - 1) / NT;
@@ -1330,34 +1361,48 @@ __device__ __forceinline__ void adj_tile(const KParams& P, const AdjPtrs& A, int
         dpv[r] = 0.0;
         flv[r] = false;
         if (s >= NC) continue;
-        const int gx = wrapx(x0 - 1 + s % LW, P.nx);
-        int gy = y0 - 1 + s / LW;
-        if (P.walls) {
-            if (gy < 1 || gy > P.ny - 2) continue;
-        } else {
-            gy = wrapx(gy, P.ny);
+        int gx = x0 - 1 + s % LW, gy = y0 - 1 + s / LW;
+        if constexpr (!IN) {
+            gx = wrapx(gx, P.nx);
+            if (P.walls) {
+                if (gy < 1 || gy > P.ny - 2) continue;
+            } else {
+                gy = wrapx(gy, P.ny);
+            }
         }
         const unsigned i = (unsigned)gy * P.pitch + gx;
         p0v[r] = A.p0_in[i];
         dpv[r] = A.dpsi_in[i];
         flv[r] = true;
     }
-    if (owner) L.sp[(ty + 1) * LW + tx + 1] = active ? psi_c : psi_at<GEO_ROWS>(P, A.gprev, x, y);
+    // psi of the ring: interior tiles pull every ring node directly (all fluid, no wrap)
+    auto ring_psi = [&](int gx, int gy) {
+        if constexpr (IN) {
+            double fr[9];
+            pull9_in(P, A.gprev, gx, gy, fr);
+            return psi_of_rho<EOS>(P, sum9(fr));
+        } else {
+            return psi_at<GEO_ROWS, EOS>(P, A.gprev, gx, gy);
+        }
+    };
+    if (owner) L.sp[(ty + 1) * LW + tx + 1] = active ? psi_c : ring_psi(x, y);
     for (int h = rt; h < NH; h += NT) {
         int hx, hy;
         if (h < LW) { hx = h - 1; hy = -1; }
         else if (h < 2 * LW) { hx = h - LW - 1; hy = TY; }
         else if (h < 2 * LW + TY) { hx = -1; hy = h - 2 * LW; }
         else { hx = TX; hy = h - 2 * LW - TY; }
-        L.sp[(hy + 1) * LW + hx + 1] = psi_at<GEO_ROWS>(P, A.gprev, x0 + hx, y0 + hy);
+        L.sp[(hy + 1) * LW + hx + 1] = ring_psi(x0 + hx, y0 + hy);
     }
     // q of the later step on the tile and two rings (0 outside the fluid rows)
     for (int s = rt; s < (TY + 4) * QW; s += NT) {
-        const int gx = wrapx(x0 - 2 + s % QW, P.nx);
-        int gy = y0 - 2 + s / QW;
+        int gx = x0 - 2 + s % QW, gy = y0 - 2 + s / QW;
         bool fluid = true;
-        if (P.walls) fluid = gy >= 1 && gy <= P.ny - 2;
-        else gy = wrapx(gy, P.ny);
+        if constexpr (!IN) {
+            gx = wrapx(gx, P.nx);
+            if (P.walls) fluid = gy >= 1 && gy <= P.ny - 2;
+            else gy = wrapx(gy, P.ny);
+        }
         double vx = 0.0, vy = 0.0;
         if (fluid) {
             const unsigned i = (unsigned)gy * P.pitch + gx;
@@ -1375,8 +1420,9 @@ __device__ __forceinline__ void adj_tile(const KParams& P, const AdjPtrs& A, int
         if (s >= NC) continue;
         const int hx = s % LW, hy = s / LW;
         int gy = y0 - 1 + hy;
-        if (!P.walls) gy = wrapx(gy, P.ny);
-        L.cs[s] = flv[r] ? dpv[r] * adj_xi(P, L.qx, L.qy, QW, (hy + 1) * QW + hx + 1, gy, p0v[r])
+        if (!IN && !P.walls) gy = wrapx(gy, P.ny);
+        L.cs[s] = flv[r] ? dpv[r] * adj_xi<IN>(P, L.qx, L.qy, QW, (hy + 1) * QW + hx + 1, gy,
+                                               p0v[r])
                          : 0.0;
     }
     __syncthreads();
@@ -1388,7 +1434,7 @@ __device__ __forceinline__ void adj_tile(const KParams& P, const AdjPtrs& A, int
                  cc[LW + 1], sx, sy);
 
     double nu[9], fb[9], pb, qx, qy, rx, ry;
-    push_add_c(P, av, L.cs, LW, (ty + 1) * LW + tx + 1, y, nu);
+    push_add_c<IN>(P, av, L.cs, LW, (ty + 1) * LW + tx + 1, y, nu);
     collide_adj(P, f, rho, psi_c, sx, sy, Ax, Ay, nu, fb, pb, qx, qy, rx, ry);
 
     const unsigned i = (unsigned)y * P.pitch + x;
@@ -1397,12 +1443,32 @@ __device__ __forceinline__ void adj_tile(const KParams& P, const AdjPtrs& A, int
     A.q_out[i] = qx;
     (A.q_out + P.plane)[i] = qy;
     A.p0_out[i] = pb;
-    A.dpsi_out[i] = dpsi_drho(P, rho, psi_c);
+    A.dpsi_out[i] = dpsi_drho<EOS>(P, rho, psi_c);
     if (wall_row) {
         if (y == 1) { A.rv_out[x] = rx; A.rv_out[P.pitch + x] = ry; }
         if (y == P.ny - 2) { A.rv_out[2 * P.pitch + x] = rx; A.rv_out[3 * P.pitch + x] = ry; }
         adj_gw_node(P, A.rv_in, A.gwgrad, x, y);
     }
+}
+
+// A reverse-step tile whose reads (the tile grown by two rings for q, by one for the rest, and
+// the pulls of those) stay inside the lattice without wrapping and touch no node next to a wall
+// row: no bounce-back, ghost row, wall force or wall vector is involved.
+template <int TX, int TY>
+__device__ __forceinline__ bool adj_interior(const KParams& P, int x0, int y0) {
+    if (x0 - 2 < 0 || x0 + TX + 1 > P.nx - 1) return false;
+    if (P.walls) return y0 >= 4 && y0 + TY + 1 <= P.ny - 3;
+    return y0 >= 3 && y0 + TY + 2 <= P.ny - 1;
+}
+
+// One reverse step on a TX x TY tile: the interior variant where it applies (a uniform branch).
+template <int TX, int TY, int NTH = TX * TY, int EOS = EOS_ANY>
+__device__ __forceinline__ void adj_tile(const KParams& P, const AdjPtrs& A, int x0, int y0,
+                                         AdjLds<TX, TY>& L) {
+    if (adj_interior<TX, TY>(P, x0, y0))
+        adj_tile_impl<TX, TY, NTH, EOS, true>(P, A, x0, y0, L);
+    else
+        adj_tile_impl<TX, TY, NTH, EOS, false>(P, A, x0, y0, L);
 }
 
 }  // namespace lbm

@@ -110,8 +110,8 @@ hipError_t launch_batch_seg_step2(int eos, const AdjInst* inst, const int* tile_
                                   int i, hipStream_t s);
 hipError_t launch_batch_seg_step(int eos, const AdjInst* inst, const int* tile_inst, int ntiles,
                                  int i, hipStream_t s);
-hipError_t launch_batch_adj(const AdjInst* inst, const int* tile_inst, int ntiles, int i, int k,
-                            hipStream_t s);
+hipError_t launch_batch_adj(int eos, const AdjInst* inst, const int* tile_inst, int ntiles, int i,
+                            int k, hipStream_t s);
 hipError_t launch_batch_adj_gw(const AdjInst* inst, int count, int max_nx, int k,
                                hipStream_t s);
 

@@ -14,7 +14,8 @@
 // per-node observables are run the same way and must produce finite sums. On periodic and
 // bounce-back lattices the adjoint's kernels run too: the segment recomputation (two steps with
 // the first written) must equal two fused steps, and one reverse step must write every output
-// on the fluid nodes only, bit-equal between its 32 x 4 and 64 x 4 tiles.
+// on the fluid nodes only, bit-equal between the generic tile everywhere and 32 x 4 and 64 x 4
+// tiles that take the interior variant where it applies.
 //
 // Test infrastructure: built and run by tests/test_emu_index_maps.py. Usage:
 //   tile_emu            run the built-in case list
@@ -366,7 +367,8 @@ struct AdjBufs {
         gg;
 };
 
-template <int TX, int TY>
+// MODE 0: adj_tile (interior variant where it applies), 1: every tile the generic variant.
+template <int TX, int TY, int NTH = TX * TY, int EOS = lbm::EOS_ANY, int MODE = 0>
 void adj_step(const Lattice& L, const double* gprev, AdjBufs& B) {
     const KParams& P = L.P;
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.y_hi - P.y_lo + TY) / TY;
@@ -376,8 +378,12 @@ void adj_step(const Lattice& L, const double* gprev, AdjBufs& B) {
                          B.q_out.data(),  B.p0_out.data(), B.dpsi_out.data(), B.rv_out.data(),
                          B.gg.data()};
     run_workgroups(
-        TX * TY, ntx * nty,
-        [&](int t) { lbm::adj_tile<TX, TY>(P, A, (t % ntx) * TX, P.y_lo + (t / ntx) * TY, *lds); },
+        NTH, ntx * nty,
+        [&](int t) {
+            const int x0 = (t % ntx) * TX, y0 = P.y_lo + (t / ntx) * TY;
+            if constexpr (MODE == 0) lbm::adj_tile<TX, TY, NTH, EOS>(P, A, x0, y0, *lds);
+            else lbm::adj_tile_impl<TX, TY, NTH, EOS, false>(P, A, x0, y0, *lds);
+        },
         [&] { std::fill((double*)lds, (double*)lds + sizeof *lds / sizeof(double), kNaN); });
     delete lds;
 }
@@ -463,11 +469,15 @@ void run_adjoint(const Lattice& L, const std::vector<double>& g0, const std::vec
         check_output(L, out, name);
         check_equal(L, out, g2, name);
     }
-    // one reverse step with 32 x 4 and 64 x 4 tiles
-    AdjBufs X = make_adj(L), Y = make_adj(L);
-    adj_step<32, 4>(L, g0.data(), X);
-    adj_step<64, 4>(L, g0.data(), Y);
-    check_adj(L, X, Y, "reverse step 32x4 vs 64x4");
+    // one reverse step: the generic tile everywhere (32 x 4), against 64 x 4 tiles and 32 x 4
+    // tiles with two threads per node, both with the interior variant where it applies and the
+    // equation of state fixed at compile time
+    AdjBufs X = make_adj(L), Y = make_adj(L), Z = make_adj(L);
+    adj_step<32, 4, 128, lbm::EOS_ANY, 1>(L, g0.data(), X);
+    adj_step<64, 4, 256, EOS>(L, g0.data(), Y);
+    adj_step<32, 4, 256, EOS>(L, g0.data(), Z);
+    check_adj(L, X, Y, "reverse step: generic 32x4 vs 64x4 (interior variant)");
+    check_adj(L, X, Z, "reverse step: generic 32x4 vs 32x4, 256 threads (interior variant)");
 }
 
 template <int GEO, int EOS>

@@ -9,7 +9,8 @@ buffers, reads an LDS slot not written in the same launch, writes outside the st
 two-step tiles differ by one bit from two fused steps. On periodic and bounce-back lattices the
 adjoint's kernels run too: the segment recomputation (two steps with the intermediate state
 written) must equal two fused steps, and a reverse step must write all of its outputs on the
-fluid nodes only, bit-equal between its 32x4 and 64x4 tiles. Lattices from 3x4 to 125x17 (ragged
+fluid nodes only, bit-equal between the generic tile everywhere and 32x4 and 64x4 tiles that
+take the interior variant where it applies. Lattices from 3x4 to 125x17 (ragged
 tiles, halo wraps) and two with interior tiles; periodic, bounce-back (with and without ghost
 rows), wet-node and solid-mask geometries; both equations of state.
 
