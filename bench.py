@@ -779,6 +779,31 @@ def profile_probe(args):
     log(f"profile probe: copy {COPY_BYTES} B x3, 20 steps of {q.nx}x{q.ny}")
 
 
+def schedule_probe(args):
+    """Workload for rocprofv3 counter runs of the ensemble schedules: 20 steps of the 96-lattice
+    ensemble with graph-replayed two-step launches of 64x8 tiles, then 20 steps with the
+    persistent schedule on the same tiles (one launch)."""
+    import torch
+
+    import paper_1410_2569_amd as L
+    import synth
+
+    prm, gws, rhos = [], [], []
+    for e in synth.c3_ensemble():
+        q = L.make_params(e["params"])
+        prm.append(dict(e["params"], rho_l=q.rho_l, rho_v=q.rho_v))
+        gws.append(e["gw"])
+        rhos.append(synth.droplet_rho(q.nx, q.ny, q.rho_l, q.rho_v, e["centres"], e["radii"],
+                                      seed=e["seed"]))
+    for schedule in (2, 1):
+        b = L.Batch(prm, gws, rhos, tune={"tile": 1, "schedule": schedule})
+        b.step(20)
+        torch.cuda.synchronize()
+        log(f"schedule probe: {len(prm)} lattices, tile 64x8, schedule {schedule}, 20 steps")
+        del b
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -818,6 +843,9 @@ def main():
     ap.add_argument("--profile-probe", action="store_true",
                     help="for counter runs: a device copy of known size, then 20 step launches "
                          "of one run of the workload; prints no JSON")
+    ap.add_argument("--schedule-probe", action="store_true",
+                    help="for counter runs: 20 steps of the 96-lattice ensemble graph-replayed, "
+                         "then 20 persistent (64x8 tiles); prints no JSON")
     args = ap.parse_args()
     if args.cpu_baseline_only is not None:
         print(json.dumps(cpu_baseline(args.cpu_baseline_only)), flush=True)
@@ -841,6 +869,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.profile_probe:
         profile_probe(args)
+        return
+    if args.schedule_probe:
+        schedule_probe(args)
         return
     if args.workload == "c5":
         print(json.dumps(c5_run(args)), flush=True)

@@ -295,9 +295,10 @@ int lbm_backward(lbm_ctx *c, int64_t nsteps, int32_t K, void *d_ws, size_t bytes
  * `count` independent instances (each with its own lbm_params: lattice size, wall force, G_w,
  * viscosities ...) advanced together. All instances' tiles form one work-list, executed by one
  * launch per time step (schedule 0) or per two steps (schedule 2), replayed from captured
- * hipGraphs, or by one persistent launch for n steps (schedule 1: an occupancy-sized grid that
- * advances its tiles two steps at a time, with a grid barrier between the two-step passes, and a
- * per-step launch for an odd last step; lbm_batch_step is then a single hipGraphLaunch). All run
+ * hipGraphs, or by one persistent launch for n steps (schedule 1: an occupancy-sized grid whose
+ * workgroups take tiles from a ticket counter per XCD and advance them two steps at a time, with
+ * a grid barrier between the two-step passes, and a per-step launch for an odd last step;
+ * lbm_batch_step is then a single hipGraphLaunch). All run
  * the same per-tile arithmetic as lbm_step, so every instance evolves bit-for-bit as it would
  * alone.
  */

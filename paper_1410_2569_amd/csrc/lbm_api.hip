@@ -1185,8 +1185,8 @@ bool batch_layout(const lbm_params* p, int32_t count, int tile, BatchLayout* B) 
     B->ntiles = (int)nt;
     B->off_tiles = o;
     o += align_up((size_t)nt * sizeof(int), kAlign);
-    B->off_bar = o;
-    o += kAlign;
+    B->off_bar = o;  // the persistent schedule's control block
+    o += align_up((size_t)lbm::kControlWords * 8, kAlign);
     B->off_rows = o;
     o += align_up((size_t)count * sizeof(int), kAlign);
     B->off_inst.resize(count);

@@ -94,7 +94,17 @@ hipError_t launch_batch_step(int tile, int geo, int eos, const InstDesc* inst,
                              const int* tile_inst, int ntiles, int cur, hipStream_t s);
 hipError_t launch_batch_step2(int tile, int geo, int eos, const InstDesc* inst,
                               const int* tile_inst, int ntiles, int cur, hipStream_t s);
-// npairs two-step passes in one launch (after a reset of the barrier counter and abort flag)
+// The persistent schedule's control block (kControlWords 8-byte words of the ensemble
+// workspace): the grid barrier's arrival counter (word 0), the abort flag (an int at byte 64),
+// and per XCD a tile-ticket counter, a barrier arrival counter, a barrier gate and a count of
+// its workgroups (kXcds words each from kTicketSlot, kXcdArrSlot, kXcdGateSlot, kXcdRegSlot).
+constexpr int kXcds = 8;
+constexpr int kTicketSlot = 16;
+constexpr int kXcdArrSlot = kTicketSlot + kXcds;
+constexpr int kXcdGateSlot = kXcdArrSlot + kXcds;
+constexpr int kXcdRegSlot = kXcdGateSlot + kXcds;
+constexpr int kControlWords = kXcdRegSlot + kXcds;
+// npairs two-step passes in one launch (after a reset of the control block)
 hipError_t launch_batch_persistent(int tile, int geo, int eos, int grid, const InstDesc* inst,
                                    const int* tile_inst, int ntiles, int npairs, int cur,
                                    unsigned long long* bar, int* flag, int spin_limit,

@@ -185,3 +185,27 @@ def test_delete_and_reallocate_without_sync(orc, gpu, schedule):
     b.step(200)
     for i in range(len(cases)):
         assert np.array_equal(b.f(i), ref[i])
+
+
+@pytest.mark.parametrize("tile", [1, 2])
+def test_persistent_full_size_bitwise_equals_graph(orc, gpu, tile):
+    """The 96-lattice ensemble with the persistent schedule (one launch of 40 steps: 20 two-step
+    passes, every barrier after the first through the per-XCD leaders) against graph-replayed
+    two-step launches of the same tiles, every instance bit for bit; at full size every XCD runs
+    dozens of workgroups, each taking many tiles per pass from its XCD's ticket counter."""
+    ens = synth.c3_ensemble()
+    prm, gws, rhos = [], [], []
+    for e in ens:
+        q = orc.make_params(e["params"])
+        prm.append(dict(e["params"], rho_l=q.rho_l, rho_v=q.rho_v))
+        gws.append(e["gw"])
+        rhos.append(synth.droplet_rho(q.nx, q.ny, q.rho_l, q.rho_v, e["centres"], e["radii"],
+                                      seed=e["seed"]))
+    out = []
+    for schedule in (2, 1):
+        b = gpu.Batch(prm, gws, rhos, tune={"tile": tile, "schedule": schedule})
+        b.step(40)
+        out.append([b.f(i) for i in range(len(prm))])
+        del b
+    for i in range(len(prm)):
+        assert np.array_equal(out[0][i], out[1][i]), f"instance {i} differs (tile {tile})"
