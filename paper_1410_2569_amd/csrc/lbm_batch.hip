@@ -265,9 +265,9 @@ k_batch_seg_step2(const AdjInst* __restrict__ inst, const int* __restrict__ tile
     const int lt = t - D->tile0_8;
     const int x0 = (lt % D->ntx) * 64;
     const int y0 = D->P.y_lo + (lt / D->ntx) * 8;
-    double* s0 = D->seg + (long long)i * D->fstride;
-    step2_tile_any<64, 8, GEO_ROWS, EOS, true>(D->P, s0, s0 + 2 * D->fstride, D->gw, x0, y0, lds,
-                                               s0 + D->fstride);
+    double* s0 = gptr(D->seg) + (long long)i * D->fstride;
+    step2_tile_any<64, 8, GEO_ROWS, EOS, true>(D->P, s0, s0 + 2 * D->fstride, gptr(D->gw), x0, y0,
+                                               lds, s0 + D->fstride);
 }
 
 // Segment state i -> i+1 of every instance (one fused step).
@@ -280,8 +280,9 @@ __global__ __launch_bounds__(256) void k_batch_seg_step(const AdjInst* __restric
     const AdjInst* D = inst + tile_inst[t];
     int x0, y0;
     adj_tile_origin(D, t, x0, y0);
-    double* s0 = D->seg + (long long)i * D->fstride;
-    step_tile<64, 4, true, GEO_ROWS, EOS>(D->P, s0, s0 + D->fstride, nullptr, D->gw, x0, y0, sp);
+    double* s0 = gptr(D->seg) + (long long)i * D->fstride;
+    step_tile<64, 4, true, GEO_ROWS, EOS>(D->P, s0, s0 + D->fstride, nullptr, gptr(D->gw), x0, y0,
+                                          sp);
 }
 
 // One reverse step of every instance: segment state i, later-step buffers of parity k.
@@ -294,9 +295,10 @@ __global__ __launch_bounds__(256) void k_batch_adj(const AdjInst* __restrict__ i
     const AdjInst* D = inst + tile_inst[t];
     int x0, y0;
     adj_tile_origin(D, t, x0, y0);
-    const AdjPtrs A{D->seg + (long long)i * D->fstride, D->a[k], D->q[k], D->p0[k], D->dpsi[k],
-                    D->rv[k], D->gw, D->a[k ^ 1], D->q[k ^ 1], D->p0[k ^ 1], D->dpsi[k ^ 1],
-                    D->rv[k ^ 1], D->gg};
+    const AdjPtrs A{gptr(D->seg) + (long long)i * D->fstride,
+                    gptr(D->a[k]),     gptr(D->q[k]),     gptr(D->p0[k]),     gptr(D->dpsi[k]),
+                    gptr(D->rv[k]),    gptr(D->gw),       gptr(D->a[k ^ 1]),  gptr(D->q[k ^ 1]),
+                    gptr(D->p0[k ^ 1]), gptr(D->dpsi[k ^ 1]), gptr(D->rv[k ^ 1]), gptr(D->gg)};
     adj_tile<64, 4, 256, EOS>(D->P, A, x0, y0, lds);
 }
 
