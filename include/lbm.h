@@ -298,7 +298,10 @@ int lbm_backward(lbm_ctx *c, int64_t nsteps, int32_t K, void *d_ws, size_t bytes
  * hipGraphs, or by one persistent launch for n steps (schedule 1: an occupancy-sized grid whose
  * workgroups take tiles from a ticket counter per XCD and advance them two steps at a time, with
  * a grid barrier between the two-step passes, and a per-step launch for an odd last step;
- * lbm_batch_step is then a single hipGraphLaunch). All run
+ * lbm_batch_step is then a single hipGraphLaunch; each wait at a barrier gives up after
+ * LBM_PERSISTENT_SPIN_LIMIT polls, an environment variable read when the ensemble is created
+ * (default 4,194,304), and ends the whole run through an abort flag that the next observables call
+ * reports as LBM_E_HIP). All run
  * the same per-tile arithmetic as lbm_step, so every instance evolves bit-for-bit as it would
  * alone.
  */

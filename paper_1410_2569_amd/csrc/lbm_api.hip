@@ -1135,6 +1135,7 @@ struct lbm_batch {
     int64_t step;
     lbm_tune tune;
     int grid;  // persistent grid size
+    int spin_limit;  // polls before a persistent grid barrier aborts the run
     int geo;   // lbm::GEO_ROWS, GEO_WET (some instance wet-node) or GEO_MASK (all masked)
     int eos;   // lbm::EOS_CS or EOS_PW shared by every instance, else EOS_ANY
     std::vector<int32_t> rows;  // contact-line rows of the last record call (host copy)
@@ -1156,6 +1157,17 @@ constexpr int kGraphChunk = 64;
 
 
 constexpr int kSpinLimit = 1 << 22;
+
+// Polls a persistent grid barrier makes before it aborts the run: LBM_PERSISTENT_SPIN_LIMIT when
+// set to a non-negative integer (read when an ensemble is created), else kSpinLimit.
+static int spin_limit_from_env() {
+    const char* v = std::getenv("LBM_PERSISTENT_SPIN_LIMIT");
+    if (!v || !*v) return kSpinLimit;
+    char* end = nullptr;
+    const long n = std::strtol(v, &end, 10);
+    if (*end != '\0' || n < 0 || n > (1L << 30)) return kSpinLimit;
+    return (int)n;
+}
 
 struct BatchLayout {
     size_t off_desc, off_tiles, off_bar, off_rows, total;
@@ -1347,6 +1359,7 @@ static int batch_create_impl(const lbm_params* p, int32_t count,
     int occ = lbm::batch_persistent_occupancy(tn.tile);
     if (tn.waves_per_cu > 0 && tn.waves_per_cu < occ) occ = tn.waves_per_cu;
     b->grid = std::max(1, std::min(occ * cus, b->ntiles));
+    b->spin_limit = spin_limit_from_env();
     *out = b;
     return LBM_OK;
 }
@@ -1435,7 +1448,7 @@ int lbm_batch_step(lbm_batch* b, int64_t n) {
             if (npairs > 0)
                 e = lbm::launch_batch_persistent(b->tune.tile, b->geo, b->eos, b->grid, b->d_inst,
                                                  b->d_tile_inst, b->ntiles, npairs, cur, b->d_bar,
-                                                 b->d_flag, kSpinLimit, b->stream);
+                                                 b->d_flag, b->spin_limit, b->stream);
             if (e == hipSuccess && (n & 1))
                 e = lbm::launch_batch_step(b->tune.tile, b->geo, b->eos, b->d_inst,
                                            b->d_tile_inst, b->ntiles, cur ^ (npairs & 1),

@@ -209,3 +209,27 @@ def test_persistent_full_size_bitwise_equals_graph(orc, gpu, tile):
         del b
     for i in range(len(prm)):
         assert np.array_equal(out[0][i], out[1][i]), f"instance {i} differs (tile {tile})"
+
+
+def test_persistent_barrier_timeout_aborts_cleanly(orc, gpu, monkeypatch):
+    """A persistent run whose barrier waits may not poll at all (LBM_PERSISTENT_SPIN_LIMIT=0, read
+    when the ensemble is created): every workgroup leaves through the abort flag instead of
+    waiting, the next observables call reports the time-out, and a new ensemble created without
+    the setting runs normally, bit for bit as the plain runs."""
+    cases = ensemble(orc, n=4, seed=5)
+    args = ([c[0] for c in cases], [c[1] for c in cases], [c[2] for c in cases])
+    tune = {"tile": 1, "schedule": 1}
+    monkeypatch.setenv("LBM_PERSISTENT_SPIN_LIMIT", "0")
+    b = gpu.Batch(*args, tune=tune)
+    monkeypatch.delenv("LBM_PERSISTENT_SPIN_LIMIT")
+    b.step(40)
+    with pytest.raises(gpu.LBMError) as e:
+        b.observables()
+    assert "timed out" in str(e.value)
+    del b
+    ref = plain_states(gpu, cases, 40)
+    b = gpu.Batch(*args, tune=tune)
+    b.step(40)
+    for i in range(len(cases)):
+        assert np.array_equal(b.f(i), ref[i])
+
