@@ -224,11 +224,15 @@ k_batch_persistent(const InstDesc* __restrict__ inst, const int* __restrict__ ti
                     if (x == xcc) next[0] = c;
                 }
                 next[1] = n;
+                // an XCD id beyond the control block raised the flag at registration
+                verdict = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
             }
             __syncthreads();
             nx = next[0];
             ng = next[1];
+            const bool go = verdict != 0;
             __syncthreads();  // next[] serves the tickets again
+            if (!go) return;
         } else if (!xcd_barrier(bar, xcc, nx, ng, (unsigned long long)G, (unsigned long long)k,
                                 flag, spin_limit, &verdict)) {
             return;

@@ -127,9 +127,10 @@ def test_wet_node_save_load_carries_wall_force(orc, gpu):
     assert_close(q, a, orc.run(q, gw, orc.init_rest(q, rho0), 121), "wet save/load")
 
 
-@pytest.mark.parametrize("schedule", [0, 2])
+@pytest.mark.parametrize("schedule", [0, 1, 2])
 def test_batch_mixing_wall_schemes(orc, gpu, schedule):
-    """An ensemble with both wall schemes: each instance bit-identical to its lone run."""
+    """An ensemble with both wall schemes: each instance bit-identical to its lone run (per-step
+    launches, the persistent launch, two steps per launch)."""
     cases = []
     for i, (nx, ny, walls, form) in enumerate([(64, 24, 2, "rho"), (96, 41, 1, "psi"),
                                                (37, 12, 2, "modpsi"), (130, 64, 2, "psi")]):
@@ -141,7 +142,7 @@ def test_batch_mixing_wall_schemes(orc, gpu, schedule):
         g = synth.gw_smooth(nx, {"rho": 0.05, "psi": -0.02, "modpsi": 0.1}[form], 0.02, seed=i)
         cases.append((dict(p, rho_l=q.rho_l, rho_v=q.rho_v), g, rho0))
     steps = 131
-    tile = 1 if schedule == 2 else 0
+    tile = 0 if schedule == 0 else 1
     b = gpu.Batch([c[0] for c in cases], [c[1] for c in cases], [c[2] for c in cases],
                   tune={"tile": tile, "schedule": schedule})
     b.step(steps)
