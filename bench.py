@@ -804,6 +804,32 @@ def schedule_probe(args):
         torch.cuda.empty_cache()
 
 
+def c5_adjoint_probe(args):
+    """Workload for rocprofv3 counter runs of the ensemble adjoint: the 8 x 2048x1024 ensemble
+    advanced 20 steps, then a 40-step checkpointed forward (checkpoint every 10 steps), the loss
+    and one ensemble reverse sweep."""
+    import torch
+
+    import paper_1410_2569_amd as L
+    import synth
+
+    prm, gws, rhos = [], [], []
+    for e in synth.c5_batch():
+        q = L.make_params(e["params"])
+        prm.append(dict(e["params"], rho_l=q.rho_l, rho_v=q.rho_v))
+        gws.append(e["gw"])
+        rhos.append(synth.droplet_rho(q.nx, q.ny, q.rho_l, q.rho_v, e["centres"], e["radii"],
+                                      seed=e["seed"]))
+    b = L.Batch(prm, gws, rhos, tune={"tile": 1, "schedule": 2})
+    b.step(20)
+    ws = b.adjoint_workspace(40, 10)
+    b.forward_ckpt(40, 10, ws)
+    b.loss()
+    b.backward(40, 10, ws)
+    torch.cuda.synchronize()
+    log(f"c5 adjoint probe: {len(prm)} lattices, 40-step gradient, K = 10")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -846,6 +872,9 @@ def main():
     ap.add_argument("--schedule-probe", action="store_true",
                     help="for counter runs: 20 steps of the 96-lattice ensemble graph-replayed, "
                          "then 20 persistent (64x8 tiles); prints no JSON")
+    ap.add_argument("--c5-adjoint-probe", action="store_true",
+                    help="for counter runs: a 40-step gradient of the 8 x 2048x1024 ensemble "
+                         "(checkpointed forward, loss, ensemble backward); prints no JSON")
     args = ap.parse_args()
     if args.cpu_baseline_only is not None:
         print(json.dumps(cpu_baseline(args.cpu_baseline_only)), flush=True)
@@ -872,6 +901,9 @@ def main():
         return
     if args.schedule_probe:
         schedule_probe(args)
+        return
+    if args.c5_adjoint_probe:
+        c5_adjoint_probe(args)
         return
     if args.workload == "c5":
         print(json.dumps(c5_run(args)), flush=True)
