@@ -237,8 +237,26 @@ def batched_speedup(args) -> dict:
             s.step(n)
 
     t_plain = _timed(plain)
-    same = all(np.array_equal(b.f(i), sims[i].f()) for i in (0, len(sims) // 2, len(sims) - 1))
+    picks = (0, len(sims) // 2, len(sims) - 1)
+    same = all(np.array_equal(b.f(i), sims[i].f()) for i in picks)
     bad = sum(1 for o in obs if o["nonfinite"])
+    del sims
+    # the same n steps as one persistent launch (captured in a hipGraph) with the fastest
+    # persistent candidate of the schedule table, checked bit for bit against the autotuned run
+    sched = schedule_table(prm, gws, rhos, 40)
+    pb = min((r for r in sched["candidates"] if r["schedule"] == "persistent"),
+             key=lambda r: r["ms_per_step"])
+    ptune = {"tile": pb["tile"], "schedule": 1, "waves_per_cu": pb["waves_per_cu"]}
+    bp = L.Batch(prm, gws, rhos, tune=ptune)
+    bp.step(2)
+    t_pers = _timed(lambda: bp.step(n), bp.stream)
+    same_p = all(np.array_equal(bp.f(i), b.f(i)) for i in picks)
+    persistent = {"tune": ptune, "grid": bp.tune()["grid"], "launches": 1,
+                  "seconds": round(t_pers, 3), "mlups": round(fluid * n / t_pers / 1e6, 1),
+                  "time_over_autotuned": round(t_pers / t_batch, 3),
+                  "bitwise_equal_to_autotuned": bool(same_p)}
+    del bp
+    log(f"bench: persistent {n} steps in one launch: {t_pers:.2f} s")
     # the ensemble's output: contact angle against G_w and the spurious current, per instance
     per_instance = [{"nx": e["params"]["nx"], "form": e["form"], "G_w": round(e["G_w"], 5),
                      "visc_ratio": e["visc_ratio"],
@@ -251,7 +269,7 @@ def batched_speedup(args) -> dict:
             "instances": len(prm), "fluid_nodes": fluid, "steps": n,
             "tune": {k: best[k] for k in ("tile", "schedule", "waves_per_cu")},
             "bitwise_equal_to_plain": bool(same), "nonfinite_instances": bad,
-            "schedules": schedule_table(prm, gws, rhos, 40),
+            "persistent": persistent, "schedules": sched,
             "per_instance": per_instance,
             "workload": "96 uneven lattices 128x64..512x256, 3 forms x G_w sweep x viscosity "
                         "ratios {1,5,15}"}
@@ -419,8 +437,25 @@ def c5_run(args) -> dict:
             "frac": round(back_bytes / t_back / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
             "bytes_per_node_step": ADJ_BYTES_PER_NODE_STEP - 144,
             "model": "recompute 144 + k_adj 280"}
+    # the forward as one persistent launch (captured in a hipGraph) with the fastest persistent
+    # candidate of the schedule table, from the initial state
+    pb = min((r for r in schedules["candidates"] if r["schedule"] == "persistent"),
+             key=lambda r: r["ms_per_step"])
+    ptune = {"tile": pb["tile"], "schedule": 1, "waves_per_cu": pb["waves_per_cu"]}
+    del sim
+    torch.cuda.empty_cache()
+    bp = L.Batch(prm, gws, rhos, tune=ptune)
+    bp.step(2)
+    NP = min(2000, N)
+    t_p = _timed(lambda: bp.step(NP), bp.stream)
+    persistent = {"tune": ptune, "grid": bp.tune()["grid"], "launches": 1, "steps": NP,
+                  "seconds": round(t_p, 3), "mlups": round(fluid * NP / t_p / 1e6, 1),
+                  "time_per_step_over_autotuned_forward":
+                      round((t_p / NP) / (t_fwd1 / max(1, N - NA)), 3)}
+    del bp
+    torch.cuda.empty_cache()
     return {"metric": "c5 large batched + adjoint", "workload": workload,
-            "forward": forward, "schedules": schedules,
+            "forward": forward, "persistent_forward": persistent, "schedules": schedules,
             "adjoint": {"steps": NA, "K": K, "batched": True, "instances": len(prm),
                         "seconds": round(t_adj, 3),
                         "mlups_forward_ckpt_plus_backward": round(2 * fluid * NA / t_adj / 1e6, 1),
