@@ -301,7 +301,10 @@ int lbm_backward(lbm_ctx *c, int64_t nsteps, int32_t K, void *d_ws, size_t bytes
  * lbm_batch_step is then a single hipGraphLaunch; each wait at a barrier gives up after
  * LBM_PERSISTENT_SPIN_LIMIT polls, an environment variable read when the ensemble is created
  * (default 4,194,304), and ends the whole run through an abort flag that the next observables call
- * reports as LBM_E_HIP). All run
+ * reports as LBM_E_HIP). The persistent grid fills the GPU: its workgroups must all be resident at
+ * once, so a persistent run must not share the GPU with other kernels that hold compute units for
+ * long (another persistent run included); if they do, its barriers time out and the run aborts as
+ * above rather than hang. All run
  * the same per-tile arithmetic as lbm_step, so every instance evolves bit-for-bit as it would
  * alone.
  */
