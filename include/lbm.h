@@ -251,11 +251,13 @@ int lbm_set_gw(lbm_ctx *c, const double *gw_host);
  *   1      two passes (psi pass, then the force-collide-stream pass reading psi through LDS);
  *   2      (default) two time steps per launch (the first step's populations stay in LDS;
  *          72 bytes per lattice update), an odd remainder step runs fused; output tile 64x8,
- *          or 64x4 when 64x8 tiles would give fewer than 512 workgroups;
+ *          or the wide 32x4 workgroups (schedule 39) on lattices of at most 384 such tiles;
  *   16+t   fused with tile shape t (0..7: 64x4, 64x8, 64x16, 128x4, and the overlapped
  *          62-column tiles with 4, 6, 8, 14 rows);
  *   32+t   two steps per launch with output tile t (0..5: 64x8, 64x4, 128x4, 64x16, 32x8,
- *          32x4).
+ *          32x4; 6, 7: 64x4 and 32x4 with one thread per first-step node and the halo ring on
+ *          threads of its own, 768 and 448 per workgroup, for lattices too small to fill the
+ *          GPU).
  * All schedules give bit-identical populations. A solid mask accepts every schedule but
  * 20..23 (LBM_E_INVAL). */
 int lbm_set_schedule(lbm_ctx *c, int32_t schedule);

@@ -568,9 +568,11 @@ static int create_impl(const lbm_params* p, const uint8_t* solid, const double* 
     c->step = 0;
     c->schedule = 2;  // two steps per launch (bit-identical to single steps, fastest)
     c->tile = 1;
-    // 64 x 8 output tiles, or 64 x 4 on lattices that would give fewer than 512 workgroups with
-    // those (twice the workgroups on the 256 compute units)
-    c->tile2 = ((p->nx + 63) / 64) * ((y_hi_of(p) - y_lo_of(p) + 8) / 8) < 512 ? 1 : 0;
+    // 64 x 8 output tiles, or the wide 32 x 4 workgroups on lattices of at most 384 such tiles
+    // (about 1.5 per compute unit), which a launch runs in one round of short chains. Measured
+    // per two-step launch (one MI355X; 64x8 / 64x4 / wide 32x4): 128x64 7.24 / 6.54 / 5.55 us,
+    // 256x128 7.35 / 6.74 / 5.78, 384x192 7.76 / 8.58 / 7.98, 512x256 8.39 / 9.44 / 10.56.
+    c->tile2 = ((p->nx + 31) / 32) * ((y_hi_of(p) - y_lo_of(p) + 4) / 4) <= 384 ? 7 : 0;
     c->adj_start = -1;
     c->adj_nsteps = 0;
     c->adj_K = 0;
@@ -665,7 +667,7 @@ int lbm_set_schedule(lbm_ctx* c, int32_t schedule) {
         c->tile = schedule - 16;
         return LBM_OK;
     }
-    if (schedule >= 32 && schedule < 38) {
+    if (schedule >= 32 && schedule < 40) {
         c->schedule = 2;
         c->tile2 = schedule - 32;
         return LBM_OK;

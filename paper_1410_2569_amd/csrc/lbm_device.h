@@ -705,6 +705,13 @@ __host__ __device__ constexpr int step2_threads(int TX, int TY, int GEO) {
 __host__ __device__ constexpr int step2_waves(int TX, int TY, int GEO) {
     return TX == 64 && (TY == 8 || TY == 4) ? 6 : 1;
 }
+// Threads of a "wide" two-step workgroup, for lattices too small to fill the chip: one R2 slot
+// per thread and the outer ring of R3 on waves of its own, so that no wave evaluates more than
+// one collision or psi value in a phase and the workgroup's chain of dependent phases is as short
+// as the tile allows (64 x 4: 768 threads, 32 x 4: 448).
+__host__ __device__ constexpr int step2_wide_threads(int TX, int TY) {
+    return ((((TX + 4) * (TY + 4) + 63) / 64 * 64 + 2 * (TX + 6) + 2 * (TY + 4)) + 63) / 64 * 64;
+}
 
 // LDS of step2_tile; with a solid mask (GEO_MASK) the link words of R2 are kept too.
 template <int TX, int TY, int GEO>

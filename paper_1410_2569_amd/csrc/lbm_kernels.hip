@@ -83,19 +83,20 @@ __global__ __launch_bounds__(64 * (TYI + 2)) void k_step_ov(KParams P,
     for (int a = 0; a < 9; ++a) (gout + a * P.plane)[i] = f[a];
 }
 
-// Two steps per launch over TX x TY output tiles (step2_tile); MID: the state after the first
-// step is written to gmid as well.
-template <int TX, int TY, int GEO, int EOS, bool MID>
-__global__
-__launch_bounds__(step2_threads(TX, TY, GEO), step2_waves(TX, TY, GEO)) void k_step2(
+// Two steps per launch over TX x TY output tiles (step2_tile) with NTH threads; MID: the state
+// after the first step is written to gmid as well.
+template <int TX, int TY, int GEO, int EOS, bool MID, int NTH = step2_threads(TX, TY, GEO)>
+__global__ __launch_bounds__(NTH, NTH == step2_threads(TX, TY, GEO)
+                                      ? step2_waves(TX, TY, GEO)
+                                      : (NTH / 64 + 3) / 4) void k_step2(
     KParams P, const double* __restrict__ gin, double* __restrict__ gout,
     const double* __restrict__ gw, double* __restrict__ gmid) {
     __shared__ Step2Lds<TX, TY, GEO> lds;
     const int ntx = (P.nx + TX - 1) / TX;
     const int nty = (P.y_hi - P.y_lo + TY) / TY;
     const int tile = xcd_tile(blockIdx.x, ntx * nty);
-    step2_tile_any<TX, TY, GEO, EOS, MID>(P, gin, gout, gw, (tile % ntx) * TX,
-                                          P.y_lo + (tile / ntx) * TY, lds, gmid);
+    step2_tile_any<TX, TY, GEO, EOS, MID, false, NTH>(P, gin, gout, gw, (tile % ntx) * TX,
+                                                      P.y_lo + (tile / ntx) * TY, lds, gmid);
 }
 
 // psi pass of the two-pass schedule; also writes the mirrored ghost rows. PRE: gin holds
@@ -296,7 +297,7 @@ static hipError_t launch_step_ov(const KParams& P, const double* gin, double* go
     });
 }
 
-template <int TX, int TY>
+template <int TX, int TY, bool WIDE = false>
 static hipError_t launch_step2_t(const KParams& P, const double* gin, double* gout,
                                  const double* gw, double* gmid, hipStream_t s) {
     const int ntx = (P.nx + TX - 1) / TX;
@@ -304,15 +305,15 @@ static hipError_t launch_step2_t(const KParams& P, const double* gin, double* go
     return dispatch(P, [&](auto geo, auto eos) {
         constexpr int G = decltype(geo)::value;
         constexpr int E = decltype(eos)::value;
+        constexpr int NT = WIDE ? step2_wide_threads(TX, TY) : step2_threads(TX, TY, G);
         if (!gmid) {
-            hipLaunchKernelGGL((k_step2<TX, TY, G, E, false>), dim3(ntx * nty),
-                               dim3(step2_threads(TX, TY, G)), 0, s, P, gin, gout, gw,
-                               (double*)nullptr);
+            hipLaunchKernelGGL((k_step2<TX, TY, G, E, false, NT>), dim3(ntx * nty), dim3(NT), 0,
+                               s, P, gin, gout, gw, (double*)nullptr);
             return hipGetLastError();
         }
         if constexpr (G == GEO_ROWS) {
-            hipLaunchKernelGGL((k_step2<TX, TY, G, E, true>), dim3(ntx * nty),
-                               dim3(step2_threads(TX, TY, G)), 0, s, P, gin, gout, gw, gmid);
+            hipLaunchKernelGGL((k_step2<TX, TY, G, E, true, NT>), dim3(ntx * nty), dim3(NT), 0,
+                               s, P, gin, gout, gw, gmid);
             return hipGetLastError();
         } else {
             return hipErrorInvalidValue;  // intermediate states: bounce-back or periodic rows only
@@ -321,7 +322,8 @@ static hipError_t launch_step2_t(const KParams& P, const double* gin, double* go
 }
 
 // Two steps in one launch; tile2 selects the output tile: 0 64x8, 1 64x4, 2 128x4, 3 64x16,
-// 4 32x8, 5 32x4 (the narrow tiles for lattices too small to fill the chip with the others).
+// 4 32x8, 5 32x4 (the narrow tiles for lattices too small to fill the chip with the others), 6
+// 64x4 and 7 32x4 with wide workgroups (step2_wide_threads).
 // gmid (optional): receives the state after the first step.
 hipError_t launch_step2(const KParams& P, int tile2, const double* gin, double* gout,
                         const double* gw, hipStream_t s, double* gmid) {
@@ -331,6 +333,8 @@ hipError_t launch_step2(const KParams& P, int tile2, const double* gin, double* 
         case 3: return launch_step2_t<64, 16>(P, gin, gout, gw, gmid, s);
         case 4: return launch_step2_t<32, 8>(P, gin, gout, gw, gmid, s);
         case 5: return launch_step2_t<32, 4>(P, gin, gout, gw, gmid, s);
+        case 6: return launch_step2_t<64, 4, true>(P, gin, gout, gw, gmid, s);
+        case 7: return launch_step2_t<32, 4, true>(P, gin, gout, gw, gmid, s);
         default: return launch_step2_t<64, 8>(P, gin, gout, gw, gmid, s);
     }
 }

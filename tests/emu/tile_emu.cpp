@@ -346,15 +346,15 @@ void check_equal(const Lattice& L, const std::vector<double>& a, const std::vect
 }
 
 // Two steps with the intermediate state written (the segment recomputation of the adjoint).
-template <int TX, int TY, int EOS>
+template <int TX, int TY, int EOS, int NTH = lbm::step2_threads(TX, TY, lbm::GEO_ROWS)>
 void step_two_mid(const Lattice& L, const double* gin, double* gout, double* gmid) {
     const KParams& P = L.P;
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.y_hi - P.y_lo + TY) / TY;
     auto* lds = new lbm::Step2Lds<TX, TY, lbm::GEO_ROWS>;
     run_workgroups(
-        lbm::step2_threads(TX, TY, lbm::GEO_ROWS), ntx * nty,
+        NTH, ntx * nty,
         [&](int t) {
-            lbm::step2_tile_any<TX, TY, lbm::GEO_ROWS, EOS, true>(
+            lbm::step2_tile_any<TX, TY, lbm::GEO_ROWS, EOS, true, false, NTH>(
                 P, gin, gout, L.gw.data(), (t % ntx) * TX, P.y_lo + (t / ntx) * TY, *lds, gmid);
         },
         [&] { std::memset((void*)lds, 0xFF, sizeof *lds); });
@@ -459,10 +459,14 @@ template <int EOS>
 void run_adjoint(const Lattice& L, const std::vector<double>& g0, const std::vector<double>& g1,
                  const std::vector<double>& g2) {
     // segment recomputation: two steps with the first written, against two fused steps
-    for (int shape = 0; shape < 2; ++shape) {
+    for (int shape = 0; shape < 3; ++shape) {
         std::vector<double> mid(g0.size(), kNaN), out(g0.size(), kNaN);
-        const char* name = shape ? "two-step 64x8 + mid" : "two-step 64x4 + mid";
-        if (shape) step_two_mid<64, 8, EOS>(L, g0.data(), out.data(), mid.data());
+        const char* name = shape == 2 ? "two-step 64x4 wide + mid"
+                                      : (shape ? "two-step 64x8 + mid" : "two-step 64x4 + mid");
+        if (shape == 2)
+            step_two_mid<64, 4, EOS, lbm::step2_wide_threads(64, 4)>(L, g0.data(), out.data(),
+                                                                    mid.data());
+        else if (shape) step_two_mid<64, 8, EOS>(L, g0.data(), out.data(), mid.data());
         else step_two_mid<64, 4, EOS>(L, g0.data(), out.data(), mid.data());
         check_output(L, mid, name);
         check_equal(L, mid, g1, name);
@@ -526,6 +530,8 @@ void run_case(const Lattice& L) {
     two(step_two<64, 16, GEO, EOS>, "two-step 64x16");
     two(step_two<32, 8, GEO, EOS>, "two-step 32x8");
     two(step_two<32, 4, GEO, EOS>, "two-step 32x4");
+    two(step_two<64, 4, GEO, EOS, lbm::step2_wide_threads(64, 4)>, "two-step 64x4, wide");
+    two(step_two<32, 4, GEO, EOS, lbm::step2_wide_threads(32, 4)>, "two-step 32x4, wide");
     observables<GEO, EOS>(L, ref);
     if constexpr (GEO == lbm::GEO_ROWS) run_adjoint<EOS>(L, g0, g1, ref);
 }

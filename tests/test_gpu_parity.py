@@ -142,7 +142,7 @@ def test_tile_shapes_and_schedules_bitwise(orc, gpu):
         else:
             assert np.array_equal(f, ref), f"tile shape {t} differs from tile shape 0"
     # two steps per launch, every output tile, odd step count (one single-step remainder)
-    for t in range(6):
+    for t in range(8):
         sim = gpu.Sim(pg, gw, rho0)
         sim.set_schedule(32 + t)
         sim.step(steps)
@@ -178,7 +178,7 @@ def test_interior_tiles_bitwise(orc, gpu, walls):
     ref = sim.f()
     f = orc.run(q, gw, orc.init_rest(q, rho0), steps)
     assert_f_close(q, ref, f, what=f"walls={walls}")
-    for t in range(6):
+    for t in range(8):
         sim = gpu.Sim(pg, gw, rho0)
         sim.set_schedule(32 + t)
         sim.step(steps)
@@ -200,7 +200,7 @@ def test_tiny_and_ragged_lattices_all_tiles(orc, gpu, nx, ny, walls):
     pg = dict(p, rho_l=q.rho_l, rho_v=q.rho_v)
     gw = rng.uniform(-0.1, 0.1, (2, nx))
     f = orc.run(q, gw, orc.init_rest(q, rho0), steps)
-    for sched in [0, 1, 2] + [16 + t for t in range(8)] + [32 + t for t in range(6)]:
+    for sched in [0, 1, 2] + [16 + t for t in range(8)] + [32 + t for t in range(8)]:
         sim = gpu.Sim(pg, gw, rho0)
         sim.set_schedule(sched)
         sim.step(steps)

@@ -46,7 +46,7 @@ def test_mask_parity_all_schedules(orc, gpu, form):
     steps = 301
     f = orc.run(q, gw, orc.init_rest(q, rho0), steps)
     ref = None
-    for sched in (16, 17, 18, 19, 1, 2, 32, 33, 34, 35, 36, 37):
+    for sched in (16, 17, 18, 19, 1, 2, 32, 33, 34, 35, 36, 37, 38, 39):
         sim = gpu.Sim(pg, gw, rho0)
         sim.set_schedule(sched)
         sim.step(steps)
@@ -113,7 +113,7 @@ def test_paper_rough_surface_full_size(orc, gpu):
     rel = rel_err(q, ref, f)
     print("rough full size", rel)
     assert rel <= RTOL
-    for sched in (2, 33, 34, 35, 36, 37):
+    for sched in (2, 33, 34, 35, 36, 37, 38, 39):
         s2 = gpu.Sim(pg, c["gw"], c["rho0"])
         s2.set_schedule(sched)
         s2.step(201)

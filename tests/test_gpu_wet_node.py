@@ -84,7 +84,7 @@ def test_wet_node_every_tile_bitwise(orc, gpu):
     q, pg, gw, rho0 = wet_case(orc, 200, 70, "rho", seed=13, gwv=0.1)
     steps = 151
     ref = None
-    for sched in [16 + t for t in range(8)] + [32 + t for t in range(6)] + [1]:
+    for sched in [16 + t for t in range(8)] + [32 + t for t in range(8)] + [1]:
         sim = gpu.Sim(pg, gw, rho0)
         sim.set_schedule(sched)
         sim.step(steps)
@@ -106,7 +106,7 @@ def test_wet_node_tiny_lattices(orc, gpu, nx, ny):
     gw = np.random.default_rng(nx * 7 + ny).uniform(-0.1, 0.1, (2, nx))
     pg = dict(p, rho_l=q.rho_l, rho_v=q.rho_v)
     f = orc.run(q, gw, orc.init_rest(q, rho0), 40)
-    for sched in [0, 1, 2] + [16 + t for t in range(8)] + [32 + t for t in range(6)]:
+    for sched in [0, 1, 2] + [16 + t for t in range(8)] + [32 + t for t in range(8)]:
         sim = gpu.Sim(pg, gw, rho0)
         sim.set_schedule(sched)
         sim.step(40)
