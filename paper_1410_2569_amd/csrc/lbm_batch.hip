@@ -213,6 +213,7 @@ k_batch_persistent(const InstDesc* __restrict__ inst, const int* __restrict__ ti
             T = next[slot];
             slot ^= 1;
         }
+        if (k + 1 == npairs) break;  // the launch's end orders the last pass before what follows
         if (k == 0) {
             if (!grid_barrier(bar, (unsigned long long)G, flag, spin_limit, &verdict)) return;
             if (threadIdx.x == 0) {
