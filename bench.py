@@ -181,7 +181,7 @@ def schedule_table(prm, gws, rhos, steps: int) -> dict:
     names = {0: "per-step", 1: "persistent", 2: "two-step"}
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     rows = []
-    for tile in range(4):
+    for tile in range(5):
         for sched in (0, 2, 1):
             tunes = [{"tile": tile, "schedule": sched, "waves_per_cu": 0}]
             for t in tunes:
@@ -586,8 +586,8 @@ def rough_run(args) -> dict:
     cs = cs * max(1, args.rough_replicas)
     args_b = ([c["params"] for c in cs], [c["gw"] for c in cs], [c["rho0"] for c in cs])
     best, best_t = None, math.inf
-    for tune in [{"tile": t, "schedule": 0} for t in range(4)] + \
-            [{"tile": t, "schedule": 2} for t in range(4)]:
+    for tune in [{"tile": t, "schedule": 0} for t in range(5)] + \
+            [{"tile": t, "schedule": 2} for t in range(5)]:
         b = L.Batch(*args_b, tune=tune, solids=[c["mask"] for c in cs])
         b.step(20)
         t = _timed(lambda: b.step(400), b.stream)

@@ -311,7 +311,9 @@ int lbm_backward(lbm_ctx *c, int64_t nsteps, int32_t K, void *d_ws, size_t bytes
  * alone.
  */
 typedef struct {
-    int32_t tile;         /* tile shape 0..3: 64x4, 64x8, 64x16, 128x4 */
+    int32_t tile;         /* tile shape 0..4: 64x4, 64x8, 64x16, 128x4, 32x4 (the last's
+                             two-step workgroups have one thread per first-step node: for
+                             ensembles too small to fill the GPU) */
     int32_t reserved;     /* must be 0 */
     int32_t waves_per_cu; /* persistent schedule: workgroups per compute unit (0 = occupancy) */
     int32_t schedule;     /* 0 per-step launches, 1 persistent, 2 two steps per launch (output

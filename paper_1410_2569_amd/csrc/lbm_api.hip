@@ -1181,7 +1181,7 @@ struct BatchLayout {
 
 bool batch_layout(const lbm_params* p, int32_t count, int tile, BatchLayout* B) {
     int TX = 64, TY = 4;
-    lbm::tile_shape(tile, &TX, &TY);
+    lbm::batch_tile_shape(tile, &TX, &TY);
     size_t o = 0;
     B->off_desc = o;
     o += align_up((size_t)count * sizeof(lbm::InstDesc), kAlign);
@@ -1219,7 +1219,7 @@ int batch_fail(lbm_batch* b, int code, const std::string& m) {
 
 int validate_tune(const lbm_tune* t) {
     if (!t) return LBM_OK;
-    if (t->tile < 0 || t->tile > 3 || t->schedule < 0 || t->schedule > 2 || t->waves_per_cu < 0 ||
+    if (t->tile < 0 || t->tile > 4 || t->schedule < 0 || t->schedule > 2 || t->waves_per_cu < 0 ||
         t->reserved != 0)
         return LBM_E_INVAL;
     return LBM_OK;
@@ -1861,7 +1861,7 @@ int lbm_autotune(const lbm_params* p, int32_t count, const double* const* gw_hos
     // two sweeps over the candidates: the first also brings the device to its working clocks,
     // and each candidate counts with its faster run
     for (int sweep = 0; sweep < 2; ++sweep) {
-        for (int tile = 0; tile < 4; ++tile) {
+        for (int tile = 0; tile < 5; ++tile) {
             for (int sched = 0; sched < 3; ++sched) {
                 for (int half = 0; half < (sched == 1 ? 2 : 1); ++half) {
                     lbm_tune t{tile, 0, 0, sched};

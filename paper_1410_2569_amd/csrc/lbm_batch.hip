@@ -48,18 +48,20 @@ __global__ __launch_bounds__(TX* TY) void k_batch_step(const InstDesc* __restric
     step_tile<TX, TY, true, GEO, EOS>(D->P, D->g[cur], D->g[cur ^ 1], nullptr, D->gw, x0, y0, sp);
 }
 
-// Two steps per launch over the work-list (the tiles are the output tiles of step2_tile).
-template <int TX, int TY, int GEO, int EOS>
-__global__
-__launch_bounds__(step2_threads(TX, TY, GEO), step2_waves(TX, TY, GEO)) void k_batch_step2(
+// Two steps per launch over the work-list (the tiles are the output tiles of step2_tile), NTH
+// threads per workgroup.
+template <int TX, int TY, int GEO, int EOS, int NTH = step2_threads(TX, TY, GEO)>
+__global__ __launch_bounds__(NTH, NTH == step2_threads(TX, TY, GEO) ? step2_waves(TX, TY, GEO)
+                                                                    : (NTH / 64 + 3) / 4) void
+k_batch_step2(
     const InstDesc* __restrict__ inst, const int* __restrict__ tile_inst, int ntiles, int cur) {
     __shared__ Step2Lds<TX, TY, GEO> lds;
     const int t = xcd_tile(blockIdx.x, ntiles);
     const InstDesc* D = inst + tile_inst[t];
     int x0, y0;
     batch_tile_origin(D, t, TX, TY, x0, y0);
-    step2_tile_any<TX, TY, GEO, EOS>(D->P, gptr(D->g[cur]), gptr(D->g[cur ^ 1]), gptr(D->gw), x0,
-                                     y0, lds);
+    step2_tile_any<TX, TY, GEO, EOS, false, false, NTH>(D->P, gptr(D->g[cur]), gptr(D->g[cur ^ 1]),
+                                                        gptr(D->gw), x0, y0, lds);
 }
 
 // Bounded wait (thread 0 of a workgroup) until *ctr >= target. Returns 0 when the run was
@@ -79,9 +81,15 @@ __device__ __forceinline__ int spin_until(unsigned long long* ctr, unsigned long
 
 // Grid-wide barrier number `target / gridDim.x` on a 64-bit arrival counter: every workgroup
 // releases and acquires at agent scope itself. Returns false when the run was aborted.
+// Every wave waits for its own global stores of the pass to reach the L2 before the workgroup
+// barrier: the barrier alone orders them for the workgroup's waves (which share the compute
+// unit's write-through L1), not for a release that thread 0 then makes for all of them.
+__device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 __device__ __forceinline__ bool grid_barrier(unsigned long long* bar, unsigned long long target,
                                              int* flag, int spin_limit, int* verdict) {
-    __syncthreads();  // every wave's stores of this pass have completed
+    stores_done();
+    __syncthreads();  // every wave's stores of this pass have reached the L2
     if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -103,19 +111,19 @@ __device__ __forceinline__ int xcc_id() {
 }
 
 // Grid barrier number k (k >= 1) through one leader per XCD. The workgroups of an XCD share its
-// L2, so one write-back and one invalidation of that L2 serve all of them: each workgroup
-// arrives at its XCD's counter once its stores have reached the L2; the last to arrive (the
-// leader) writes the L2 back (agent-scope release), arrives at the global counter, waits for
-// every XCD's leader, invalidates the L2 (agent-scope acquire) and opens its XCD's gate; the
-// others wait at the gate and then invalidate only their compute unit's L1, which may hold
-// lines that other compute units have since rewritten. nx: workgroups on this XCD; ng: XCDs
-// with workgroups; g0: the global count after the first (grid_barrier) pass. A per-workgroup
-// release and acquire (grid_barrier) cost 28 us per pass on 512 workgroups, most of it in 512
-// serialised L2 write-backs and invalidations.
+// L2, so one write-back of that L2 serves all of them: each workgroup arrives at its XCD's
+// counter once its stores have reached the L2; the last to arrive (the leader) writes the L2
+// back (agent-scope release), arrives at the global counter, waits for every XCD's leader,
+// acquires and opens its XCD's gate; the others wait at the gate and then acquire at agent
+// scope themselves (their compute unit's L1 may hold lines that other compute units have since
+// rewritten). nx: workgroups on this XCD; ng: XCDs with workgroups; g0: the global count after
+// the first (grid_barrier) pass. A per-workgroup release and acquire (grid_barrier) cost 28 us
+// per pass on 512 workgroups, most of it in serialised L2 write-backs and invalidations.
 __device__ __forceinline__ bool xcd_barrier(unsigned long long* bar, int xcc, unsigned long long nx,
                                             unsigned long long ng, unsigned long long g0,
                                             unsigned long long k, int* flag, int spin_limit,
                                             int* verdict) {
+    stores_done();
     __syncthreads();  // every wave's stores of this pass have reached the L2
     if (threadIdx.x == 0) {
         unsigned long long* xarr = bar + kXcdArrSlot + xcc;
@@ -133,7 +141,9 @@ __device__ __forceinline__ bool xcd_barrier(unsigned long long* bar, int xcc, un
             __hip_atomic_store(xgate, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             ok = spin_until(xgate, k, flag, spin_limit);
-            asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+            // agent-scope acquire: a workgroup-scope invalidation does not reach the compute
+            // unit's L1 outside thread-group-split mode, and stale L1 lines were read here
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         *verdict = ok;
     }
@@ -157,11 +167,16 @@ __device__ __forceinline__ bool xcd_barrier(unsigned long long* bar, int xcc, un
 // Threads of a persistent workgroup: those of the two-step launches, except 512 for 64 x 8 tiles:
 // two workgroups per CU then leave 128 VGPRs per thread (4 waves per SIMD) where 768 threads leave
 // 80, which the loop state around the tile function overflows.
+// The 32 x 4 tile runs its wide workgroup (step2_wide_threads) in every schedule.
 __host__ __device__ constexpr int persist_threads(int TX, int TY, int GEO) {
-    return TX == 64 && TY == 8 ? 512 : step2_threads(TX, TY, GEO);
+    return TX == 64 && TY == 8 ? 512
+                               : (TX == 32 && TY == 4 ? step2_wide_threads(32, 4)
+                                                      : step2_threads(TX, TY, GEO));
 }
 __host__ __device__ constexpr int persist_waves(int TX, int TY, int GEO) {
-    return TX == 64 && TY == 8 ? 4 : step2_waves(TX, TY, GEO);
+    return TX == 64 && TY == 8 ? 4
+                               : (TX == 32 && TY == 4 ? (step2_wide_threads(32, 4) / 64 + 3) / 4
+                                                      : step2_waves(TX, TY, GEO));
 }
 
 template <int TX, int TY, int GEO, int EOS>
@@ -396,17 +411,28 @@ static hipError_t launch_batch2_t(int geo, int eos, const InstDesc* inst, const 
                                   int ntiles, int cur, hipStream_t s) {
     return dispatch(geo, eos, [&](auto g, auto e) {
         constexpr int G = decltype(g)::value;
-        hipLaunchKernelGGL((k_batch_step2<TX, TY, G, decltype(e)::value>), dim3(ntiles),
-                           dim3(step2_threads(TX, TY, G)), 0, s, inst, tile_inst, ntiles, cur);
+        constexpr int NT = TX == 32 && TY == 4 ? step2_wide_threads(32, 4)
+                                               : step2_threads(TX, TY, G);
+        hipLaunchKernelGGL((k_batch_step2<TX, TY, G, decltype(e)::value, NT>), dim3(ntiles),
+                           dim3(NT), 0, s, inst, tile_inst, ntiles, cur);
         return hipGetLastError();
     });
 }
 
-// Two steps per launch (schedule 2) with the output tiles of the work-list's tile shape (0 64x4,
-// 1 64x8, 2 64x16, 3 128x4).
+// Tile shapes of an ensemble's work-list: 0 64x4, 1 64x8, 2 64x16, 3 128x4, 4 32x4 (whose
+// two-step workgroups are the wide ones: for ensembles too small to fill the chip).
+void batch_tile_shape(int tile, int* tx, int* ty) {
+    static const int k[5][2] = {{64, 4}, {64, 8}, {64, 16}, {128, 4}, {32, 4}};
+    if (tile < 0 || tile > 4) tile = 0;
+    *tx = k[tile][0];
+    *ty = k[tile][1];
+}
+
+// Two steps per launch (schedule 2) with the output tiles of the work-list's tile shape.
 hipError_t launch_batch_step2(int tile, int geo, int eos, const InstDesc* inst,
                               const int* tile_inst, int ntiles, int cur, hipStream_t s) {
     switch (tile) {
+        case 4: return launch_batch2_t<32, 4>(geo, eos, inst, tile_inst, ntiles, cur, s);
         case 1: return launch_batch2_t<64, 8>(geo, eos, inst, tile_inst, ntiles, cur, s);
         case 2: return launch_batch2_t<64, 16>(geo, eos, inst, tile_inst, ntiles, cur, s);
         case 3: return launch_batch2_t<128, 4>(geo, eos, inst, tile_inst, ntiles, cur, s);
@@ -417,6 +443,7 @@ hipError_t launch_batch_step2(int tile, int geo, int eos, const InstDesc* inst,
 hipError_t launch_batch_step(int tile, int geo, int eos, const InstDesc* inst,
                              const int* tile_inst, int ntiles, int cur, hipStream_t s) {
     switch (tile) {
+        case 4: return launch_batch_t<32, 4>(geo, eos, inst, tile_inst, ntiles, cur, s);
         case 1: return launch_batch_t<64, 8>(geo, eos, inst, tile_inst, ntiles, cur, s);
         case 2: return launch_batch_t<64, 16>(geo, eos, inst, tile_inst, ntiles, cur, s);
         case 3: return launch_batch_t<128, 4>(geo, eos, inst, tile_inst, ntiles, cur, s);
@@ -429,6 +456,8 @@ hipError_t launch_batch_persistent(int tile, int geo, int eos, int grid, const I
                                    unsigned long long* bar, int* flag, int spin_limit,
                                    hipStream_t s) {
     switch (tile) {
+        case 4: return launch_persist_t<32, 4>(geo, eos, grid, inst, tile_inst, ntiles, npairs,
+                                               cur, bar, flag, spin_limit, s);
         case 1: return launch_persist_t<64, 8>(geo, eos, grid, inst, tile_inst, ntiles, npairs,
                                                cur, bar, flag, spin_limit, s);
         case 2: return launch_persist_t<64, 16>(geo, eos, grid, inst, tile_inst, ntiles, npairs,
@@ -442,6 +471,7 @@ hipError_t launch_batch_persistent(int tile, int geo, int eos, int grid, const I
 
 int batch_persistent_occupancy(int tile) {
     switch (tile) {
+        case 4: return occupancy_t<32, 4>();
         case 1: return occupancy_t<64, 8>();
         case 2: return occupancy_t<64, 16>();
         case 3: return occupancy_t<128, 4>();

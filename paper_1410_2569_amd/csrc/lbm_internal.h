@@ -40,6 +40,8 @@ struct AdjInst {
 
 int n_tiles();
 void tile_shape(int tile, int* tx, int* ty);
+// Tile shape of an ensemble's work-list (tune.tile 0..4).
+void batch_tile_shape(int tile, int* tx, int* ty);
 hipError_t launch_step(const KParams& P, int schedule, int tile, const double* gin, double* gout,
                        double* psi, const double* gw, hipStream_t s);
 // gmid (optional, bounce-back or periodic rows): also receives the state after the first step

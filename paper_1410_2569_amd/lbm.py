@@ -624,7 +624,7 @@ def autotune(params_list, gw_list, rho0_list, steps=200, device="cuda"):
     gwp = (_dp * n)(*[_dptr(g) for g in gws])
     rp = (_dp * n)(*[_dptr(r) for r in rhos])
     need = 0
-    for tile in range(4):
+    for tile in range(5):
         b = C.c_size_t()
         t = Tune(tile, 0, 0, 0)
         check(lib().lbm_batch_workspace_size(arr, n, C.byref(t), C.byref(b)))

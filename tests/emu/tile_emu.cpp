@@ -295,9 +295,8 @@ std::vector<double> make_state(const Lattice& L) {
     return g;
 }
 
-template <int GEO, int EOS>
+template <int GEO, int EOS, int TX = 64, int TY = 4>
 void step_fused(const Lattice& L, const double* gin, double* gout) {
-    constexpr int TX = 64, TY = 4;
     const KParams& P = L.P;
     const int ntx = (P.nx + TX - 1) / TX, nty = (P.y_hi - P.y_lo + TY) / TY;
     std::vector<double> sp((TY + 2) * (TX + 2));
@@ -517,6 +516,12 @@ void run_case(const Lattice& L) {
     check_output(L, g1, "fused step 1");
     step_fused<GEO, EOS>(L, g1.data(), ref.data());
     check_output(L, ref, "fused step 2");
+    {  // the fused step on 32 x 4 tiles (the odd step of an ensemble on that work-list)
+        std::vector<double> g1n(g0.size(), kNaN);
+        step_fused<GEO, EOS, 32, 4>(L, g0.data(), g1n.data());
+        check_output(L, g1n, "fused step 32x4");
+        check_equal(L, g1n, g1, "fused step 32x4");
+    }
     auto two = [&](auto fn, const char* name) {
         std::vector<double> out(g0.size(), kNaN);
         fn(L, g0.data(), out.data());

@@ -112,6 +112,11 @@ int main() {
     EXPECT(lbm_batch_workspace_size(ens, 3, &t, &n) == LBM_OK);
     lbm_tune tb{7, 0, 0, 2};
     EXPECT(lbm_batch_workspace_size(ens, 3, &tb, &n) == LBM_E_INVAL);
+    lbm_tune tw{4, 0, 0, 2};  // the 32 x 4 tile
+    EXPECT(lbm_batch_workspace_size(ens, 3, &tw, &n) == LBM_OK);
+    tw.tile = 5;
+    EXPECT(lbm_batch_workspace_size(ens, 3, &tw, &n) == LBM_E_INVAL);
+    EXPECT(lbm_batch_workspace_size(ens, 3, &t, &n) == LBM_OK);
     lbm_params mixed[2] = {good(64, 32), good(64, 32, LBM_WALLS_MASK)};
     EXPECT(lbm_batch_workspace_size(mixed, 2, nullptr, &n) == LBM_E_INVAL);
     lbm_batch* b = nullptr;

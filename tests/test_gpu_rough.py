@@ -151,7 +151,7 @@ def test_mask_rejected_where_unsupported(orc, gpu):
 
 
 @pytest.mark.parametrize("tile,schedule", [(0, 0), (1, 0), (2, 0), (3, 0), (1, 1), (0, 2), (1, 2),
-                                           (2, 2), (3, 2)])
+                                           (2, 2), (3, 2), (4, 1), (4, 2)])
 def test_masked_ensemble_bitwise_equals_lone_runs(orc, gpu, tile, schedule):
     """Pillared lattices of several sizes and forms as one ensemble: every instance carries the
     same bits as the lattice stepped alone, and the per-instance contact planes feed the fits."""

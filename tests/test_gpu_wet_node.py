@@ -127,8 +127,8 @@ def test_wet_node_save_load_carries_wall_force(orc, gpu):
     assert_close(q, a, orc.run(q, gw, orc.init_rest(q, rho0), 121), "wet save/load")
 
 
-@pytest.mark.parametrize("schedule", [0, 1, 2])
-def test_batch_mixing_wall_schemes(orc, gpu, schedule):
+@pytest.mark.parametrize("schedule,tile", [(0, 0), (1, 1), (2, 1), (1, 4), (2, 4)])
+def test_batch_mixing_wall_schemes(orc, gpu, schedule, tile):
     """An ensemble with both wall schemes: each instance bit-identical to its lone run (per-step
     launches, the persistent launch, two steps per launch)."""
     cases = []
@@ -142,7 +142,6 @@ def test_batch_mixing_wall_schemes(orc, gpu, schedule):
         g = synth.gw_smooth(nx, {"rho": 0.05, "psi": -0.02, "modpsi": 0.1}[form], 0.02, seed=i)
         cases.append((dict(p, rho_l=q.rho_l, rho_v=q.rho_v), g, rho0))
     steps = 131
-    tile = 0 if schedule == 0 else 1
     b = gpu.Batch([c[0] for c in cases], [c[1] for c in cases], [c[2] for c in cases],
                   tune={"tile": tile, "schedule": schedule})
     b.step(steps)
