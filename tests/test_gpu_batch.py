@@ -233,3 +233,21 @@ def test_persistent_barrier_timeout_aborts_cleanly(orc, gpu, monkeypatch):
     for i in range(len(cases)):
         assert np.array_equal(b.f(i), ref[i])
 
+
+
+@pytest.mark.parametrize("tile", [4, 0])
+def test_persistent_many_passes_small_tiles(orc, gpu, tile):
+    """Small tiles of small lattices, whose data a compute unit's L1 keeps from one pass to the
+    next: 1,000 steps (500 passes, each barrier after the first through the per-XCD leaders) of
+    the persistent schedule against graph-replayed two-step launches, bit for bit. A barrier
+    whose waiting workgroups do not invalidate their L1 reads stale lines here."""
+    cases = ensemble(orc)
+    args = ([c[0] for c in cases], [c[1] for c in cases], [c[2] for c in cases])
+    out = []
+    for schedule in (2, 1):
+        b = gpu.Batch(*args, tune={"tile": tile, "schedule": schedule})
+        b.step(1000)
+        out.append([b.f(i) for i in range(len(cases))])
+        del b
+    for i in range(len(cases)):
+        assert np.array_equal(out[0][i], out[1][i]), f"instance {i} differs (tile {tile})"
