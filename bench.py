@@ -918,9 +918,9 @@ def main():
     if args.steps % 2:
         args.steps += 1  # two steps per launch: keep the timed region a whole number of launches
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
-        log("bench.py: only --gpus 1 is supported (single-GPU build)")
+        log("bench.py: only --gpus 1 is supported (one GPU per process, no collectives)")
         sys.exit(2)
 
     import torch

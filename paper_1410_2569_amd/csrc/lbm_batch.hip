@@ -87,7 +87,7 @@ __device__ __forceinline__ int spin_until(unsigned long long* ctr, unsigned long
 __device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 __device__ __forceinline__ bool grid_barrier(unsigned long long* bar, unsigned long long target,
-                                             int* flag, int spin_limit, int* verdict) {
+                                             int* flag, int spin_limit, int* go_on) {
     stores_done();
     __syncthreads();  // every wave's stores of this pass have reached the L2
     if (threadIdx.x == 0) {
@@ -95,12 +95,12 @@ __device__ __forceinline__ bool grid_barrier(unsigned long long* bar, unsigned l
         __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int ok = spin_until(bar, target, flag, spin_limit);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        *verdict = ok;
+        *go_on = ok;
     }
     // The other threads acquire through the workgroup barrier: thread 0's agent-scope acquire
     // happens before it, and it invalidated the caches that the workgroup's waves share.
     __syncthreads();
-    return *verdict != 0;
+    return *go_on != 0;
 }
 
 // The XCD that runs the calling wave (the hardware's own register, 0 ... 7 on this device).
@@ -122,7 +122,7 @@ __device__ __forceinline__ int xcc_id() {
 __device__ __forceinline__ bool xcd_barrier(unsigned long long* bar, int xcc, unsigned long long nx,
                                             unsigned long long ng, unsigned long long g0,
                                             unsigned long long k, int* flag, int spin_limit,
-                                            int* verdict) {
+                                            int* go_on) {
     stores_done();
     __syncthreads();  // every wave's stores of this pass have reached the L2
     if (threadIdx.x == 0) {
@@ -145,10 +145,10 @@ __device__ __forceinline__ bool xcd_barrier(unsigned long long* bar, int xcc, un
             // unit's L1 outside thread-group-split mode, and stale L1 lines were read here
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        *verdict = ok;
+        *go_on = ok;
     }
     __syncthreads();
-    return *verdict != 0;
+    return *go_on != 0;
 }
 
 // npairs two-step passes over the work-list in one launch (the tiles are the output tiles of
@@ -185,7 +185,7 @@ k_batch_persistent(const InstDesc* __restrict__ inst, const int* __restrict__ ti
                    int ntiles, int npairs, int cur0, unsigned long long* bar, int* flag,
                    int spin_limit) {
     __shared__ Step2Lds<TX, TY, GEO> lds;
-    __shared__ int verdict;
+    __shared__ int go_on;
     __shared__ unsigned long long next[2];
     const int G = gridDim.x;
     // this XCD's share of the work-list: [c0, c0 + S)
@@ -230,7 +230,7 @@ k_batch_persistent(const InstDesc* __restrict__ inst, const int* __restrict__ ti
         }
         if (k + 1 == npairs) break;  // the launch's end orders the last pass before what follows
         if (k == 0) {
-            if (!grid_barrier(bar, (unsigned long long)G, flag, spin_limit, &verdict)) return;
+            if (!grid_barrier(bar, (unsigned long long)G, flag, spin_limit, &go_on)) return;
             if (threadIdx.x == 0) {
                 unsigned long long n = 0, c = 0;
                 for (int x = 0; x < kXcds; ++x) {
@@ -241,16 +241,16 @@ k_batch_persistent(const InstDesc* __restrict__ inst, const int* __restrict__ ti
                 }
                 next[1] = n;
                 // an XCD id beyond the control block raised the flag at registration
-                verdict = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+                go_on = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
             }
             __syncthreads();
             nx = next[0];
             ng = next[1];
-            const bool go = verdict != 0;
+            const bool go = go_on != 0;
             __syncthreads();  // next[] serves the tickets again
             if (!go) return;
         } else if (!xcd_barrier(bar, xcc, nx, ng, (unsigned long long)G, (unsigned long long)k,
-                                flag, spin_limit, &verdict)) {
+                                flag, spin_limit, &go_on)) {
             return;
         }
         cur0 ^= 1;
