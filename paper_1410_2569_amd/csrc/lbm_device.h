@@ -221,6 +221,13 @@ __device__ __forceinline__ double psi_at(const KParams& P, const double* __restr
                                   f[8]);
 }
 
+// The pull behind lattice slot (gx, gy) (slot_source; IN: a fluid node reached without wrap)
+// into f, without evaluating psi. Returns false when the slot's psi is 0 (nothing pulled);
+// fluid: the slot is a fluid node of the lattice (not a ghost row).
+template <int GEO, bool IN>
+__device__ __forceinline__ bool pull_slot(const KParams& P, const double* __restrict__ g, int gx,
+                                          int gy, double f[9], bool& fluid);
+
 __device__ __forceinline__ double sum9(const double f[9]) {
 #pragma clang fp contract(off)
     return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
@@ -663,6 +670,22 @@ __device__ __forceinline__ void pull9_in(const KParams& P, const double* __restr
     f[8] = (g + 8 * pl)[rp - 1];
 }
 
+template <int GEO, bool IN>
+__device__ __forceinline__ bool pull_slot(const KParams& P, const double* __restrict__ g, int gx,
+                                          int gy, double f[9], bool& fluid) {
+    if constexpr (IN) {
+        pull9_in(P, g, gx, gy, f);
+        fluid = true;
+        return true;
+    } else {
+        int sx, sy;
+        const bool v = slot_source(P, gx, gy, sx, sy);
+        fluid = v && (!P.walls || (gy >= 1 && gy <= P.ny - 2));
+        if (v) pull9<GEO>(P, g, sx, sy, f);
+        return v;
+    }
+}
+
 // pull9_lds for a node away from the wall rows.
 __device__ __forceinline__ void pull9_lds_in(const double* g1, int plane, int W, int l,
                                              double f[9]) {
@@ -760,68 +783,112 @@ __device__ __forceinline__ void step2_tile(const KParams& P, const double* __res
     static_assert(NR <= 3, "at most three R2 slots per thread");
     double fk[NR][9], rk[NR];
     bool ok[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int s = tid + r * NT;
-        ok[r] = false;
-        rk[r] = 1.0;
-        if (s >= PL) continue;
-        const int lx = s % W2, ly = s / W2;
-        if constexpr (IN) {
-            pull9_in(P, gin, x0 - 2 + lx, y0 - 2 + ly, fk[r]);
-            rk[r] = sum9(fk[r]);
-            ps1[(ly + 1) * W3 + lx + 1] = psi_of_rho<EOS>(P, rk[r]);
-            ok[r] = true;
-            continue;
-        }
-        if constexpr (MK) {
-            const int gx = wrapx(x0 - 2 + lx, P.nx), gy = wrapx(y0 - 2 + ly, P.ny);
-            const unsigned lk = P.links[(unsigned)gy * P.pitch + gx];
-            L.lk[s] = (unsigned short)lk;
-            double ps = 0.0;  // solid node
-            if (!(lk & 1u)) {
-                pull9_mask(P, gin, gx, gy, lk, fk[r]);
-                rk[r] = sum9(fk[r]);
-                ps = psi_of_rho<EOS>(P, rk[r]);
-                ok[r] = true;
-            }
-            ps1[(ly + 1) * W3 + lx + 1] = ps;
-            continue;
-        }
-        double ps = 0.0;
-        int gy = y0 - 2 + ly;
-        bool fluid;
-        if (P.walls) fluid = gy >= 1 && gy <= P.ny - 2;
-        else { gy = wrapx(gy, P.ny); fluid = true; }
-        if (fluid) {
-            pull9<GEO>(P, gin, wrapx(x0 - 2 + lx, P.nx), gy, fk[r]);
-            rk[r] = sum9(fk[r]);
-            ps = psi_of_rho<EOS>(P, rk[r]);
-            ok[r] = true;
-        } else {
-            ps = psi_at<GEO, EOS>(P, gin, x0 - 2 + lx, y0 - 2 + ly);  // solid row: ghost or 0
-        }
-        ps1[(ly + 1) * W3 + lx + 1] = ps;
-    }
     // The ring of R3 outside R2 goes to the waves after those with a slot in the last pass of R2,
     // when they are enough, so that no wave evaluates more than NR psi values.
     constexpr int NRING = 2 * W3 + 2 * H2;
     constexpr int LAST = PL - (NR - 1) * NT;  // threads with a slot in the last pass
     constexpr int RB = (LAST + 63) / 64 * 64;
     constexpr int R0 = RB + NRING <= NT ? RB : 0;
-    for (int h = tid - R0; h < NRING; h += NT) {
-        if (h < 0) continue;
-        int lx, ly;  // R3-local coordinates
+    auto ring_pos = [](int h, int& lx, int& ly) {  // R3-local coordinates of ring slot h
         if (h < W3) { lx = h; ly = 0; }
         else if (h < 2 * W3) { lx = h - W3; ly = H3 - 1; }
         else if (h < 2 * W3 + H2) { lx = 0; ly = h - 2 * W3 + 1; }
         else { lx = W3 - 1; ly = h - 2 * W3 - H2 + 1; }
-        if constexpr (IN) {
-            double f[9];
-            pull9_in(P, gin, x0 - 3 + lx, y0 - 3 + ly, f);
-            ps1[ly * W3 + lx] = psi_of_rho<EOS>(P, sum9(f));
-        } else {
-            ps1[ly * W3 + lx] = psi_at<GEO, EOS>(P, gin, x0 - 3 + lx, y0 - 3 + ly);
+    };
+    if constexpr (!MK && NR == 2 && R0 > 0 && NT < step2_threads(TX, TY, GEO)) {
+        // Two passes over R2 and the ring past the second one's threads: a thread holds its first
+        // R2 slot and at most one more pull, its second slot or a ring slot, and issues both
+        // pulls before it evaluates either psi (one round trip to memory instead of two; the
+        // values are those of the loop below). Only for workgroups smaller than the tile's
+        // default (the persistent 64 x 8 workgroup of 512 threads, 16 waves per compute unit:
+        // 0.337 -> 0.326 ms per step on 8 x 2048x1024); with the default 768 threads the other
+        // workgroup of the compute unit hides the second round trip, and issuing both measured
+        // 1-3% slower.
+        const int s1 = tid + NT, h = tid - R0;
+        int l0, l1 = -1;
+        bool v0, v1 = false;
+        rk[0] = rk[1] = 1.0;
+        {
+            const int lx = tid % W2, ly = tid / W2;
+            l0 = (ly + 1) * W3 + lx + 1;
+            v0 = pull_slot<GEO, IN>(P, gin, x0 - 2 + lx, y0 - 2 + ly, fk[0], ok[0]);
+        }
+        ok[1] = false;
+        if (s1 < PL) {
+            const int lx = s1 % W2, ly = s1 / W2;
+            l1 = (ly + 1) * W3 + lx + 1;
+            v1 = pull_slot<GEO, IN>(P, gin, x0 - 2 + lx, y0 - 2 + ly, fk[1], ok[1]);
+        } else if (h >= 0 && h < NRING) {
+            int lx, ly;
+            ring_pos(h, lx, ly);
+            l1 = ly * W3 + lx;
+            bool fluid;
+            v1 = pull_slot<GEO, IN>(P, gin, x0 - 3 + lx, y0 - 3 + ly, fk[1], fluid);
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int l = r ? l1 : l0;
+            if (l < 0) continue;
+            const bool v = r ? v1 : v0;
+            const double rho = v ? sum9(fk[r]) : 1.0;
+            rk[r] = ok[r] ? rho : 1.0;
+            ps1[l] = v ? psi_of_rho<EOS>(P, rho) : 0.0;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int s = tid + r * NT;
+            ok[r] = false;
+            rk[r] = 1.0;
+            if (s >= PL) continue;
+            const int lx = s % W2, ly = s / W2;
+            if constexpr (IN) {
+                pull9_in(P, gin, x0 - 2 + lx, y0 - 2 + ly, fk[r]);
+                rk[r] = sum9(fk[r]);
+                ps1[(ly + 1) * W3 + lx + 1] = psi_of_rho<EOS>(P, rk[r]);
+                ok[r] = true;
+                continue;
+            }
+            if constexpr (MK) {
+                const int gx = wrapx(x0 - 2 + lx, P.nx), gy = wrapx(y0 - 2 + ly, P.ny);
+                const unsigned lk = P.links[(unsigned)gy * P.pitch + gx];
+                L.lk[s] = (unsigned short)lk;
+                double ps = 0.0;  // solid node
+                if (!(lk & 1u)) {
+                    pull9_mask(P, gin, gx, gy, lk, fk[r]);
+                    rk[r] = sum9(fk[r]);
+                    ps = psi_of_rho<EOS>(P, rk[r]);
+                    ok[r] = true;
+                }
+                ps1[(ly + 1) * W3 + lx + 1] = ps;
+                continue;
+            }
+            double ps = 0.0;
+            int gy = y0 - 2 + ly;
+            bool fluid;
+            if (P.walls) fluid = gy >= 1 && gy <= P.ny - 2;
+            else { gy = wrapx(gy, P.ny); fluid = true; }
+            if (fluid) {
+                pull9<GEO>(P, gin, wrapx(x0 - 2 + lx, P.nx), gy, fk[r]);
+                rk[r] = sum9(fk[r]);
+                ps = psi_of_rho<EOS>(P, rk[r]);
+                ok[r] = true;
+            } else {
+                ps = psi_at<GEO, EOS>(P, gin, x0 - 2 + lx, y0 - 2 + ly);  // solid row: ghost or 0
+            }
+            ps1[(ly + 1) * W3 + lx + 1] = ps;
+        }
+        for (int h = tid - R0; h < NRING; h += NT) {
+            if (h < 0) continue;
+            int lx, ly;
+            ring_pos(h, lx, ly);
+            if constexpr (IN) {
+                double f[9];
+                pull9_in(P, gin, x0 - 3 + lx, y0 - 3 + ly, f);
+                ps1[ly * W3 + lx] = psi_of_rho<EOS>(P, sum9(f));
+            } else {
+                ps1[ly * W3 + lx] = psi_at<GEO, EOS>(P, gin, x0 - 3 + lx, y0 - 3 + ly);
+            }
         }
     }
     __syncthreads();

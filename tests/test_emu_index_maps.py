@@ -50,12 +50,15 @@ def test_index_maps_under_sanitizers(tmp_path):
 @pytest.mark.parametrize("old,new,case", [
     # the last slot of the outer psi ring of the two-step tile never written
     ("h < NRING; h += NT", "h < NRING - 1; h += NT", ("65", "13", "1", "1", "0", "2")),
+    # ... the same where a thread issues both of its pulls before either psi (64 x 8 on 512 threads)
+    ("} else if (h >= 0 && h < NRING) {", "} else if (h >= 0 && h < NRING - 1) {",
+     ("65", "13", "1", "1", "0", "2")),
     # the last slot of the psi ring around the output tile never written
     ("h < NRING1; h += NT", "h < NRING1 - 1; h += NT", ("130", "30", "0", "1", "0", "0")),
     # a diagonal population pulled from the wrong column
     ("f[6] = bot ? (g + 8 * pl)[r0 + ux] : (g + 6 * pl)[rm + xp];",
      "f[6] = bot ? (g + 8 * pl)[r0 + ux] : (g + 6 * pl)[rm + ux];", ("33", "10", "1", "1", "1", "1")),
-], ids=["psi_ring_R3", "psi_ring_R1", "pull_column"])
+], ids=["psi_ring_R3", "psi_ring_R3_fused", "psi_ring_R1", "pull_column"])
 def test_checker_catches_planted_index_mistakes(tmp_path, old, new, case):
     src = open(HEADER).read()
     assert src.count(old) == 1, old
